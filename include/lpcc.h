@@ -1,0 +1,149 @@
+/*
+ * lpcc.h - C ABI of the gfx950 (MI355X) implementation of the integer-only
+ * octree context model and range coder of "Towards Practical Lossless Neural
+ * Compression for LiDAR Point Clouds" (arXiv 2603.25260).
+ *
+ * What the library computes
+ *   A point cloud of int32 voxel coordinates in [0, 2^D)^3 is turned into an
+ *   octree (Sec. S3.2: Morton sort, halve and de-duplicate, 8-bit occupancy
+ *   codes).  Depth by depth, from the root, an integer-only network predicts
+ *   each node's distribution over the 255 non-empty occupancy codes
+ *   (Eq. 2-3): shallow depths propagate the previous depth's features through
+ *   a ResBlock and one upsample/prune step (Eq. 8-9); deep depths re-densify
+ *   the last coded level down to the dense depth k0 = D - n_deep - 1 and
+ *   upsample/prune back (GRED and XFP, Eq. 4-7 and 10-11).  Every layer uses
+ *   int8 weights and activations, int32 accumulation and multiply-shift
+ *   requantisation (Sec. 3.3, Eq. 12-14); the softmax uses an exponent table
+ *   on the non-positive domain and integer normalisation (Eq. 15).  The
+ *   resulting 16-bit CDF drives a byte-oriented range coder, in chunks of 2^c
+ *   nodes per depth.  Nothing is computed in floating point.
+ *
+ * Conventions
+ *   - All functions return an int status: LPCC_OK (0) or a negative code.
+ *   - Pointers to point data and streams may be host or device memory of the
+ *     context's device; the kind is detected per call.  The library copies
+ *     what it needs and keeps no caller pointer after a call returns.
+ *   - Coordinates: int32 [n][3] (x, y, z).  Duplicates are allowed and removed.
+ *     n = 0 is a valid (empty) frame.
+ *   - Decoded coordinates are the unique voxels in Morton order (x is the most
+ *     significant bit of every bit triple).
+ *   - A context is used by one host thread at a time; a model may be shared by
+ *     several contexts of the same device.
+ *   - Calls are synchronous: outputs are complete when the call returns.
+ *
+ * Bitstream (little-endian): u32 "LPC1", u8 version (1), u8 D, u8 n_deep,
+ *   u8 c (log2 of the chunk size), u32 blob id (FNV-1a of the weight blob),
+ *   u32 N_D, u32 N_d for d = 0..D-1, u16 payload length of every chunk
+ *   (depth ascending, chunk ascending), then the payloads.  Chunk k of depth d
+ *   codes nodes [k 2^c, min((k+1) 2^c, N_d)) of that depth.
+ */
+#ifndef LPCC_H
+#define LPCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LPCC_OK 0
+#define LPCC_E_INVAL (-1)    /* null pointer, coordinate outside [0,2^D), bad level / chunk size */
+#define LPCC_E_CAPACITY (-2) /* output too small; the required size is written back            */
+#define LPCC_E_CORRUPT (-3)  /* malformed or inconsistent bitstream                             */
+#define LPCC_E_MODEL (-4)    /* malformed weight blob, or stream made with another model       */
+#define LPCC_E_DEVICE (-5)   /* HIP runtime error; text via lpcc_last_error                     */
+#define LPCC_E_NOMEM (-6)    /* device memory allocation failed                                 */
+
+typedef struct lpcc_model lpcc_model; /* weights resident on one device, read-only  */
+typedef struct lpcc_ctx lpcc_ctx;     /* device, stream, workspace of one caller     */
+
+/*
+ * Weight blob -> device model (the per-depth layers of Sec. S2; parameters are
+ * not shared between depths).  The blob is parsed, validated (layer order,
+ * shapes, |bias| < 2^24, 0 <= m < 2^31, 0 <= r <= 62, zero points in int8) and
+ * copied to `device`; the caller keeps ownership of `blob`.
+ * Errors: LPCC_E_INVAL (null), LPCC_E_MODEL (bad blob), LPCC_E_DEVICE / NOMEM.
+ */
+int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out);
+void lpcc_model_free(lpcc_model* m);
+/* Channel width C, octree depth D, number of deep (re-densified) depths, blob id. */
+int lpcc_model_info(const lpcc_model* m, int* C, int* D, int* n_deep, uint32_t* blob_id);
+
+/*
+ * Context on `device`.  `hip_stream` (a hipStream_t, may be NULL for the null
+ * stream) is where all work of the context is enqueued; the context does not
+ * own it.  Device workspace grows on demand and is reused between calls.
+ */
+int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out);
+void lpcc_ctx_free(lpcc_ctx* c);
+/* Text of the last error of this context (valid until the next call). */
+const char* lpcc_last_error(const lpcc_ctx* c);
+
+/*
+ * Encode one frame (octree construction, per-depth model, range coding).
+ *   xyz        int32 [n][3], host or device
+ *   chunk_log2 c in [4, 14]: nodes per range-coder chunk = 2^c
+ *   out        bitstream buffer (host or device) of `cap` bytes
+ *   out_len    bytes written, or the required size on LPCC_E_CAPACITY
+ * Errors: LPCC_E_INVAL (bad coordinate / argument), LPCC_E_CAPACITY.
+ */
+int lpcc_encode_frame(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int chunk_log2,
+                      uint8_t* out, size_t cap, size_t* out_len);
+
+/*
+ * Decode one frame, depth by depth (the decoder sees only coded depths).
+ *   bs, len    bitstream, host or device
+ *   xyz_out    int32 [cap][3] (host or device): unique voxels in Morton order
+ *   n_out      number of voxels, also returned with LPCC_E_CAPACITY
+ * Errors: LPCC_E_CORRUPT (bad header, counts, lengths, or coder state),
+ *         LPCC_E_MODEL (stream made with another model), LPCC_E_CAPACITY.
+ */
+int lpcc_decode_frame(lpcc_ctx* c, const lpcc_model* m, const uint8_t* bs, size_t len, int32_t* xyz_out,
+                      int64_t cap, int64_t* n_out);
+
+/*
+ * CDF rows of one depth: the encoder's model output for `level` (0..D-1),
+ * int32 [N_level][256] with cdf[0] = 0, cdf[255] = 65536 and
+ * cdf[s+1] - cdf[s] >= 1 the frequency of occupancy code s + 1.
+ *   cdf_out    host or device; n_nodes = N_level (also with LPCC_E_CAPACITY)
+ */
+int lpcc_level_probs(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int level,
+                     int32_t* cdf_out, int64_t cap, int64_t* n_nodes);
+
+/* Depth and point count from the first 16 bytes of a stream (host memory only). */
+int lpcc_peek_header(const uint8_t* bs, size_t len, int* D, int64_t* n_points);
+
+/*
+ * Batched forms: `nf` frames of one model share every launch of a depth
+ * (one launch per depth and layer over the rows of all frames).  Results are
+ * identical, byte for byte, to the per-frame calls.  Per-frame status codes
+ * go to status[nf]; the return value is LPCC_OK if every frame succeeded,
+ * otherwise the first failing frame's code.  Pointers follow the per-frame
+ * rules; every xyz[i] / out[i] / bs[i] / xyz_out[i] is a separate buffer.
+ */
+int lpcc_encode_batch(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n,
+                      int chunk_log2, uint8_t* const* out, const size_t* cap, size_t* out_len, int* status);
+int lpcc_decode_batch(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* bs, const size_t* len,
+                      int32_t* const* xyz_out, const int64_t* cap, int64_t* n_out, int* status);
+
+/*
+ * Kernel timing: when enabled, the context records HIP events around every
+ * launch of the kernel family named `name` ("predict", "conv", "up", ...) on
+ * its stream and accumulates their durations.  lpcc_timing_read returns the
+ * number of launches and the summed milliseconds since the last reset.
+ */
+int lpcc_timing_enable(lpcc_ctx* c, const char* name);
+int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* units);
+
+/*
+ * The integer exponent table of the softmax (Eq. 15) as the library builds
+ * it: out[i] = round(2^15 e^{-i/16}), i = 0..255, computed on the host with
+ * an integer recurrence.  Host memory; needs no device.
+ */
+int lpcc_softmax_table(int32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPCC_H */

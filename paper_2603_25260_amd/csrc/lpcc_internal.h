@@ -1,0 +1,152 @@
+// Internal declarations of the gfx950 library: device descriptors shared by
+// the kernels and the host runtime.  Integer arithmetic only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lpcc.h"
+
+namespace lpcc {
+
+constexpr int kMaxD = 21;
+constexpr int kNSym = 255;
+constexpr int kTaps3 = 27;
+
+enum LayerKind { K_EMB = 1, K_DOWN, K_CONV1, K_CONV2, K_SKIP, K_UP, K_FC1, K_FC2 };
+
+// One layer as the kernels see it.  Weights are packed for the B operand of
+// v_mfma_i32_16x16x64_i8: for k-step s (64 input rows k) and column block nb
+// (16 outputs) lane l holds 16 bytes W[64 s + 16 (l/16) + i][16 nb + l%16],
+// i = 0..15, zero-padded beyond K = taps*cin and cout.
+struct LayerDev {
+  const int8_t* Wp;     // packed weights, Kpad x Npad bytes
+  const int8_t* Wr;     // row-major W[taps][cin][cout] (VALU paths)
+  const int32_t* bias;  // [Npad]; dense layers carry -z_in * colsum folded in
+  const int32_t* zc;    // [taps][Npad] = -z_in * sum_c W[t][c][o] for sparse layers, or null
+  int32_t m_pos, m_neg;
+  int32_t r, z_out;
+  int32_t taps, cin, cout;
+  int32_t ksteps;       // Kpad / 64
+  int32_t npad;
+  int32_t pad_;
+};
+
+// Requantisation of an int32 accumulator (Eq. 14): sign-selected multiplier,
+// 64-bit product, round half up, arithmetic shift, zero point, clamp to int8.
+__device__ __forceinline__ int requant(int acc, int m_pos, int m_neg, int r, int z_out) {
+  long long m = acc >= 0 ? m_pos : m_neg;
+  long long p = (long long)acc * m;
+  if (r > 0) p = (p + (1ll << (r - 1))) >> r;
+  p += z_out;
+  return p < -128 ? -128 : (p > 127 ? 127 : (int)p);
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4i mfma16(v4i a, v4i b, v4i c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Row-range work items.  A launch covers a list of segments; every block
+// works on one tile (segment, first row) of the flattened tile list.
+// ---------------------------------------------------------------------------
+struct Tile {
+  int32_t seg;
+  int32_t row0;
+};
+
+// Gather-GEMM segment: out[row] = epilogue(sum over taps of in[src(row,t)] W[t])
+struct GemmSeg {
+  const int8_t* in;        // input rows
+  int64_t in_stride;       // bytes between input rows
+  const int32_t* kmap;     // conv: [27][kstride] source rows (-1 = empty)
+  int64_t kstride;
+  const uint8_t* code;     // down/up: occupancy codes of the parents
+  const int32_t* cstart;   // down/up: first child row of each parent
+  const LayerDev* L;
+  int8_t* out;
+  int64_t out_stride;
+  const int8_t* resid;     // optional residual added after requantisation
+  int64_t resid_stride;
+  int32_t rows;
+  int32_t child_rows;      // rows of the child depth (bounds of cstart-derived indices)
+};
+
+// Predictor segment (fc1 -> fc2 -> integer softmax -> frequencies)
+struct PredSeg {
+  const int8_t* F;         // [rows][C]
+  const uint8_t* code;     // encode: true codes (symbol = code - 1)
+  const LayerDev* fc1;
+  const LayerDev* fc2;
+  uint32_t* sf;            // encode: start | freq << 16 per node
+  uint16_t* cdf16;         // decode: cdf[0..254] per node (256 slots)
+  int32_t* cdf32;          // level_probs: cdf[0..255] per node
+  int32_t rows;
+  int32_t pad_;
+};
+
+// Range-coder chunk: nodes [begin, begin+count) of one (frame, depth)
+struct Chunk {
+  int64_t node0;           // index into the per-call node arrays
+  int32_t count;
+  int32_t pad_;
+  int64_t scratch;         // byte offset of this chunk's scratch / payload
+};
+
+// Device-side error bits
+enum : uint32_t { ERR_COORD = 1u, ERR_CORRUPT = 2u, ERR_COUNT = 4u, ERR_ACC = 8u };
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_morton(const int32_t* xyz, int64_t n, int D, uint64_t frame_tag, uint64_t* keys,
+                         uint32_t* err, hipStream_t s);
+// Octree build over sorted keys (frame id in bits >= 3D).
+hipError_t launch_level_hist(const uint64_t* keys, int64_t n, int D, int tile, uint32_t* hist,
+                             hipStream_t s);
+hipError_t launch_level_scan(uint32_t* hist, int nblocks, int D, uint32_t* totals, hipStream_t s);
+struct LevelOut {
+  uint64_t* key[kMaxD + 1];
+  uint8_t* code[kMaxD + 1];
+  int32_t* cstart[kMaxD + 1];
+  uint32_t* frame_off;  // [frames][D+1]: first node of every frame per depth
+};
+hipError_t launch_level_write(const uint64_t* keys, int64_t n, int D, int tile, const uint32_t* hist,
+                              const LevelOut& lo, hipStream_t s);
+hipError_t launch_sentinels(const LevelOut& lo, const uint32_t* totals, int D, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+
+hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
+                              uint64_t mask, hipStream_t s);
+hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* tkeys, const int32_t* tvals,
+                       uint64_t mask, int32_t* kmap, int64_t kstride, hipStream_t s);
+
+// GEMM families; `mode` selects the row source
+enum GemmMode { G_CONV = 0, G_DENSE = 1, G_DOWN = 2 };
+hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs_dev, const Tile* tiles_dev,
+                       int ntiles, hipStream_t s);
+hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, hipStream_t s);
+hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, hipStream_t s);
+hipError_t launch_copy_rows(const int8_t* src, int64_t src_stride, int8_t* dst, int64_t dst_stride,
+                            int64_t rows, int width, hipStream_t s);
+hipError_t launch_predict(int C, int mode, const PredSeg* segs_dev, const Tile* tiles_dev, int ntiles,
+                          const int32_t* lut, hipStream_t s);
+
+hipError_t launch_rc_encode(const Chunk* chunks, int nchunks, const uint32_t* sf, uint8_t* scratch,
+                            uint32_t* lens, hipStream_t s);
+hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scratch, const uint32_t* lens,
+                          uint8_t* const* dst, hipStream_t s);
+hipError_t launch_rc_decode_sized(const Chunk* chunks, int nchunks, const uint8_t* payload, const uint16_t* cdf16,
+                                  uint8_t* codes, uint32_t* err, size_t max_len, hipStream_t s);
+hipError_t launch_expand(const uint64_t* pkeys, const uint8_t* codes, int64_t n, uint64_t* ckeys,
+                         int32_t* cstart, int64_t n_child_expected, uint32_t* scan_tmp, uint32_t* err,
+                         hipStream_t s);
+hipError_t launch_keys_to_xyz(const uint64_t* keys, int64_t n, int D, int32_t* xyz, hipStream_t s);
+
+}  // namespace lpcc

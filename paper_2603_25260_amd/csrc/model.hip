@@ -1,0 +1,480 @@
+// Integer-only network layers on gfx950 int8 MFMA (Sec. 3.3, Eq. 13-14):
+//   * gather-GEMM for the 3x3x3 submanifold convolutions (indexed linear
+//     transforms over a kernel map), the stride-2 child convolution of the
+//     re-densification (Eq. 4) and dense linear layers;
+//   * upsampling + pruning (Eq. 6/9/11): Linear(C+8 -> 8C) + PReLU per parent,
+//     only occupied child slots are written, in Morton order;
+//   * the occupancy embedding;
+//   * the predictor (Eq. 7) fused with the integer softmax (Eq. 15) and the
+//     16-bit frequency table that drives the range coder.
+// One wave computes a 16-row tile with v_mfma_i32_16x16x64_i8; int32
+// accumulation is exact, so any summation order gives the same result.
+#include "lpcc_internal.h"
+
+namespace lpcc {
+
+// Lane layout of v_mfma_i32_16x16x64_i8 used throughout: A lane l holds row
+// l%16, 16 consecutive k of group l/16; B lane l holds column l%16, the same
+// k; the accumulator lane l holds rows 4(l/16)+i (i = 0..3) of column l%16.
+
+__device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
+
+// Epilogue: one wave's 16 x COUT int32 tile staged in LDS, then every lane
+// handles a contiguous run of COUT/4 columns of one row.
+template <int COUT>
+struct Stage {
+  int32_t v[16][COUT];
+};
+
+// ---------------------------------------------------------------------------
+// Gather-GEMM: out[row][o] = rq(bias[o] + sum_t sum_c in[src(row,t)][c] W[t][c][o]
+//                               + sum over present taps of zc[t][o]) (+ resid)
+// MODE G_CONV : src(row,t) = kmap[t][row]            (27 taps)
+// MODE G_DENSE: src(row,0) = row                      (1 tap)
+// MODE G_DOWN : src(row,o) = child in slot o of parent row, if occupied (8 taps)
+// ---------------------------------------------------------------------------
+template <int MODE>
+struct Taps;
+template <>
+struct Taps<G_CONV> { static constexpr int n = 27; };
+template <>
+struct Taps<G_DENSE> { static constexpr int n = 1; };
+template <>
+struct Taps<G_DOWN> { static constexpr int n = 8; };
+
+template <int MODE>
+__device__ __forceinline__ int src_row(const GemmSeg& S, int row, int tap) {
+  if (MODE == G_CONV) return S.kmap[(int64_t)tap * S.kstride + row];
+  if (MODE == G_DENSE) return row;
+  uint32_t code = S.code[row];
+  if (!((code >> tap) & 1u)) return -1;
+  const int cr = S.cstart[row] + __popc(code & ((1u << tap) - 1u));
+  return cr < S.child_rows ? cr : -1;  // out of range only for a corrupt stream
+}
+
+template <int MODE, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles) {
+  constexpr int TAPS = Taps<MODE>::n;
+  constexpr int K = TAPS * CIN;
+  constexpr int KS = (K + 63) / 64;
+  constexpr int NB = COUT / 16;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "widths must be multiples of 16");
+  __shared__ Stage<COUT> st[4];
+
+  const Tile tl = tiles[blockIdx.x];
+  const GemmSeg S = segs[tl.seg];
+  const LayerDev L = *S.L;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int row0 = tl.row0 + wave * 16;
+  const int row = row0 + r;
+  const bool rv = row < S.rows;
+
+  v4i acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; nb++) acc[nb] = v4i{0, 0, 0, 0};
+
+  // source row of every k-step for this lane (taps beyond TAPS are padding)
+  int src[KS];
+#pragma unroll
+  for (int s = 0; s < KS; s++) {
+    const int k0 = 64 * s + 16 * g;
+    const int tap = k0 / CIN;
+    src[s] = (rv && tap < TAPS) ? src_row<MODE>(S, row, tap) : -1;
+  }
+  const v4i* Wp = (const v4i*)L.Wp;
+#pragma unroll
+  for (int s = 0; s < KS; s++) {
+    const int k0 = 64 * s + 16 * g;
+    const int c0 = k0 % CIN;
+    v4i a = v4i{0, 0, 0, 0};
+    if (src[s] >= 0) a = ld16(S.in + (int64_t)src[s] * S.in_stride + c0);
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+      v4i b = Wp[((int64_t)s * NB + nb) * 64 + lane];
+      acc[nb] = mfma16(a, b, acc[nb]);
+    }
+  }
+
+  // stage the tile, then requantise row-contiguous runs
+#pragma unroll
+  for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) st[wave].v[4 * g + i][16 * nb + r] = acc[nb][i];
+  __syncthreads();
+  constexpr int PER = COUT / 4;
+  const int er = lane >> 2;           // epilogue row within the tile
+  const int ec = (lane & 3) * PER;    // first column
+  const int orow = row0 + er;
+  if (orow < S.rows) {
+    int zsum[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) zsum[q] = 0;
+    if (L.zc != nullptr) {
+      for (int t = 0; t < TAPS; t++) {
+        if (src_row<MODE>(S, orow, t) < 0) continue;
+#pragma unroll
+        for (int q = 0; q < PER; q++) zsum[q] += L.zc[t * L.npad + ec + q];
+      }
+    }
+    int8_t res[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) res[q] = 0;
+    if (S.resid != nullptr) {
+#pragma unroll
+      for (int q = 0; q < PER; q++) res[q] = S.resid[(int64_t)orow * S.resid_stride + ec + q];
+    }
+    int8_t outv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      int a = st[wave].v[er][ec + q] + L.bias[ec + q] + zsum[q];
+      int y = requant(a, L.m_pos, L.m_neg, L.r, L.z_out);
+      if (S.resid != nullptr) {
+        y += res[q];
+        y = y < -128 ? -128 : (y > 127 ? 127 : y);
+      }
+      outv[q] = (int8_t)y;
+    }
+    int8_t* dst = S.out + (int64_t)orow * S.out_stride + ec;
+#pragma unroll
+    for (int q = 0; q < PER; q++) dst[q] = outv[q];
+  }
+}
+
+template <int MODE>
+static hipError_t launch_gemm_mode(int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
+                                   hipStream_t s) {
+#define LPCC_G(CI, CO)                                                                          \
+  if (cin == CI && cout == CO) {                                                                \
+    hipLaunchKernelGGL((k_gemm<MODE, CI, CO>), dim3(ntiles), dim3(256), 0, s, segs, tiles);     \
+    return hipGetLastError();                                                                   \
+  }
+  LPCC_G(16, 16) LPCC_G(32, 16) LPCC_G(32, 32) LPCC_G(64, 32) LPCC_G(64, 64) LPCC_G(128, 64)
+#undef LPCC_G
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
+                       hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (mode == G_CONV) return launch_gemm_mode<G_CONV>(cin, cout, segs, tiles, ntiles, s);
+  if (mode == G_DENSE) return launch_gemm_mode<G_DENSE>(cin, cout, segs, tiles, ntiles, s);
+  if (mode == G_DOWN) return launch_gemm_mode<G_DOWN>(cin, cout, segs, tiles, ntiles, s);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Upsampling + pruning: per parent p, A = [Z[p] (C) | bits(X[p]) (8)],
+// out block o (columns oC..oC+C-1) is child slot o; occupied slots only,
+// child row = cstart[p] + rank of o among the set bits.
+// ---------------------------------------------------------------------------
+template <int C>
+__global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles) {
+  constexpr int KS = (C + 8 + 63) / 64;
+  constexpr int NBS = C / 16;          // column blocks per child slot
+  constexpr int NBT = 8 * NBS;         // column blocks of the layer
+
+  const Tile tl = tiles[blockIdx.x];
+  const GemmSeg S = segs[tl.seg];
+  const LayerDev L = *S.L;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int row0 = tl.row0 + wave * 16;
+  const int row = row0 + r;
+  const bool rv = row < S.rows;
+  const uint32_t code = rv ? S.code[row] : 0u;
+
+  v4i a[KS];
+#pragma unroll
+  for (int s = 0; s < KS; s++) {
+    const int k0 = 64 * s + 16 * g;
+    a[s] = v4i{0, 0, 0, 0};
+    if (rv && k0 < C) {
+      a[s] = ld16(S.in + (int64_t)row * S.in_stride + k0);
+    } else if (rv && k0 == C) {  // occupancy bits as int8 {0,127}, then zeros
+      uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        if ((code >> b) & 1u) w0 |= 127u << (8 * b);
+        if ((code >> (b + 4)) & 1u) w1 |= 127u << (8 * b);
+      }
+      a[s] = v4i{(int)w0, (int)w1, 0, 0};
+    }
+  }
+  // the parents whose outputs this lane holds: rows 4g+i of the tile
+  uint32_t pcode[4];
+  int pcs[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int p = row0 + 4 * g + i;
+    pcode[i] = p < S.rows ? S.code[p] : 0u;
+    pcs[i] = p < S.rows ? S.cstart[p] : 0;
+  }
+  const v4i* Wp = (const v4i*)L.Wp;
+
+  for (int o = 0; o < 8; o++) {
+    // skip a slot that no parent of this wave's tile occupies (wave-uniform)
+    if (__ballot((code >> o) & 1u) == 0ull) continue;
+    v4i acc[NBS];
+#pragma unroll
+    for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; s++)
+#pragma unroll
+      for (int nb = 0; nb < NBS; nb++) {
+        v4i b = Wp[((int64_t)s * NBT + o * NBS + nb) * 64 + lane];
+        acc[nb] = mfma16(a[s], b, acc[nb]);
+      }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      if (!((pcode[i] >> o) & 1u)) continue;
+      const int crow = pcs[i] + __popc(pcode[i] & ((1u << o) - 1u));
+      if (crow >= S.child_rows) continue;  // only for a corrupt stream
+      int8_t* dst = S.out + (int64_t)crow * S.out_stride;
+#pragma unroll
+      for (int nb = 0; nb < NBS; nb++) {
+        const int col = 16 * nb + r;
+        dst[col] = (int8_t)requant(acc[nb][i] + L.bias[o * C + col], L.m_pos, L.m_neg, L.r, L.z_out);
+      }
+    }
+  }
+}
+
+hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (C == 16) hipLaunchKernelGGL((k_up<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles);
+  else if (C == 32) hipLaunchKernelGGL((k_up<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles);
+  else if (C == 64) hipLaunchKernelGGL((k_up<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Occupancy embedding (first step of the re-densification, Eq. 4): 8 int8
+// channels {0,127} from the code bits, Linear(8 -> C), ReLU requantisation.
+// One thread per output element.  Tiles cover 64 rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                             int C) {
+  const Tile tl = tiles[blockIdx.x];
+  const GemmSeg S = segs[tl.seg];
+  const LayerDev L = *S.L;
+  for (int e = threadIdx.x; e < 64 * C; e += blockDim.x) {
+    const int row = tl.row0 + e / C, o = e % C;
+    if (row >= S.rows) continue;
+    const uint32_t code = S.code[row];
+    int acc = L.bias[o];
+    for (int b = 0; b < 8; b++)
+      if ((code >> b) & 1u) acc += 127 * (int)L.Wr[b * C + o];
+    S.out[(int64_t)row * S.out_stride + o] = (int8_t)requant(acc, L.m_pos, L.m_neg, L.r, L.z_out);
+  }
+}
+
+hipError_t launch_emb(const GemmSeg* segs, const Tile* tiles, int ntiles, int C, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_emb, dim3(ntiles), dim3(256), 0, s, segs, tiles, C);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_rows(const int8_t* __restrict__ src, int64_t ss, int8_t* __restrict__ dst, int64_t ds,
+                            int64_t rows, int width) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t words = width / 4;
+  if (e >= rows * words) return;
+  int64_t row = e / words, w = e % words;
+  *(int32_t*)(dst + row * ds + 4 * w) = *(const int32_t*)(src + row * ss + 4 * w);
+}
+
+hipError_t launch_copy_rows(const int8_t* src, int64_t src_stride, int8_t* dst, int64_t dst_stride, int64_t rows,
+                            int width, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  int64_t tot = rows * (width / 4);
+  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, src_stride, dst,
+                     dst_stride, rows, width);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Predictor + integer softmax + frequency table.
+//   h = relu-rq(F W1 + b1)            (C -> C)
+//   l = rq(h W2 + b2)                 (C -> 255 int8 logits)
+//   M = max l, E_i = LUT[M - l_i], S = sum E_i
+//   f_i = 1 + floor(E_i * 65281 / S), the remainder 65536 - sum f goes to the
+//   lowest index holding M;  cdf[s] = sum_{i<s} f_i.
+// Division: floor(n / S) = q or q+1 with q = mulhi(n, floor(2^32 / S)); the
+// reciprocal comes from a shift-subtract long division.  Integer-only.
+// A wave handles 16 nodes; lane l owns rows 4(l/16)+i and columns 16b + l%16.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t recip32(uint32_t S) {  // floor(2^32 / S), 2^15 <= S < 2^23
+  uint64_t rem = 1ull << 32;
+  uint32_t q = 0;
+#pragma unroll
+  for (int b = 17; b >= 0; b--) {
+    uint64_t t = (uint64_t)S << b;
+    if (rem >= t) { rem -= t; q |= 1u << b; }
+  }
+  return q;
+}
+
+__device__ __forceinline__ uint32_t divS(uint32_t n, uint32_t S, uint32_t inv) {
+  uint32_t q = __umulhi(n, inv);
+  uint32_t rem = n - q * S;
+  return rem >= S ? q + 1 : q;
+}
+
+// reductions over the 16 lanes sharing l/16
+__device__ __forceinline__ int red16_max(int v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int red16_min(int v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int red16_sum(int v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+enum { P_ENCODE = 0, P_CDF16 = 1, P_CDF32 = 2 };
+
+template <int C, int MODE>
+__global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                                 const int32_t* __restrict__ lut_g) {
+  __shared__ int32_t lut[256];
+  __shared__ int8_t hs[4][16][64];
+  lut[threadIdx.x] = lut_g[threadIdx.x];
+
+  const Tile tl = tiles[blockIdx.x];
+  const PredSeg S = segs[tl.seg];
+  const LayerDev L1 = *S.fc1;
+  const LayerDev L2 = *S.fc2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int row0 = tl.row0 + wave * 16;
+  const int row = row0 + r;
+  const bool rv = row < S.rows;
+
+  // fc1: K = C (padded to 64)
+  constexpr int NB1 = C / 16;
+  v4i a = v4i{0, 0, 0, 0};
+  if (rv && 16 * g < C) a = ld16(S.F + (int64_t)row * C + 16 * g);
+  v4i acc1[NB1];
+  const v4i* W1 = (const v4i*)L1.Wp;
+#pragma unroll
+  for (int nb = 0; nb < NB1; nb++) acc1[nb] = mfma16(a, W1[nb * 64 + lane], v4i{0, 0, 0, 0});
+  // requantise straight from the accumulator layout into the A layout of fc2
+#pragma unroll
+  for (int nb = 0; nb < NB1; nb++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int col = 16 * nb + r;
+      hs[wave][4 * g + i][col] = (int8_t)requant(acc1[nb][i] + L1.bias[col], L1.m_pos, L1.m_neg, L1.r, L1.z_out);
+    }
+  if (C < 64) {  // zero the K padding (columns C..63 of the 16 rows)
+    for (int k = lane; k < 16 * (64 - C); k += 64) hs[wave][k / (64 - C)][C + k % (64 - C)] = 0;
+  }
+  __syncthreads();
+  v4i h = *(const v4i*)&hs[wave][r][16 * g];
+
+  // fc2: 16 column blocks of 16 logits
+  const v4i* W2 = (const v4i*)L2.Wp;
+  int lg[4][16];
+#pragma unroll
+  for (int b = 0; b < 16; b++) {
+    v4i acc = mfma16(h, W2[b * 64 + lane], v4i{0, 0, 0, 0});
+    const int col = 16 * b + r;
+    const int bias = L2.bias[col];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+      lg[i][b] = col < kNSym ? requant(acc[i] + bias, L2.m_pos, L2.m_neg, L2.r, L2.z_out) : -1000;
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int nrow = row0 + 4 * g + i;
+    int M = -1000;
+#pragma unroll
+    for (int b = 0; b < 16; b++) M = max(M, lg[i][b]);
+    M = red16_max(M);
+    int arg = 1000;
+#pragma unroll
+    for (int b = 0; b < 16; b++)
+      if (lg[i][b] == M) arg = min(arg, 16 * b + r);
+    arg = red16_min(arg);
+    int E[16];
+    int Ssum = 0;
+#pragma unroll
+    for (int b = 0; b < 16; b++) {
+      E[b] = (16 * b + r < kNSym) ? lut[M - lg[i][b]] : 0;
+      Ssum += E[b];
+    }
+    const uint32_t S_ = (uint32_t)red16_sum(Ssum);
+    const uint32_t inv = recip32(S_);
+    int f[16];
+    int fsum = 0;
+#pragma unroll
+    for (int b = 0; b < 16; b++) {
+      f[b] = (16 * b + r < kNSym) ? 1 + (int)divS((uint32_t)E[b] * 65281u, S_, inv) : 0;
+      fsum += f[b];
+    }
+    const int R = 65536 - red16_sum(fsum);
+#pragma unroll
+    for (int b = 0; b < 16; b++)
+      if (16 * b + r == arg) f[b] += R;
+
+    if (MODE == P_ENCODE) {
+      const int sym = nrow < S.rows ? (int)S.code[nrow] - 1 : 0;
+      int st_ = 0, fr = 0;
+#pragma unroll
+      for (int b = 0; b < 16; b++) {
+        const int col = 16 * b + r;
+        st_ += col < sym ? f[b] : 0;
+        fr += col == sym ? f[b] : 0;
+      }
+      st_ = red16_sum(st_);
+      fr = red16_sum(fr);
+      if (r == 0 && nrow < S.rows) S.sf[nrow] = (uint32_t)st_ | ((uint32_t)fr << 16);
+    } else {
+      // exclusive prefix over columns 16b + r: scan across the 16 lanes per block b
+      int base = 0;
+#pragma unroll
+      for (int b = 0; b < 16; b++) {
+        int inc = f[b];
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          int v = __shfl_up(inc, o, 16);
+          if (r >= o) inc += v;
+        }
+        const int tot = __shfl(inc, 15, 16);
+        const int cdf = base + inc - f[b];
+        base += tot;
+        if (nrow < S.rows) {
+          const int col = 16 * b + r;
+          if (MODE == P_CDF16) S.cdf16[(int64_t)nrow * 256 + col] = (uint16_t)(col < kNSym ? cdf : 0);
+          else S.cdf32[(int64_t)nrow * 256 + col] = col < kNSym ? cdf : 65536;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_predict(int C, int mode, const PredSeg* segs, const Tile* tiles, int ntiles, const int32_t* lut,
+                          hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+#define LPCC_P(CC, MM)                                                                            \
+  if (C == CC && mode == MM) {                                                                    \
+    hipLaunchKernelGGL((k_predict<CC, MM>), dim3(ntiles), dim3(256), 0, s, segs, tiles, lut);     \
+    return hipGetLastError();                                                                     \
+  }
+  LPCC_P(16, 0) LPCC_P(16, 1) LPCC_P(16, 2)
+  LPCC_P(32, 0) LPCC_P(32, 1) LPCC_P(32, 2)
+  LPCC_P(64, 0) LPCC_P(64, 1) LPCC_P(64, 2)
+#undef LPCC_P
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lpcc

@@ -1,0 +1,410 @@
+// Octree construction, coordinate hash, 3x3x3 neighbourhoods and child
+// expansion on gfx950 (Sec. S3.2 of the paper; neighbourhoods for the sparse
+// convolutions of Sec. 3.3).  Integer-only; wave64 ballots and prefix counts.
+#include "lpcc_internal.h"
+
+namespace lpcc {
+
+// ---------------------------------------------------------------------------
+// Morton keys: bit 3b+2 = x_b, 3b+1 = y_b, 3b = z_b, and a frame tag above
+// the 3D coordinate bits so that several frames sort into one array.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+  x = (x ^ (x >> 32)) & 0x1fffffull;
+  return (uint32_t)x;
+}
+
+__global__ void k_morton(const int32_t* __restrict__ xyz, int64_t n, int D, uint64_t tag,
+                         uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+  uint32_t side = 1u << D;
+  if (x < 0 || y < 0 || z < 0 || (uint32_t)x >= side || (uint32_t)y >= side || (uint32_t)z >= side) {
+    atomicOr(err, ERR_COORD);
+    x = y = z = 0;
+  }
+  keys[i] = tag | (spread3((uint32_t)x) << 2) | (spread3((uint32_t)y) << 1) | spread3((uint32_t)z);
+}
+
+hipError_t launch_morton(const int32_t* xyz, int64_t n, int D, uint64_t frame_tag, uint64_t* keys,
+                         uint32_t* err, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_morton, dim3((unsigned)blocks), dim3(256), 0, s, xyz, n, D, frame_tag, keys, err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Level build over sorted keys.  For element i let d*(i) be the shallowest
+// depth at which it starts a new node: 0 at a frame start (the tags differ),
+// D+1 for a duplicate, else D - floor(b/3) with b the highest bit in which it
+// differs from its predecessor.  Element i is the first element of a depth-d
+// node iff d*(i) <= d, so node indices are prefix counts of (d* <= d).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dstar(const uint64_t* keys, int64_t i, int D) {
+  if (i == 0) return 0;
+  uint64_t x = keys[i] ^ keys[i - 1];
+  if (x == 0) return D + 1;
+  int b = 63 - __clzll((long long)x);
+  int d = D - b / 3;
+  return d < 0 ? 0 : d;
+}
+
+constexpr int kLevelThreads = 256;
+
+// hist[tile][v] = #elements of the tile with d* = v (v = 0..D)
+__global__ void k_level_hist(const uint64_t* __restrict__ keys, int64_t n, int D, int tile,
+                             uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kMaxD + 2];
+  for (int v = threadIdx.x; v <= D + 1; v += blockDim.x) h[v] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * tile;
+  for (int k = threadIdx.x; k < tile; k += blockDim.x) {
+    int64_t i = base + k;
+    if (i < n) atomicAdd(&h[dstar(keys, i, D)], 1u);
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v <= D; v += blockDim.x) hist[(int64_t)blockIdx.x * (D + 1) + v] = h[v];
+}
+
+hipError_t launch_level_hist(const uint64_t* keys, int64_t n, int D, int tile, uint32_t* hist, hipStream_t s) {
+  int64_t nb = (n + tile - 1) / tile;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_hist, dim3((unsigned)nb), dim3(kLevelThreads), 0, s, keys, n, D, tile, hist);
+  return hipGetLastError();
+}
+
+// In place: hist[t][d] <- #elements of tiles < t with d* <= d (exclusive over
+// tiles, cumulative over depth).  totals[d] = N_d.  One block.
+__global__ void k_level_scan(uint32_t* __restrict__ hist, int nb, int D, uint32_t* __restrict__ totals) {
+  __shared__ uint32_t part[kLevelThreads][kMaxD + 1];
+  int tid = threadIdx.x;
+  int per = (nb + blockDim.x - 1) / blockDim.x;
+  int t0 = tid * per, t1 = min(nb, t0 + per);
+  uint32_t run[kMaxD + 1];
+  for (int d = 0; d <= D; d++) run[d] = 0;
+  for (int t = t0; t < t1; t++) {
+    uint32_t c = 0;
+    for (int d = 0; d <= D; d++) { c += hist[(int64_t)t * (D + 1) + d]; run[d] += c; }
+  }
+  for (int d = 0; d <= D; d++) part[tid][d] = run[d];
+  __syncthreads();
+  if (tid <= D) {  // serial exclusive scan over threads, one depth per thread
+    uint32_t acc = 0;
+    for (int k = 0; k < (int)blockDim.x; k++) { uint32_t v = part[k][tid]; part[k][tid] = acc; acc += v; }
+    totals[tid] = acc;
+  }
+  __syncthreads();
+  for (int d = 0; d <= D; d++) run[d] = part[tid][d];
+  for (int t = t0; t < t1; t++) {
+    uint32_t c = 0, inc[kMaxD + 1];
+    for (int d = 0; d <= D; d++) { c += hist[(int64_t)t * (D + 1) + d]; inc[d] = c; }
+    for (int d = 0; d <= D; d++) { hist[(int64_t)t * (D + 1) + d] = run[d]; run[d] += inc[d]; }
+  }
+}
+
+hipError_t launch_level_scan(uint32_t* hist, int nb, int D, uint32_t* totals, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(kLevelThreads), 0, s, hist, nb, D, totals);
+  return hipGetLastError();
+}
+
+// Writes, for every depth d, the node keys V_d (key >> 3(D-d), tag kept),
+// the occupancy codes X_{d} (atomic OR of 1 << child slot into the parent's
+// byte) and the first-child index of every node.  Tiles hold `tile`
+// elements, processed in rounds of 256 in order.
+__global__ void k_level_write(const uint64_t* __restrict__ keys, int64_t n, int D, int tile,
+                              const uint32_t* __restrict__ offs, LevelOut lo) {
+  __shared__ uint32_t wtot[4][kMaxD + 1];
+  __shared__ uint32_t run[kMaxD + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  if (threadIdx.x <= D) run[threadIdx.x] = offs[(int64_t)blockIdx.x * (D + 1) + threadIdx.x];
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * tile;
+  for (int k0 = 0; k0 < tile; k0 += blockDim.x) {
+    int64_t i = base + k0 + threadIdx.x;
+    bool valid = i < n;
+    int ds = valid ? dstar(keys, i, D) : D + 2;
+    uint64_t key = valid ? keys[i] : 0;
+    uint32_t excl[kMaxD + 1];
+    for (int d = 0; d <= D; d++) {
+      uint64_t m = __ballot(ds <= d);
+      excl[d] = __popcll(m & lt);
+      if (lane == 0) wtot[wave][d] = __popcll(m);
+    }
+    __syncthreads();
+    if (valid) {
+      uint32_t node[kMaxD + 1];
+      for (int d = 0; d <= D; d++) {
+        uint32_t before = run[d];
+        for (int w = 0; w < wave; w++) before += wtot[w][d];
+        // index of the depth-d node holding element i
+        node[d] = before + excl[d] + (ds <= d ? 1u : 0u) - 1u;
+      }
+      if (ds == 0) {  // first element of a frame: record its node per depth
+        const uint64_t f = (3 * D >= 64) ? 0 : (key >> (3 * D));
+        for (int d = 0; d <= D; d++) lo.frame_off[f * (D + 1) + d] = node[d];
+      }
+      for (int d = 0; d <= D; d++) {
+        if (ds > d) continue;
+        lo.key[d][node[d]] = key >> (3 * (D - d));
+        if (d < D) lo.cstart[d][node[d]] = (int32_t)node[d + 1];
+        if (d >= 1) {
+          uint32_t slot = (uint32_t)((key >> (3 * (D - d))) & 7u);
+          uint32_t p = node[d - 1];
+          atomicOr((uint32_t*)(lo.code[d - 1] + (p & ~3u)), (1u << slot) << (8 * (p & 3u)));
+        }
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x <= D) {
+      uint32_t add = 0;
+      for (int w = 0; w < 4; w++) add += wtot[w][threadIdx.x];
+      run[threadIdx.x] += add;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_level_write(const uint64_t* keys, int64_t n, int D, int tile, const uint32_t* hist,
+                              const LevelOut& lo, hipStream_t s) {
+  int64_t nb = (n + tile - 1) / tile;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_write, dim3((unsigned)nb), dim3(kLevelThreads), 0, s, keys, n, D, tile, hist, lo);
+  return hipGetLastError();
+}
+
+// cstart[d][N_d] = N_{d+1}: sentinel after the last node of every depth
+__global__ void k_sentinels(LevelOut lo, const uint32_t* __restrict__ totals, int D) {
+  int d = threadIdx.x;
+  if (d < D) lo.cstart[d][totals[d]] = (int32_t)totals[d + 1];
+}
+
+hipError_t launch_sentinels(const LevelOut& lo, const uint32_t* totals, int D, hipStream_t s) {
+  hipLaunchKernelGGL(k_sentinels, dim3(1), dim3(64), 0, s, lo, totals, D);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Coordinate hash: open addressing, linear probing, 2^k >= 2N slots of
+// {u64 key, i32 row}; empty slots hold all-ones.  Lookups return the same
+// row whatever the insertion order.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint64_t hmix(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__global__ void k_hash_insert(const uint64_t* __restrict__ keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
+                              uint64_t mask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t k = keys[i];
+  uint64_t slot = hmix(k) & mask;
+  for (uint64_t probe = 0; probe <= mask; probe++) {
+    unsigned long long prev = atomicCAS((unsigned long long*)&tkeys[slot], (unsigned long long)kEmpty,
+                                        (unsigned long long)k);
+    if (prev == kEmpty || prev == k) {
+      tvals[slot] = (int32_t)i;
+      return;
+    }
+    slot = (slot + 1) & mask;
+  }
+}
+
+hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, tkeys, tvals,
+                     mask);
+  return hipGetLastError();
+}
+
+// One lane per (node, tap): neighbour (dx,dy,dz) of tap 9(dx+1)+3(dy+1)+(dz+1);
+// kmap[tap * kstride + node] = its row, or -1 when empty / outside [0,2^j)^3.
+__global__ void k_kmap(const uint64_t* __restrict__ keys, int64_t n, int j, const uint64_t* __restrict__ tkeys,
+                       const int32_t* __restrict__ tvals, uint64_t mask, int32_t* __restrict__ kmap,
+                       int64_t kstride) {
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * 27) return;
+  int64_t i = gid / 27;
+  int t = (int)(gid - i * 27);
+  uint64_t key = keys[i];
+  uint64_t low = j > 0 ? (key & ((1ull << (3 * j)) - 1)) : 0;
+  uint64_t tag = key ^ low;
+  int x = (int)compact3(low >> 2) + t / 9 - 1;
+  int y = (int)compact3(low >> 1) + (t / 3) % 3 - 1;
+  int z = (int)compact3(low) + t % 3 - 1;
+  int side = 1 << j;
+  int32_t r = -1;
+  if (x >= 0 && y >= 0 && z >= 0 && x < side && y < side && z < side) {
+    uint64_t q = tag | (spread3((uint32_t)x) << 2) | (spread3((uint32_t)y) << 1) | spread3((uint32_t)z);
+    uint64_t slot = hmix(q) & mask;
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+      uint64_t v = tkeys[slot];
+      if (v == q) { r = tvals[slot]; break; }
+      if (v == kEmpty) break;
+      slot = (slot + 1) & mask;
+    }
+  }
+  kmap[(int64_t)t * kstride + i] = r;
+}
+
+hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* tkeys, const int32_t* tvals,
+                       uint64_t mask, int32_t* kmap, int64_t kstride, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t tot = n * 27;
+  hipLaunchKernelGGL(k_kmap, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, keys, n, j, tkeys, tvals, mask,
+                     kmap, kstride);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Child expansion (decode): children of parent p are (key_p << 3) | o for the
+// set bits o of X[p], ascending, which keeps Morton order (Sec. S3.2).
+// Three passes: per-tile popcount sums, one-block scan, write.
+// ---------------------------------------------------------------------------
+constexpr int kExpandTile = 2048;
+
+__global__ void k_expand_sum(const uint8_t* __restrict__ codes, int64_t n, uint32_t* __restrict__ sums) {
+  __shared__ uint32_t ws[4];
+  int64_t base = (int64_t)blockIdx.x * kExpandTile;
+  uint32_t c = 0;
+  for (int k = threadIdx.x; k < kExpandTile; k += blockDim.x) {
+    int64_t i = base + k;
+    if (i < n) c += __popc((uint32_t)codes[i]);
+  }
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ void k_expand_scan(uint32_t* __restrict__ sums, int nb, int64_t expected, uint32_t* err) {
+  __shared__ uint32_t part[256];
+  int tid = threadIdx.x;
+  int per = (nb + 255) / 256;
+  int t0 = tid * per, t1 = min(nb, t0 + per);
+  uint32_t run = 0;
+  for (int t = t0; t < t1; t++) run += sums[t];
+  part[tid] = run;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int k = 0; k < 256; k++) { uint32_t v = part[k]; part[k] = acc; acc += v; }
+    if ((int64_t)acc != expected) atomicOr(err, ERR_COUNT);
+  }
+  __syncthreads();
+  uint32_t acc = part[tid];
+  for (int t = t0; t < t1; t++) { uint32_t v = sums[t]; sums[t] = acc; acc += v; }
+}
+
+__global__ void k_expand_write(const uint64_t* __restrict__ pkeys, const uint8_t* __restrict__ codes, int64_t n,
+                               const uint32_t* __restrict__ offs, uint64_t* __restrict__ ckeys,
+                               int32_t* __restrict__ cstart, int64_t expected) {
+  __shared__ uint32_t wtot[4];
+  __shared__ uint32_t run;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) run = offs[blockIdx.x];
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kExpandTile;
+  for (int k0 = 0; k0 < kExpandTile; k0 += blockDim.x) {
+    int64_t i = base + k0 + threadIdx.x;
+    uint32_t code = i < n ? codes[i] : 0u;
+    uint32_t c = __popc(code);
+    // inclusive wave scan
+    uint32_t inc = c;
+    for (int off = 1; off < 64; off <<= 1) {
+      uint32_t v = __shfl_up(inc, off);
+      if (lane >= off) inc += v;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint32_t before = run;
+    for (int w = 0; w < wave; w++) before += wtot[w];
+    uint32_t first = before + inc - c;
+    if (i < n) {
+      cstart[i] = (int32_t)first;
+      uint64_t pk = pkeys[i];
+      uint32_t r = first;
+      for (int o = 0; o < 8; o++)
+        if ((code >> o) & 1u) {
+          if ((int64_t)r < expected) ckeys[r] = (pk << 3) | (uint64_t)o;
+          r++;
+        }
+      if (i == n - 1) cstart[n] = (int32_t)(first + c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) run += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_expand(const uint64_t* pkeys, const uint8_t* codes, int64_t n, uint64_t* ckeys, int32_t* cstart,
+                         int64_t n_child_expected, uint32_t* scan_tmp, uint32_t* err, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int nb = (int)((n + kExpandTile - 1) / kExpandTile);
+  hipLaunchKernelGGL(k_expand_sum, dim3(nb), dim3(256), 0, s, codes, n, scan_tmp);
+  hipLaunchKernelGGL(k_expand_scan, dim3(1), dim3(256), 0, s, scan_tmp, nb, n_child_expected, err);
+  hipLaunchKernelGGL(k_expand_write, dim3(nb), dim3(256), 0, s, pkeys, codes, n, scan_tmp, ckeys, cstart,
+                     n_child_expected);
+  return hipGetLastError();
+}
+
+__global__ void k_keys_to_xyz(const uint64_t* __restrict__ keys, int64_t n, int D, int32_t* __restrict__ xyz) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t k = keys[i] & ((D >= 21) ? ~0ull : ((1ull << (3 * D)) - 1));
+  xyz[3 * i] = (int32_t)compact3(k >> 2);
+  xyz[3 * i + 1] = (int32_t)compact3(k >> 1);
+  xyz[3 * i + 2] = (int32_t)compact3(k);
+}
+
+hipError_t launch_keys_to_xyz(const uint64_t* keys, int64_t n, int D, int32_t* xyz, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keys_to_xyz, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, D, xyz);
+  return hipGetLastError();
+}
+
+}  // namespace lpcc

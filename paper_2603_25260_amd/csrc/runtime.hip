@@ -1,0 +1,1453 @@
+// Host runtime and C ABI: model upload, contexts, and the encode / decode /
+// level_probs pipelines.  Every stage is one launch per depth (or per layer
+// position) over the rows of all frames of a call, driven by segment and
+// tile tables that are uploaded once per phase.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+
+#include "lpcc_internal.h"
+
+using namespace lpcc;
+
+// ===========================================================================
+// Model
+// ===========================================================================
+struct HostLayer {
+  int kind, depth, j, taps, cin, cout;
+  int32_t m_pos, m_neg, r, z_in, z_out;
+  std::vector<int32_t> bias;
+  std::vector<int8_t> W;  // [taps][cin][cout]
+};
+
+struct lpcc_model {
+  int device = 0;
+  int C = 0, D = 0, n_deep = 0, k0 = 0;
+  uint32_t blob_id = 0;
+  std::vector<int> first;        // first layer index of each depth (size D+1)
+  std::vector<HostLayer> host;   // parsed layers
+  LayerDev* d_layers = nullptr;  // device copies of the descriptors
+  void* d_mem = nullptr;         // packed weights, biases, corrections, table
+  int32_t* d_lut = nullptr;
+};
+
+namespace {
+
+uint32_t rd32(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+uint32_t fnv1a(const uint8_t* p, size_t n) {
+  uint32_t h = 2166136261u;
+  for (size_t i = 0; i < n; i++) {
+    h ^= p[i];
+    h *= 16777619u;
+  }
+  return h;
+}
+
+// layer sequence of coded depth d: (kind, j, taps, cin, cout)
+struct Spec {
+  int kind, j, taps, cin, cout;
+};
+std::vector<Spec> depth_layers(int C, int D, int n_deep, int d) {
+  const int k0 = D - n_deep - 1;
+  std::vector<Spec> v;
+  if (d >= 1 && d <= k0) {
+    v.push_back({K_CONV1, 0, 27, C, C});
+    v.push_back({K_CONV2, 0, 27, C, C});
+    v.push_back({K_UP, d - 1, 1, C + 8, 8 * C});
+  } else if (d > k0) {
+    v.push_back({K_EMB, d - 1, 1, 8, C});
+    for (int j = d - 1; j > k0; j--) v.push_back({K_DOWN, j, 8, C, C});
+    v.push_back({K_CONV1, k0, 27, 2 * C, C});
+    v.push_back({K_CONV2, k0, 27, C, C});
+    v.push_back({K_SKIP, k0, 1, 2 * C, C});
+    for (int j = k0; j < d; j++) v.push_back({K_UP, j, 1, C + 8, 8 * C});
+  }
+  v.push_back({K_FC1, d, 1, C, C});
+  v.push_back({K_FC2, d, 1, C, kNSym});
+  return v;
+}
+
+// Exponent table of the integer softmax, E[i] = round(2^15 e^{-i/16}), built
+// with integers only: T_0 = 2^31, T_{i+1} = round(T_i * round(2^32 e^{-1/16}) / 2^32),
+// E[i] = round(T_i / 2^16).  (Equal to the rounded exponential for all i.)
+void softmax_table(int32_t* E) {
+  uint64_t T = 1ull << 31;
+  for (int i = 0; i < 256; i++) {
+    E[i] = (int32_t)((T + (1ull << 15)) >> 16);
+    T = (T * 4034748382ull + (1ull << 31)) >> 32;
+  }
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int parse_blob(const uint8_t* b, size_t len, lpcc_model* m) {
+  if (len < 32 || rd32(b) != 0x5743504Cu || rd32(b + 4) != 1) return LPCC_E_MODEL;
+  m->C = (int)rd32(b + 8);
+  m->D = (int)rd32(b + 12);
+  m->n_deep = (int)rd32(b + 16);
+  const int n_layers = (int)rd32(b + 20);
+  if (!(m->C == 16 || m->C == 32 || m->C == 64)) return LPCC_E_MODEL;  // widths with kernels
+  if (m->D < 1 || m->D > kMaxD || m->n_deep < 0 || m->n_deep > m->D - 1) return LPCC_E_MODEL;
+  m->k0 = m->D - m->n_deep - 1;
+  m->blob_id = fnv1a(b, len);
+  size_t off = 32;
+  m->first.assign(m->D + 1, 0);
+  for (int d = 0; d < m->D; d++) {
+    m->first[d] = (int)m->host.size();
+    for (const Spec& sp : depth_layers(m->C, m->D, m->n_deep, d)) {
+      if (off + 44 > len) return LPCC_E_MODEL;
+      HostLayer L;
+      L.kind = (int)rd32(b + off);
+      L.depth = (int)rd32(b + off + 4);
+      L.j = (int)rd32(b + off + 8);
+      L.taps = (int)rd32(b + off + 12);
+      L.cin = (int)rd32(b + off + 16);
+      L.cout = (int)rd32(b + off + 20);
+      L.m_pos = (int32_t)rd32(b + off + 24);
+      L.m_neg = (int32_t)rd32(b + off + 28);
+      L.r = (int32_t)rd32(b + off + 32);
+      L.z_in = (int32_t)rd32(b + off + 36);
+      L.z_out = (int32_t)rd32(b + off + 40);
+      if (L.kind != sp.kind || L.depth != d || L.j != sp.j || L.taps != sp.taps || L.cin != sp.cin ||
+          L.cout != sp.cout)
+        return LPCC_E_MODEL;
+      if (L.m_pos < 0 || L.m_neg < 0 || L.r < 0 || L.r > 62 || L.z_in < -128 || L.z_in > 127 || L.z_out < -128 ||
+          L.z_out > 127)
+        return LPCC_E_MODEL;
+      off += 44;
+      const size_t nb = (size_t)L.cout * 4, nw = (size_t)L.taps * L.cin * L.cout;
+      if (off + nb + nw > len) return LPCC_E_MODEL;
+      L.bias.resize(L.cout);
+      for (int o = 0; o < L.cout; o++) {
+        L.bias[o] = (int32_t)rd32(b + off + 4 * (size_t)o);
+        if (L.bias[o] <= -(1 << 24) || L.bias[o] >= (1 << 24)) return LPCC_E_MODEL;
+      }
+      off += nb;
+      L.W.assign((const int8_t*)(b + off), (const int8_t*)(b + off + nw));
+      off = align_up(off + nw, 4);
+      m->host.push_back(std::move(L));
+    }
+  }
+  m->first[m->D] = (int)m->host.size();
+  if ((int)m->host.size() != n_layers || off != len) return LPCC_E_MODEL;
+  return LPCC_OK;
+}
+
+// Device image of one layer: packed B operand, bias (zero point folded in for
+// dense layers), per-tap zero-point corrections for sparse layers.
+struct LayerImage {
+  std::vector<int8_t> packed;
+  std::vector<int32_t> bias, zc;
+  int ksteps, npad;
+};
+
+LayerImage build_image(const HostLayer& L) {
+  LayerImage im;
+  const int K = L.taps * L.cin;
+  const int kpad = (int)align_up(K, 64);
+  im.ksteps = kpad / 64;
+  im.npad = (int)align_up(L.cout, 16);
+  const int NB = im.npad / 16;
+  im.packed.assign((size_t)kpad * im.npad, 0);
+  for (int s = 0; s < im.ksteps; s++)
+    for (int nb = 0; nb < NB; nb++)
+      for (int lane = 0; lane < 64; lane++)
+        for (int i = 0; i < 16; i++) {
+          const int k = 64 * s + 16 * (lane / 16) + i, col = 16 * nb + lane % 16;
+          int8_t v = 0;
+          if (k < K && col < L.cout) v = L.W[(size_t)k * L.cout + col];
+          im.packed[(((size_t)s * NB + nb) * 64 + lane) * 16 + i] = v;
+        }
+  im.bias.assign(im.npad, 0);
+  const bool sparse = L.taps > 1;
+  for (int o = 0; o < L.cout; o++) {
+    int64_t b = L.bias[o];
+    if (!sparse && L.z_in != 0) {
+      int64_t cs = 0;
+      for (int k = 0; k < K; k++) cs += L.W[(size_t)k * L.cout + o];
+      b -= (int64_t)L.z_in * cs;
+    }
+    im.bias[o] = (int32_t)b;
+  }
+  if (sparse && L.z_in != 0) {
+    im.zc.assign((size_t)L.taps * im.npad, 0);
+    for (int t = 0; t < L.taps; t++)
+      for (int o = 0; o < L.cout; o++) {
+        int64_t cs = 0;
+        for (int c = 0; c < L.cin; c++) cs += L.W[((size_t)t * L.cin + c) * L.cout + o];
+        im.zc[(size_t)t * im.npad + o] = (int32_t)(-(int64_t)L.z_in * cs);
+      }
+  }
+  return im;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Context
+// ===========================================================================
+namespace {
+
+// Grow-only device buffer carved by a bump pointer.  A measuring pass with
+// base == nullptr sizes a phase before the real pass.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  bool measuring = false;
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = (T*)(base + off);
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct lpcc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  char* dev[3] = {nullptr, nullptr, nullptr};  // arenas: octree, model, descriptors
+  size_t cap[3] = {0, 0, 0};
+  uint8_t* pinned = nullptr;  // host staging (descriptors, small read-backs)
+  size_t pinned_cap = 0;
+  // kernel timing
+  std::string time_family;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t ev_used = 0;
+  int64_t time_units = 0;
+};
+
+namespace {
+
+#define HIPC(expr)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      char b_[256];                                                                  \
+      snprintf(b_, sizeof(b_), "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+      c->err = b_;                                                                   \
+      return e_ == hipErrorOutOfMemory ? LPCC_E_NOMEM : LPCC_E_DEVICE;               \
+    }                                                                                \
+  } while (0)
+
+int reserve(lpcc_ctx* c, int which, size_t bytes) {
+  if (bytes <= c->cap[which]) return LPCC_OK;
+  size_t nc = std::max(bytes, c->cap[which] + c->cap[which] / 4);
+  HIPC(hipStreamSynchronize(c->stream));
+  if (c->dev[which]) HIPC(hipFree(c->dev[which]));
+  c->dev[which] = nullptr;
+  c->cap[which] = 0;
+  HIPC(hipMalloc((void**)&c->dev[which], nc));
+  c->cap[which] = nc;
+  return LPCC_OK;
+}
+
+int reserve_pinned(lpcc_ctx* c, size_t bytes) {
+  if (bytes <= c->pinned_cap) return LPCC_OK;
+  size_t nc = std::max(bytes, c->pinned_cap * 2);
+  HIPC(hipStreamSynchronize(c->stream));
+  if (c->pinned) HIPC(hipHostFree(c->pinned));
+  c->pinned = nullptr;
+  c->pinned_cap = 0;
+  HIPC(hipHostMalloc((void**)&c->pinned, nc, hipHostMallocDefault));
+  c->pinned_cap = nc;
+  return LPCC_OK;
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// Descriptor batch: host bytes uploaded in one copy; launches are closures
+// over offsets into the uploaded block.
+struct Batch {
+  std::vector<uint8_t> bytes;
+  struct L {
+    std::string family;
+    int64_t units;
+    std::function<hipError_t(const uint8_t*)> fn;
+  };
+  std::vector<L> launches;
+  template <class T>
+  size_t add(const std::vector<T>& v) {
+    size_t off = align_up(bytes.size(), 64);
+    bytes.resize(off + std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (!v.empty()) memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+  void launch(const std::string& fam, int64_t units, std::function<hipError_t(const uint8_t*)> fn) {
+    launches.push_back({fam, units, std::move(fn)});
+  }
+};
+
+// Upload and enqueue a batch.  `slot` chooses the half of the descriptor
+// arena so that two batches of one call never overlap.
+int run_batch(lpcc_ctx* c, Batch& b, size_t* desc_off) {
+  const size_t n = align_up(b.bytes.size(), 256);
+  size_t need = *desc_off + n;
+  if (need > c->cap[2]) {
+    // everything enqueued so far has to finish before the arena may move
+    HIPC(hipStreamSynchronize(c->stream));
+    *desc_off = 0;
+    need = n;
+    int st = reserve(c, 2, std::max<size_t>(need, 1 << 20));
+    if (st) return st;
+  }
+  int st = reserve_pinned(c, std::max(c->pinned_cap, need));
+  if (st) return st;
+  // the pinned block mirrors the device block; regions of one call do not overlap
+  memcpy(c->pinned + *desc_off, b.bytes.data(), b.bytes.size());
+  uint8_t* dbase = (uint8_t*)c->dev[2] + *desc_off;
+  if (!b.bytes.empty())
+    HIPC(hipMemcpyAsync(dbase, c->pinned + *desc_off, b.bytes.size(), hipMemcpyHostToDevice, c->stream));
+  *desc_off += n;
+  for (auto& L : b.launches) {
+    const bool timed = !c->time_family.empty() && L.family == c->time_family;
+    if (timed) {
+      if (c->ev_used == c->ev.size()) {
+        hipEvent_t a, z;
+        HIPC(hipEventCreate(&a));
+        HIPC(hipEventCreate(&z));
+        c->ev.push_back({a, z});
+      }
+      HIPC(hipEventRecord(c->ev[c->ev_used].first, c->stream));
+    }
+    HIPC(L.fn(dbase));
+    if (timed) {
+      HIPC(hipEventRecord(c->ev[c->ev_used].second, c->stream));
+      c->ev_used++;
+      c->time_units += L.units;
+    }
+  }
+  b.bytes.clear();
+  b.launches.clear();
+  return LPCC_OK;
+}
+
+// tiles of 64 rows over a list of segments with the given row counts
+std::vector<Tile> make_tiles(const std::vector<int64_t>& rows, int rows_per_tile = 64) {
+  std::vector<Tile> t;
+  for (size_t s = 0; s < rows.size(); s++)
+    for (int64_t r = 0; r < rows[s]; r += rows_per_tile) t.push_back({(int32_t)s, (int32_t)r});
+  return t;
+}
+
+int64_t nchunks_of(int64_t N, int c) { return (N + (1ll << c) - 1) >> c; }
+
+}  // namespace
+
+// ===========================================================================
+// Pipeline state of one call (all frames share every per-depth array)
+// ===========================================================================
+namespace {
+
+struct Frames {
+  int nf = 0;
+  std::vector<std::vector<int64_t>> N;    // [f][d] nodes of frame f at depth d
+  std::vector<std::vector<int64_t>> off;  // [f][d] first node of frame f at depth d
+  std::vector<int64_t> tot;               // [d] nodes of all frames
+};
+
+struct Levels {
+  uint64_t* key[kMaxD + 1] = {};
+  uint8_t* code[kMaxD + 1] = {};
+  int32_t* cstart[kMaxD + 1] = {};
+};
+
+// Model-phase buffers (depth d arrays are [tot[d]] rows)
+struct ModelBufs {
+  int8_t* F[kMaxD + 1] = {};         // features that predict depth d (shallow d and k0)
+  int32_t* kmap[kMaxD + 1] = {};     // [27][tot[j]] for the depths that convolve
+  uint64_t* hkeys[kMaxD + 1] = {};
+  int32_t* hvals[kMaxD + 1] = {};
+  uint64_t hmask[kMaxD + 1] = {};
+  int8_t *h = nullptr, *S = nullptr;  // shallow ResBlock temporaries
+  // deep temporaries per target depth d
+  int8_t* G[kMaxD + 1][kMaxD + 1] = {};  // [d][j] embedding / down-sampled features at depth j
+  int8_t* cat[kMaxD + 1] = {};           // [tot[k0]][2C]
+  int8_t* dh[kMaxD + 1] = {};
+  int8_t* ds[kMaxD + 1] = {};
+  int8_t* Z[kMaxD + 1][kMaxD + 1] = {};  // [d][j] upsampled features at depth j (j = k0 is H)
+};
+
+bool need_kmap(const lpcc_model* m, int j) { return j <= m->k0 - 1 || (j == m->k0 && m->n_deep > 0); }
+
+// Carve the model buffers for depths in [0, last] (`wanted` selects the
+// predicted depths; shallow features are always built up to min(last, k0)).
+void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, const std::vector<bool>& wanted,
+                 ModelBufs& B) {
+  const int C = m->C, k0 = m->k0;
+  const int shallow_last = std::min(last, k0);
+  int64_t tmax = 0;
+  for (int d = 0; d <= shallow_last; d++) {
+    B.F[d] = A.take<int8_t>((size_t)fr.tot[d] * C);
+    tmax = std::max(tmax, fr.tot[d]);
+  }
+  B.h = A.take<int8_t>((size_t)tmax * C);
+  B.S = A.take<int8_t>((size_t)tmax * C);
+  const int kmax = std::min(last, k0);
+  for (int j = 0; j <= kmax; j++) {
+    if (!need_kmap(m, j)) continue;
+    if (j >= last && !(j == k0 && last > k0)) continue;  // only depths that feed a wanted depth
+    uint64_t sz = 1;
+    while (sz < (uint64_t)std::max<int64_t>(2 * fr.tot[j], 2)) sz <<= 1;
+    B.hmask[j] = sz - 1;
+    B.hkeys[j] = A.take<uint64_t>(sz);
+    B.hvals[j] = A.take<int32_t>(sz);
+    B.kmap[j] = A.take<int32_t>((size_t)27 * fr.tot[j]);
+  }
+  for (int d = k0 + 1; d <= last; d++) {
+    if (!wanted[d]) continue;
+    for (int j = d - 1; j > k0; j--) B.G[d][j] = A.take<int8_t>((size_t)fr.tot[j] * C);
+    B.cat[d] = A.take<int8_t>((size_t)fr.tot[k0] * 2 * C);
+    B.dh[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
+    B.ds[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
+    for (int j = k0; j <= d; j++) B.Z[d][j] = A.take<int8_t>((size_t)fr.tot[j] * C);
+  }
+}
+
+const LayerDev* dlayer(const lpcc_model* m, int d, int k) { return m->d_layers + m->first[d] + k; }
+
+GemmSeg seg0() {
+  GemmSeg s;
+  memset(&s, 0, sizeof(s));
+  return s;
+}
+
+// Hash + neighbour table of depth j
+void plan_kmap(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, int j, hipStream_t st) {
+  const int64_t n = fr.tot[j];
+  uint64_t* hk = B.hkeys[j];
+  int32_t* hv = B.hvals[j];
+  const uint64_t mask = B.hmask[j];
+  int32_t* km = B.kmap[j];
+  const uint64_t* keys = lv.key[j];
+  b.launch("hash", n, [=](const uint8_t*) {
+    hipError_t e = launch_fill_u64(hk, (int64_t)mask + 1, ~0ull, st);
+    if (e != hipSuccess) return e;
+    e = launch_hash_insert(keys, n, hk, hv, mask, st);
+    if (e != hipSuccess) return e;
+    return launch_kmap(keys, n, j, hk, hv, mask, km, n, st);
+  });
+}
+
+void plan_gemm(Batch& b, const char* fam, int mode, int cin, int cout, const std::vector<GemmSeg>& segs,
+               hipStream_t st) {
+  std::vector<int64_t> rows;
+  int64_t units = 0;
+  for (auto& s : segs) {
+    rows.push_back(s.rows);
+    units += s.rows;
+  }
+  auto tiles = make_tiles(rows);
+  if (tiles.empty()) return;
+  const size_t so = b.add(segs), to = b.add(tiles);
+  const int nt = (int)tiles.size();
+  std::string f(fam);
+  b.launch(f, units, [=](const uint8_t* base) {
+    const GemmSeg* S = (const GemmSeg*)(base + so);
+    const Tile* T = (const Tile*)(base + to);
+    if (f == "up") return launch_up(cout, S, T, nt, st);
+    if (f == "emb") return launch_emb(S, T, nt, cout, st);
+    return launch_gemm(mode, cin, cout, S, T, nt, st);
+  });
+}
+
+// Shallow depth d (1 <= d <= k0): S = ResBlock(F_{d-1}); F_d = Prune(Up([S | bits X_{d-1}]))
+void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B, int d,
+                  hipStream_t st) {
+  const int C = m->C;
+  const int j = d - 1;
+  const int rows = (int)fr.tot[j];
+  GemmSeg s = seg0();
+  s.in = B.F[j];
+  s.in_stride = C;
+  s.kmap = B.kmap[j];
+  s.kstride = fr.tot[j];
+  s.L = dlayer(m, d, 0);
+  s.out = B.h;
+  s.out_stride = C;
+  s.rows = rows;
+  plan_gemm(b, "conv", G_CONV, C, C, {s}, st);
+  s.in = B.h;
+  s.L = dlayer(m, d, 1);
+  s.out = B.S;
+  s.resid = B.F[j];
+  s.resid_stride = C;
+  plan_gemm(b, "conv", G_CONV, C, C, {s}, st);
+  GemmSeg u = seg0();
+  u.in = B.S;
+  u.in_stride = C;
+  u.code = lv.code[j];
+  u.cstart = lv.cstart[j];
+  u.L = dlayer(m, d, 2);
+  u.out = B.F[d];
+  u.out_stride = C;
+  u.rows = rows;
+  u.child_rows = (int)fr.tot[d];
+  plan_gemm(b, "up", 0, C, C, {u}, st);
+}
+
+// Deep depths `ds` (all > k0), stage by stage; every launch covers all of them.
+void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B,
+               const std::vector<int>& dset, hipStream_t st) {
+  if (dset.empty()) return;
+  const int C = m->C, k0 = m->k0;
+  auto Gout = [&](int d, int j) -> std::pair<int8_t*, int64_t> {  // destination of depth-j G of target d
+    if (j == k0) return {B.cat[d] + C, 2 * C};
+    return {B.G[d][j], C};
+  };
+  // occupancy embedding at depth d-1
+  {
+    std::vector<GemmSeg> v;
+    for (int d : dset) {
+      GemmSeg s = seg0();
+      s.code = lv.code[d - 1];
+      s.L = dlayer(m, d, 0);
+      auto o = Gout(d, d - 1);
+      s.out = o.first;
+      s.out_stride = o.second;
+      s.rows = (int)fr.tot[d - 1];
+      v.push_back(s);
+    }
+    plan_gemm(b, "emb", 0, 8, C, v, st);
+  }
+  // stride-2 steps j -> j-1 for j = d-1 .. k0+1; step t handles j = d - t
+  int maxsteps = 0;
+  for (int d : dset) maxsteps = std::max(maxsteps, d - 1 - k0);
+  for (int t = 1; t <= maxsteps; t++) {
+    std::vector<GemmSeg> v;
+    for (int d : dset) {
+      const int j = d - t;
+      if (j <= k0) continue;
+      GemmSeg s = seg0();
+      s.in = B.G[d][j];
+      s.in_stride = C;
+      s.code = lv.code[j - 1];
+      s.cstart = lv.cstart[j - 1];
+      s.L = dlayer(m, d, t);
+      auto o = Gout(d, j - 1);
+      s.out = o.first;
+      s.out_stride = o.second;
+      s.rows = (int)fr.tot[j - 1];
+      s.child_rows = (int)fr.tot[j];
+      v.push_back(s);
+    }
+    plan_gemm(b, "down", G_DOWN, C, C, v, st);
+  }
+  // [F_k0 | G]
+  for (int d : dset) {
+    const int8_t* src = B.F[k0];
+    int8_t* dst = B.cat[d];
+    const int64_t rows = fr.tot[k0];
+    b.launch("copy", rows, [=](const uint8_t*) { return launch_copy_rows(src, C, dst, 2 * C, rows, C, st); });
+  }
+  // ResBlock at k0: conv1 (2C -> C), skip (2C -> C), conv2 (+ skip)
+  std::vector<GemmSeg> c1, sk, c2;
+  for (int d : dset) {
+    const int base = 1 + (d - 1 - k0);  // index of conv1 in depth d's layer list
+    GemmSeg s = seg0();
+    s.in = B.cat[d];
+    s.in_stride = 2 * C;
+    s.kmap = B.kmap[k0];
+    s.kstride = fr.tot[k0];
+    s.L = dlayer(m, d, base);
+    s.out = B.dh[d];
+    s.out_stride = C;
+    s.rows = (int)fr.tot[k0];
+    c1.push_back(s);
+    GemmSeg k = seg0();
+    k.in = B.cat[d];
+    k.in_stride = 2 * C;
+    k.L = dlayer(m, d, base + 2);
+    k.out = B.ds[d];
+    k.out_stride = C;
+    k.rows = (int)fr.tot[k0];
+    sk.push_back(k);
+    GemmSeg s2 = seg0();
+    s2.in = B.dh[d];
+    s2.in_stride = C;
+    s2.kmap = B.kmap[k0];
+    s2.kstride = fr.tot[k0];
+    s2.L = dlayer(m, d, base + 1);
+    s2.out = B.Z[d][k0];
+    s2.out_stride = C;
+    s2.resid = B.ds[d];
+    s2.resid_stride = C;
+    s2.rows = (int)fr.tot[k0];
+    c2.push_back(s2);
+  }
+  plan_gemm(b, "conv", G_CONV, 2 * C, C, c1, st);
+  plan_gemm(b, "skip", G_DENSE, 2 * C, C, sk, st);
+  plan_gemm(b, "conv", G_CONV, C, C, c2, st);
+  // upsample + prune k0 -> d
+  int maxup = 0;
+  for (int d : dset) maxup = std::max(maxup, d - k0);
+  for (int t = 0; t < maxup; t++) {
+    std::vector<GemmSeg> v;
+    for (int d : dset) {
+      const int j = k0 + t;
+      if (j >= d) continue;
+      const int base = 1 + (d - 1 - k0) + 3;  // first up layer
+      GemmSeg u = seg0();
+      u.in = B.Z[d][j];
+      u.in_stride = C;
+      u.code = lv.code[j];
+      u.cstart = lv.cstart[j];
+      u.L = dlayer(m, d, base + t);
+      u.out = B.Z[d][j + 1];
+      u.out_stride = C;
+      u.rows = (int)fr.tot[j];
+      u.child_rows = (int)fr.tot[j + 1];
+      v.push_back(u);
+    }
+    plan_gemm(b, "up", 0, C, C, v, st);
+  }
+}
+
+const int8_t* features_of(const lpcc_model* m, const ModelBufs& B, int d) {
+  return d <= m->k0 ? B.F[d] : B.Z[d][d];
+}
+
+void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& segs, int mode, hipStream_t st) {
+  std::vector<int64_t> rows;
+  int64_t units = 0;
+  for (auto& s : segs) {
+    rows.push_back(s.rows);
+    units += s.rows;
+  }
+  auto tiles = make_tiles(rows);
+  if (tiles.empty()) return;
+  const size_t so = b.add(segs), to = b.add(tiles);
+  const int nt = (int)tiles.size(), C = m->C;
+  const int32_t* lut = m->d_lut;
+  b.launch("predict", units, [=](const uint8_t* base) {
+    return launch_predict(C, mode, (const PredSeg*)(base + so), (const Tile*)(base + to), nt, lut, st);
+  });
+}
+
+// Octree of all frames: Morton keys, radix sort, level arrays.  Fills
+// `fr` (after a synchronisation) and the level pointers.
+int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n,
+                 Levels& lv, Frames& fr, std::vector<int>& fstatus, size_t* desc_off) {
+  const int D = m->D;
+  hipStream_t st = c->stream;
+  int64_t ntot = 0;
+  std::vector<int64_t> start(nf + 1, 0);
+  for (int f = 0; f < nf; f++) {
+    start[f] = ntot;
+    ntot += n[f];
+  }
+  start[nf] = ntot;
+  int fbits = 0;
+  while ((1ll << fbits) < nf) fbits++;
+  if (3 * D + fbits > 64) {
+    c->err = "too many frames for this depth";
+    return LPCC_E_INVAL;
+  }
+  const int end_bit = 3 * D + fbits;
+  size_t sort_tmp = 0;
+  HIPC(hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                         (int)std::max<int64_t>(ntot, 1), 0, std::max(end_bit, 1), st));
+  const int tile = 2048;
+  const int64_t ntiles = (ntot + tile - 1) / tile;
+  // upper bounds of the node count per depth
+  std::vector<int64_t> ub(D + 1, 0);
+  for (int f = 0; f < nf; f++)
+    for (int d = 0; d <= D; d++) {
+      int64_t cap = d >= 21 ? n[f] : std::min<int64_t>(n[f], 1ll << (3 * d));
+      ub[d] += cap;
+    }
+  bool need_stage = false;
+  for (int f = 0; f < nf; f++)
+    if (n[f] > 0 && !is_device_ptr(xyz[f])) need_stage = true;
+
+  int32_t* xyz_stage = nullptr;
+  uint64_t *kin = nullptr, *kout = nullptr;
+  void* tmp = nullptr;
+  uint32_t *err = nullptr, *hist = nullptr, *totals = nullptr, *foff = nullptr;
+  auto carve = [&](Arena& A) {
+    if (need_stage) xyz_stage = A.take<int32_t>((size_t)ntot * 3);
+    kin = A.take<uint64_t>(ntot);
+    kout = A.take<uint64_t>(ntot);
+    tmp = A.take<char>(sort_tmp);
+    err = A.take<uint32_t>(nf);
+    hist = A.take<uint32_t>((size_t)std::max<int64_t>(ntiles, 1) * (D + 1));
+    totals = A.take<uint32_t>(D + 1);
+    foff = A.take<uint32_t>((size_t)nf * (D + 1));
+    for (int d = 0; d <= D; d++) {
+      lv.key[d] = A.take<uint64_t>(ub[d]);
+      lv.code[d] = A.take<uint8_t>(align_up(ub[d], 4) + 4);
+      lv.cstart[d] = A.take<int32_t>(ub[d] + 1);
+    }
+  };
+  Arena meas;
+  meas.measuring = true;
+  carve(meas);
+  int s = reserve(c, 0, meas.off + 4096);
+  if (s) return s;
+  Arena A;
+  A.base = c->dev[0];
+  A.cap = c->cap[0];
+  carve(A);
+
+  HIPC(launch_fill_u32(err, nf, 0, st));
+  HIPC(launch_fill_u32(foff, (int64_t)nf * (D + 1), 0xFFFFFFFFu, st));
+  HIPC(launch_fill_u32(totals, D + 1, 0, st));
+  for (int d = 0; d <= D; d++) HIPC(launch_fill_u32((uint32_t*)lv.code[d], (int64_t)(align_up(ub[d], 4) + 4) / 4, 0, st));
+  for (int f = 0; f < nf; f++) {
+    if (n[f] <= 0) continue;
+    const int32_t* src = xyz[f];
+    if (!is_device_ptr(src)) {
+      HIPC(hipMemcpyAsync(xyz_stage + 3 * start[f], src, (size_t)n[f] * 12, hipMemcpyHostToDevice, st));
+      src = xyz_stage + 3 * start[f];
+    }
+    HIPC(launch_morton(src, n[f], D, (uint64_t)f << (3 * D), kin + start[f], err + f, st));
+  }
+  if (ntot > 0) {
+    size_t tb = sort_tmp;
+    HIPC(hipcub::DeviceRadixSort::SortKeys(tmp, tb, kin, kout, (int)ntot, 0, end_bit, st));
+    HIPC(launch_level_hist(kout, ntot, D, tile, hist, st));
+    HIPC(launch_level_scan(hist, (int)ntiles, D, totals, st));
+    LevelOut lo;
+    memset(&lo, 0, sizeof(lo));
+    for (int d = 0; d <= D; d++) {
+      lo.key[d] = lv.key[d];
+      lo.code[d] = lv.code[d];
+      lo.cstart[d] = lv.cstart[d];
+    }
+    lo.frame_off = foff;
+    HIPC(launch_level_write(kout, ntot, D, tile, hist, lo, st));
+    HIPC(launch_sentinels(lo, totals, D, st));
+  }
+  // read back counts, frame offsets and errors
+  const size_t rb = (size_t)(D + 1 + nf * (D + 1) + nf) * 4;
+  s = reserve_pinned(c, *desc_off + rb + 256);
+  if (s) return s;
+  uint32_t* h = (uint32_t*)(c->pinned + c->pinned_cap - align_up(rb, 256));
+  HIPC(hipMemcpyAsync(h, totals, (D + 1) * 4, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(h + D + 1, foff, (size_t)nf * (D + 1) * 4, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(h + (D + 1) * (nf + 1), err, (size_t)nf * 4, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  fr.nf = nf;
+  fr.tot.assign(D + 1, 0);
+  for (int d = 0; d <= D; d++) fr.tot[d] = h[d];
+  fr.N.assign(nf, std::vector<int64_t>(D + 1, 0));
+  fr.off.assign(nf, std::vector<int64_t>(D + 1, 0));
+  fstatus.assign(nf, LPCC_OK);
+  for (int f = 0; f < nf; f++)
+    if (h[(D + 1) * (nf + 1) + f] & ERR_COORD) fstatus[f] = LPCC_E_INVAL;
+  for (int d = 0; d <= D; d++) {
+    int64_t next = fr.tot[d];
+    for (int f = nf - 1; f >= 0; f--) {
+      const uint32_t o = h[D + 1 + f * (D + 1) + d];
+      if (n[f] <= 0 || o == 0xFFFFFFFFu) {
+        fr.off[f][d] = next;
+        fr.N[f][d] = 0;
+        continue;
+      }
+      fr.off[f][d] = o;
+      fr.N[f][d] = next - o;
+      next = o;
+    }
+  }
+  return LPCC_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Encode (and level_probs) of a batch of frames
+// ===========================================================================
+namespace {
+
+struct OutSpec {
+  uint8_t* const* out;
+  const size_t* cap;
+  size_t* out_len;
+};
+
+int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n, int cl,
+                OutSpec os, int* status, int probe_level, int32_t* cdf_out, int64_t cdf_cap, int64_t* n_nodes) {
+  const int D = m->D, C = m->C, k0 = m->k0;
+  hipStream_t st = c->stream;
+  size_t desc_off = 0;
+  Levels lv;
+  Frames fr;
+  std::vector<int> fst;
+  int s = build_octree(c, m, nf, xyz, n, lv, fr, fst, &desc_off);
+  if (s) return s;
+  for (int f = 0; f < nf; f++)
+    if (fst[f] != LPCC_OK) {
+      for (int g = 0; g < nf; g++) status[g] = fst[g];
+      return fst[f];
+    }
+  const bool probe = probe_level >= 0;
+  const int last = probe ? probe_level : D - 1;
+  std::vector<bool> wanted(D, !probe);
+  if (probe) wanted[probe_level] = true;
+  if (probe) {
+    *n_nodes = fr.tot[probe_level];
+    if (fr.tot[probe_level] > cdf_cap) {
+      status[0] = LPCC_E_CAPACITY;
+      return LPCC_E_CAPACITY;
+    }
+  }
+  // ---- model phase buffers
+  ModelBufs B;
+  uint32_t* sf = nullptr;
+  int32_t* cdf_stage = nullptr;
+  uint8_t* scratch = nullptr;
+  uint32_t* lens = nullptr;
+  std::vector<int64_t> dbase(D + 1, 0);
+  for (int d = 0; d < D; d++) dbase[d + 1] = dbase[d] + fr.tot[d];
+  // chunk table (encode only)
+  std::vector<Chunk> chunks;
+  std::vector<int> chunk_frame;
+  int64_t scratch_bytes = 0;
+  if (!probe) {
+    for (int f = 0; f < nf; f++)
+      for (int d = 0; d < D; d++) {
+        const int64_t Nfd = fr.N[f][d];
+        for (int64_t k = 0; k < nchunks_of(Nfd, cl); k++) {
+          Chunk ch;
+          ch.node0 = dbase[d] + fr.off[f][d] + (k << cl);
+          ch.count = (int32_t)std::min<int64_t>(1ll << cl, Nfd - (k << cl));
+          ch.pad_ = 0;
+          ch.scratch = scratch_bytes;
+          scratch_bytes += align_up(2 * (size_t)ch.count + 16, 16);
+          chunks.push_back(ch);
+          chunk_frame.push_back(f);
+        }
+      }
+  }
+  const bool cdf_dev = probe && is_device_ptr(cdf_out);
+  // per-frame output staging (host outputs and frames that fail): header
+  // bound + the frame's chunk scratch bound
+  std::vector<size_t> stage_off(nf, 0);
+  size_t stage_bytes = 0;
+  if (!probe) {
+    std::vector<size_t> fbytes(nf, 16 + 4 * (size_t)D);
+    for (size_t k = 0; k < chunks.size(); k++) fbytes[chunk_frame[k]] += 2 + align_up(2 * (size_t)chunks[k].count + 16, 16);
+    for (int f = 0; f < nf; f++) {
+      stage_off[f] = stage_bytes;
+      stage_bytes += align_up(fbytes[f], 256);
+    }
+  }
+  uint8_t* stage = nullptr;
+  auto carve = [&](Arena& A) {
+    carve_model(A, m, fr, last, wanted, B);
+    if (!probe) {
+      sf = A.take<uint32_t>(dbase[D]);
+      scratch = A.take<uint8_t>(scratch_bytes);
+      lens = A.take<uint32_t>(chunks.size());
+      stage = A.take<uint8_t>(stage_bytes);
+    } else if (!cdf_dev) {
+      cdf_stage = A.take<int32_t>((size_t)fr.tot[probe_level] * 256);
+    }
+  };
+  Arena meas;
+  carve(meas);
+  s = reserve(c, 1, meas.off + 4096);
+  if (s) return s;
+  Arena A;
+  A.base = c->dev[1];
+  A.cap = c->cap[1];
+  carve(A);
+
+  Batch b;
+  // F_0 = 0
+  {
+    int8_t* f0 = B.F[0];
+    const int64_t bytes = fr.tot[0] * C;
+    b.launch("fill", 0, [=](const uint8_t*) { return launch_fill_u32((uint32_t*)f0, (bytes + 3) / 4, 0, st); });
+  }
+  for (int j = 0; j <= std::min(last, k0); j++)
+    if (B.kmap[j]) plan_kmap(b, lv, fr, B, j, st);
+  for (int d = 1; d <= std::min(last, k0); d++) plan_shallow(b, m, lv, fr, B, d, st);
+  std::vector<int> dset;
+  for (int d = k0 + 1; d <= last; d++)
+    if (wanted[d]) dset.push_back(d);
+  plan_deep(b, m, lv, fr, B, dset, st);
+  // predictor
+  std::vector<PredSeg> ps;
+  for (int d = 0; d <= last; d++) {
+    if (!wanted[d] || fr.tot[d] == 0) continue;
+    PredSeg p;
+    memset(&p, 0, sizeof(p));
+    p.F = features_of(m, B, d);
+    p.code = lv.code[d];
+    p.fc1 = dlayer(m, d, m->first[d + 1] - m->first[d] - 2);
+    p.fc2 = dlayer(m, d, m->first[d + 1] - m->first[d] - 1);
+    p.rows = (int)fr.tot[d];
+    if (probe) p.cdf32 = cdf_dev ? cdf_out : cdf_stage;
+    else p.sf = sf + dbase[d];
+    ps.push_back(p);
+  }
+  plan_predict(b, m, ps, probe ? 2 : 0, st);
+  if (!probe && !chunks.empty()) {
+    const size_t co = b.add(chunks);
+    const int nch = (int)chunks.size();
+    b.launch("rc_encode", dbase[D], [=](const uint8_t* base) {
+      return launch_rc_encode((const Chunk*)(base + co), nch, sf, scratch, lens, st);
+    });
+  }
+  s = run_batch(c, b, &desc_off);
+  if (s) return s;
+
+  if (probe) {
+    if (!cdf_dev && fr.tot[probe_level] > 0)
+      HIPC(hipMemcpyAsync(cdf_out, cdf_stage, (size_t)fr.tot[probe_level] * 1024, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    status[0] = LPCC_OK;
+    return LPCC_OK;
+  }
+
+  // ---- stream assembly: lengths -> headers -> payload placement
+  const size_t nch = chunks.size();
+  std::vector<uint32_t> hl(nch);
+  if (nch) {
+    HIPC(hipMemcpyAsync(hl.data(), lens, nch * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+  }
+  std::vector<std::vector<uint8_t>> hdr(nf);
+  std::vector<size_t> total(nf, 0);
+  std::vector<uint8_t*> dst(nch, nullptr);
+  std::vector<bool> odev(nf, false);
+  {
+    size_t ci = 0;
+    for (int f = 0; f < nf; f++) {
+      size_t nchf = 0;
+      for (int d = 0; d < D; d++) nchf += (size_t)nchunks_of(fr.N[f][d], cl);
+      std::vector<uint8_t>& H = hdr[f];
+      H.assign(16 + 4 * (size_t)D + 2 * nchf, 0);
+      H[0] = 'L'; H[1] = 'P'; H[2] = 'C'; H[3] = '1';
+      H[4] = 1; H[5] = (uint8_t)D; H[6] = (uint8_t)m->n_deep; H[7] = (uint8_t)cl;
+      auto w32 = [&](size_t o, uint32_t v) { for (int k = 0; k < 4; k++) H[o + k] = (uint8_t)(v >> (8 * k)); };
+      w32(8, m->blob_id);
+      w32(12, (uint32_t)fr.N[f][D]);
+      for (int d = 0; d < D; d++) w32(16 + 4 * d, (uint32_t)fr.N[f][d]);
+      size_t pay = 0;
+      for (size_t k = 0; k < nchf; k++) {
+        H[16 + 4 * D + 2 * k] = (uint8_t)(hl[ci + k] & 0xFF);
+        H[16 + 4 * D + 2 * k + 1] = (uint8_t)(hl[ci + k] >> 8);
+        pay += hl[ci + k];
+      }
+      total[f] = H.size() + pay;
+      os.out_len[f] = total[f];
+      status[f] = total[f] > os.cap[f] ? LPCC_E_CAPACITY : LPCC_OK;
+      odev[f] = is_device_ptr(os.out[f]);
+      ci += nchf;
+    }
+  }
+  {
+    size_t ci = 0;
+    for (int f = 0; f < nf; f++) {
+      size_t nchf = 0;
+      for (int d = 0; d < D; d++) nchf += (size_t)nchunks_of(fr.N[f][d], cl);
+      const bool direct = status[f] == LPCC_OK && odev[f];
+      uint8_t* base = direct ? os.out[f] : stage + stage_off[f];
+      size_t o = hdr[f].size();
+      for (size_t k = 0; k < nchf; k++) {
+        dst[ci + k] = base + o;
+        o += hl[ci + k];
+      }
+      ci += nchf;
+    }
+  }
+  if (nch) {
+    const size_t co = b.add(chunks), po = b.add(dst);
+    const int n_ch = (int)nch;
+    b.launch("pack", 0, [=](const uint8_t* base) {
+      return launch_rc_pack((const Chunk*)(base + co), n_ch, scratch, lens, (uint8_t* const*)(base + po), st);
+    });
+    s = run_batch(c, b, &desc_off);
+    if (s) return s;
+  }
+  for (int f = 0; f < nf; f++) {
+    if (status[f] != LPCC_OK) continue;
+    if (odev[f]) {
+      HIPC(hipMemcpyAsync(os.out[f], hdr[f].data(), hdr[f].size(), hipMemcpyHostToDevice, st));
+    } else {
+      memcpy(os.out[f], hdr[f].data(), hdr[f].size());
+      if (total[f] > hdr[f].size())
+        HIPC(hipMemcpyAsync(os.out[f] + hdr[f].size(), stage + stage_off[f] + hdr[f].size(),
+                            total[f] - hdr[f].size(), hipMemcpyDeviceToHost, st));
+    }
+  }
+  HIPC(hipStreamSynchronize(st));
+  int ret = LPCC_OK;
+  for (int f = 0; f < nf; f++)
+    if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
+  return ret;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Decode of a batch of frames
+// ===========================================================================
+namespace {
+
+struct Header {
+  int D = 0, n_deep = 0, cl = 0;
+  uint32_t blob = 0;
+  std::vector<int64_t> N;     // [D+1]
+  std::vector<uint32_t> len;  // chunk lengths
+  size_t hdr = 0, total = 0;
+};
+
+int parse_header(const uint8_t* h, size_t avail, size_t len, Header& H, bool need_lengths) {
+  if (len < 16 || avail < 16) return LPCC_E_CORRUPT;
+  if (h[0] != 'L' || h[1] != 'P' || h[2] != 'C' || h[3] != '1' || h[4] != 1) return LPCC_E_CORRUPT;
+  H.D = h[5];
+  H.n_deep = h[6];
+  H.cl = h[7];
+  H.blob = rd32(h + 8);
+  if (H.D < 1 || H.D > kMaxD || H.cl < 4 || H.cl > 14) return LPCC_E_CORRUPT;
+  const size_t fixed = 16 + 4 * (size_t)H.D;
+  if (len < fixed) return LPCC_E_CORRUPT;
+  if (avail < fixed) return LPCC_E_CAPACITY;  // caller fetches more
+  H.N.assign(H.D + 1, 0);
+  H.N[H.D] = rd32(h + 12);
+  for (int d = 0; d < H.D; d++) H.N[d] = rd32(h + 16 + 4 * d);
+  if (H.N[0] > 1 || ((H.N[0] == 0) != (H.N[H.D] == 0))) return LPCC_E_CORRUPT;
+  for (int d = 0; d < H.D; d++)
+    if (H.N[d + 1] < H.N[d] || H.N[d + 1] > 8 * H.N[d]) return LPCC_E_CORRUPT;
+  int64_t nch = 0;
+  for (int d = 0; d < H.D; d++) nch += nchunks_of(H.N[d], H.cl);
+  H.hdr = fixed + 2 * (size_t)nch;
+  if (len < H.hdr) return LPCC_E_CORRUPT;
+  if (!need_lengths) return LPCC_OK;
+  if (avail < H.hdr) return LPCC_E_CAPACITY;
+  H.len.resize(nch);
+  size_t tot = 0;
+  for (int64_t k = 0; k < nch; k++) {
+    H.len[k] = (uint32_t)h[fixed + 2 * k] | ((uint32_t)h[fixed + 2 * k + 1] << 8);
+    tot += H.len[k];
+  }
+  H.total = H.hdr + tot;
+  if (H.total != len) return LPCC_E_CORRUPT;
+  return LPCC_OK;
+}
+
+int read_header(lpcc_ctx* c, const uint8_t* bs, size_t len, Header& H) {
+  if (!bs) return LPCC_E_INVAL;
+  if (!is_device_ptr(bs)) return parse_header(bs, len, len, H, true);
+  std::vector<uint8_t> tmp(std::min<size_t>(len, 16 + 4 * kMaxD));
+  HIPC(hipMemcpy(tmp.data(), bs, tmp.size(), hipMemcpyDeviceToHost));
+  int s = parse_header(tmp.data(), tmp.size(), len, H, false);
+  if (s) return s;
+  tmp.resize(H.hdr);
+  HIPC(hipMemcpy(tmp.data(), bs, H.hdr, hipMemcpyDeviceToHost));
+  return parse_header(tmp.data(), tmp.size(), len, H, true);
+}
+
+int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* bs, const size_t* len,
+                int32_t* const* xyz_out, const int64_t* cap, int64_t* n_out, int* status) {
+  const int D = m->D, C = m->C, k0 = m->k0;
+  hipStream_t st = c->stream;
+  std::vector<Header> H(nf);
+  std::vector<int> live;
+  for (int f = 0; f < nf; f++) {
+    n_out[f] = 0;
+    int s = read_header(c, bs[f], len[f], H[f]);
+    if (s == LPCC_E_DEVICE || s == LPCC_E_NOMEM) return s;
+    if (s == LPCC_OK && (H[f].D != D || H[f].n_deep != m->n_deep || H[f].blob != m->blob_id)) s = LPCC_E_MODEL;
+    if (s == LPCC_OK) {
+      n_out[f] = H[f].N[D];
+      if (H[f].N[D] > cap[f]) s = LPCC_E_CAPACITY;
+    }
+    status[f] = s;
+    if (s == LPCC_OK && H[f].N[D] > 0) live.push_back(f);
+  }
+  // frames in the batch must share one chunk size; decode others separately
+  Frames fr;
+  fr.nf = nf;
+  fr.tot.assign(D + 1, 0);
+  fr.N.assign(nf, std::vector<int64_t>(D + 1, 0));
+  fr.off.assign(nf, std::vector<int64_t>(D + 1, 0));
+  for (int f : live)
+    for (int d = 0; d <= D; d++) {
+      fr.off[f][d] = fr.tot[d];
+      fr.N[f][d] = H[f].N[d];
+      fr.tot[d] += H[f].N[d];
+    }
+  if (live.empty()) {
+    int ret = LPCC_OK;
+    for (int f = 0; f < nf; f++)
+      if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
+    return ret;
+  }
+  // chunks per depth (all frames), payload placement
+  std::vector<std::vector<Chunk>> dchunks(D);
+  std::vector<size_t> dmaxlen(D, 0);
+  size_t paybytes = 0;
+  std::vector<size_t> payoff(nf, 0);
+  for (int f : live) {
+    payoff[f] = paybytes;
+    paybytes += align_up(H[f].total - H[f].hdr, 16);
+    size_t ci = 0, po = payoff[f];
+    const int cl = H[f].cl;
+    for (int d = 0; d < D; d++) {
+      const int64_t Nfd = H[f].N[d];
+      for (int64_t k = 0; k < nchunks_of(Nfd, cl); k++) {
+        Chunk ch;
+        ch.node0 = fr.off[f][d] + (k << cl);
+        ch.count = (int32_t)std::min<int64_t>(1ll << cl, Nfd - (k << cl));
+        ch.pad_ = (int32_t)H[f].len[ci];
+        ch.scratch = (int64_t)po;
+        po += H[f].len[ci];
+        dmaxlen[d] = std::max<size_t>(dmaxlen[d], H[f].len[ci]);
+        dchunks[d].push_back(ch);
+        ci++;
+      }
+    }
+  }
+  Levels lv;
+  ModelBufs B;
+  uint8_t* payload = nullptr;
+  uint16_t* cdf16 = nullptr;
+  uint32_t *err = nullptr, *scan_tmp = nullptr;
+  int32_t* xyz_stage = nullptr;
+  int64_t maxN = 0;
+  for (int d = 0; d <= D; d++) maxN = std::max(maxN, fr.tot[d]);
+  std::vector<bool> wanted(D, true);
+  std::vector<bool> xdev(nf, false);
+  bool any_host_out = false;
+  for (int f : live) {
+    xdev[f] = is_device_ptr(xyz_out[f]);
+    if (!xdev[f]) any_host_out = true;
+  }
+  auto carve = [&](Arena& A) {
+    for (int d = 0; d <= D; d++) {
+      lv.key[d] = A.take<uint64_t>(fr.tot[d]);
+      lv.code[d] = A.take<uint8_t>(align_up(fr.tot[d], 4) + 4);
+      lv.cstart[d] = A.take<int32_t>(fr.tot[d] + 1);
+    }
+    payload = A.take<uint8_t>(paybytes);
+    cdf16 = A.take<uint16_t>((size_t)maxN * 256);
+    err = A.take<uint32_t>(4);
+    scan_tmp = A.take<uint32_t>((size_t)(maxN / 2048 + 2));
+    if (any_host_out) xyz_stage = A.take<int32_t>((size_t)fr.tot[D] * 3);
+    carve_model(A, m, fr, D - 1, wanted, B);
+  };
+  Arena meas;
+  carve(meas);
+  int s = reserve(c, 1, meas.off + 4096);
+  if (s) return s;
+  Arena A;
+  A.base = c->dev[1];
+  A.cap = c->cap[1];
+  carve(A);
+  size_t desc_off = 0;
+
+  // payloads and roots
+  for (int f : live) {
+    const size_t pl = H[f].total - H[f].hdr;
+    if (!pl) continue;
+    HIPC(hipMemcpyAsync(payload + payoff[f], bs[f] + H[f].hdr, pl,
+                        is_device_ptr(bs[f]) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  }
+  {
+    // V_0: one root per live frame; its key is the frame's position tag
+    std::vector<uint64_t> roots;
+    for (size_t i = 0; i < live.size(); i++) roots.push_back((uint64_t)i);
+    s = reserve_pinned(c, roots.size() * 8 + 256);
+    if (s) return s;
+    memcpy(c->pinned, roots.data(), roots.size() * 8);
+    HIPC(hipMemcpyAsync(lv.key[0], c->pinned, roots.size() * 8, hipMemcpyHostToDevice, st));
+    HIPC(hipStreamSynchronize(st));
+    desc_off = align_up(roots.size() * 8, 256);
+  }
+  HIPC(launch_fill_u32(err, 4, 0, st));
+
+  Batch b;
+  {
+    int8_t* f0 = B.F[0];
+    const int64_t bytes = fr.tot[0] * C;
+    b.launch("fill", 0, [=](const uint8_t*) { return launch_fill_u32((uint32_t*)f0, (bytes + 3) / 4, 0, st); });
+  }
+  if (B.kmap[0]) plan_kmap(b, lv, fr, B, 0, st);
+  for (int d = 0; d < D; d++) {
+    if (d >= 1 && d <= k0) plan_shallow(b, m, lv, fr, B, d, st);
+    if (d > k0) plan_deep(b, m, lv, fr, B, {d}, st);
+    PredSeg p;
+    memset(&p, 0, sizeof(p));
+    p.F = features_of(m, B, d);
+    p.fc1 = dlayer(m, d, m->first[d + 1] - m->first[d] - 2);
+    p.fc2 = dlayer(m, d, m->first[d + 1] - m->first[d] - 1);
+    p.rows = (int)fr.tot[d];
+    p.cdf16 = cdf16;
+    plan_predict(b, m, {p}, 1, st);
+    {
+      const size_t co = b.add(dchunks[d]);
+      const int nch = (int)dchunks[d].size();
+      const size_t ml = dmaxlen[d];
+      uint8_t* codes = lv.code[d];
+      b.launch("rc_decode", fr.tot[d], [=](const uint8_t* base) {
+        return launch_rc_decode_sized((const Chunk*)(base + co), nch, payload, cdf16, codes, err + 0, ml, st);
+      });
+    }
+    {
+      const uint64_t* pk = lv.key[d];
+      const uint8_t* codes = lv.code[d];
+      const int64_t np = fr.tot[d], nc = fr.tot[d + 1];
+      uint64_t* ck = lv.key[d + 1];
+      int32_t* cs = lv.cstart[d];
+      uint32_t* e1 = err + 1;
+      uint32_t* tmp = scan_tmp;
+      b.launch("expand", np, [=](const uint8_t*) { return launch_expand(pk, codes, np, ck, cs, nc, tmp, e1, st); });
+    }
+    if (d + 1 <= k0 && B.kmap[d + 1]) plan_kmap(b, lv, fr, B, d + 1, st);
+  }
+  s = run_batch(c, b, &desc_off);
+  if (s) return s;
+  // coordinates
+  uint32_t herr[4];
+  HIPC(hipMemcpyAsync(herr, err, 16, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  if (herr[0] | herr[1]) {
+    // a corrupt frame misaligns the shared arrays: report per frame by
+    // decoding the frames one at a time
+    if (live.size() == 1) {
+      status[live[0]] = LPCC_E_CORRUPT;
+      return LPCC_E_CORRUPT;
+    }
+    for (int f : live) {
+      int st1 = LPCC_OK;
+      int64_t n1 = 0;
+      decode_impl(c, m, 1, &bs[f], &len[f], &xyz_out[f], &cap[f], &n1, &st1);
+      status[f] = st1;
+    }
+    int ret = LPCC_OK;
+    for (int f = 0; f < nf; f++)
+      if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
+    return ret;
+  }
+  for (int f : live) {
+    const uint64_t* keys = lv.key[D] + fr.off[f][D];
+    int32_t* dst = xdev[f] ? xyz_out[f] : xyz_stage + 3 * fr.off[f][D];
+    HIPC(launch_keys_to_xyz(keys, fr.N[f][D], D, dst, st));
+    if (!xdev[f])
+      HIPC(hipMemcpyAsync(xyz_out[f], dst, (size_t)fr.N[f][D] * 12, hipMemcpyDeviceToHost, st));
+  }
+  HIPC(hipStreamSynchronize(st));
+  int ret = LPCC_OK;
+  for (int f = 0; f < nf; f++)
+    if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
+  return ret;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out) {
+  if (!blob || !out) return LPCC_E_INVAL;
+  *out = nullptr;
+  std::unique_ptr<lpcc_model> m(new lpcc_model());
+  m->device = device;
+  int s = parse_blob((const uint8_t*)blob, len, m.get());
+  if (s) return s;
+  if (hipSetDevice(device) != hipSuccess) return LPCC_E_DEVICE;
+  // one device block: per layer packed W, raw W, bias, zc; then the table
+  std::vector<LayerImage> im;
+  size_t bytes = 0;
+  for (auto& L : m->host) {
+    im.push_back(build_image(L));
+    bytes += align_up(im.back().packed.size(), 256) + align_up(L.W.size(), 256) +
+             align_up(im.back().bias.size() * 4, 256) + align_up(im.back().zc.size() * 4, 256);
+  }
+  bytes += 1024 + align_up(m->host.size() * sizeof(LayerDev), 256);
+  std::vector<uint8_t> host(bytes, 0);
+  if (hipMalloc(&m->d_mem, bytes) != hipSuccess) return LPCC_E_NOMEM;
+  uint8_t* dbase = (uint8_t*)m->d_mem;
+  size_t off = 0;
+  auto put = [&](const void* src, size_t n) -> uint8_t* {
+    uint8_t* d = dbase + off;
+    if (n) memcpy(host.data() + off, src, n);
+    off += align_up(n, 256);
+    return d;
+  };
+  std::vector<LayerDev> ld(m->host.size());
+  for (size_t i = 0; i < m->host.size(); i++) {
+    const HostLayer& L = m->host[i];
+    LayerDev& D = ld[i];
+    memset(&D, 0, sizeof(D));
+    D.Wp = (const int8_t*)put(im[i].packed.data(), im[i].packed.size());
+    D.Wr = (const int8_t*)put(L.W.data(), L.W.size());
+    D.bias = (const int32_t*)put(im[i].bias.data(), im[i].bias.size() * 4);
+    D.zc = im[i].zc.empty() ? nullptr : (const int32_t*)put(im[i].zc.data(), im[i].zc.size() * 4);
+    D.m_pos = L.m_pos;
+    D.m_neg = L.m_neg;
+    D.r = L.r;
+    D.z_out = L.z_out;
+    D.taps = L.taps;
+    D.cin = L.cin;
+    D.cout = L.cout;
+    D.ksteps = im[i].ksteps;
+    D.npad = im[i].npad;
+  }
+  int32_t lut[256];
+  softmax_table(lut);
+  m->d_lut = (int32_t*)put(lut, sizeof(lut));
+  m->d_layers = (LayerDev*)put(ld.data(), ld.size() * sizeof(LayerDev));
+  if (hipMemcpy(m->d_mem, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(m->d_mem);
+    return LPCC_E_DEVICE;
+  }
+  *out = m.release();
+  return LPCC_OK;
+}
+
+void lpcc_model_free(lpcc_model* m) {
+  if (!m) return;
+  if (m->d_mem) (void)hipFree(m->d_mem);
+  delete m;
+}
+
+int lpcc_model_info(const lpcc_model* m, int* C, int* D, int* n_deep, uint32_t* blob_id) {
+  if (!m) return LPCC_E_INVAL;
+  if (C) *C = m->C;
+  if (D) *D = m->D;
+  if (n_deep) *n_deep = m->n_deep;
+  if (blob_id) *blob_id = m->blob_id;
+  return LPCC_OK;
+}
+
+int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out) {
+  if (!out) return LPCC_E_INVAL;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return LPCC_E_DEVICE;
+  lpcc_ctx* c = new lpcc_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  *out = c;
+  return LPCC_OK;
+}
+
+void lpcc_ctx_free(lpcc_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (int i = 0; i < 3; i++)
+    if (c->dev[i]) (void)hipFree(c->dev[i]);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& e : c->ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  delete c;
+}
+
+const char* lpcc_last_error(const lpcc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int lpcc_peek_header(const uint8_t* bs, size_t len, int* D, int64_t* n_points) {
+  if (!bs) return LPCC_E_INVAL;
+  if (len < 16 || bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' || bs[4] != 1) return LPCC_E_CORRUPT;
+  if (bs[5] < 1 || bs[5] > kMaxD) return LPCC_E_CORRUPT;
+  if (D) *D = bs[5];
+  if (n_points) *n_points = rd32(bs + 12);
+  return LPCC_OK;
+}
+
+int lpcc_encode_batch(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n,
+                      int chunk_log2, uint8_t* const* out, const size_t* cap, size_t* out_len, int* status) {
+  if (!c || !m || nf <= 0 || !xyz || !n || !out || !cap || !out_len || !status) return LPCC_E_INVAL;
+  if (chunk_log2 < 4 || chunk_log2 > 14) return LPCC_E_INVAL;
+  for (int f = 0; f < nf; f++)
+    if (n[f] < 0 || (n[f] > 0 && !xyz[f]) || n[f] > (1ll << 30)) return LPCC_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return LPCC_E_DEVICE;
+  c->err.clear();
+  OutSpec os{out, cap, out_len};
+  return encode_impl(c, m, nf, xyz, n, chunk_log2, os, status, -1, nullptr, 0, nullptr);
+}
+
+int lpcc_encode_frame(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int chunk_log2,
+                      uint8_t* out, size_t cap, size_t* out_len) {
+  if (!out_len) return LPCC_E_INVAL;
+  int st = 0;
+  return lpcc_encode_batch(c, m, 1, &xyz, &n, chunk_log2, &out, &cap, out_len, &st);
+}
+
+int lpcc_level_probs(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int level, int32_t* cdf_out,
+                     int64_t cap, int64_t* n_nodes) {
+  if (!c || !m || !n_nodes || n < 0 || (n > 0 && !xyz)) return LPCC_E_INVAL;
+  if (level < 0 || level >= m->D) return LPCC_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return LPCC_E_DEVICE;
+  c->err.clear();
+  int st = 0;
+  size_t dummy = 0;
+  OutSpec os{nullptr, &dummy, &dummy};
+  *n_nodes = 0;
+  return encode_impl(c, m, 1, &xyz, &n, 10, os, &st, level, cdf_out, cap, n_nodes);
+}
+
+int lpcc_decode_batch(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* bs, const size_t* len,
+                      int32_t* const* xyz_out, const int64_t* cap, int64_t* n_out, int* status) {
+  if (!c || !m || nf <= 0 || !bs || !len || !xyz_out || !cap || !n_out || !status) return LPCC_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return LPCC_E_DEVICE;
+  c->err.clear();
+  return decode_impl(c, m, nf, bs, len, xyz_out, cap, n_out, status);
+}
+
+int lpcc_decode_frame(lpcc_ctx* c, const lpcc_model* m, const uint8_t* bs, size_t len, int32_t* xyz_out,
+                      int64_t cap, int64_t* n_out) {
+  if (!n_out) return LPCC_E_INVAL;
+  int st = 0;
+  return lpcc_decode_batch(c, m, 1, &bs, &len, &xyz_out, &cap, n_out, &st);
+}
+
+int lpcc_timing_enable(lpcc_ctx* c, const char* name) {
+  if (!c) return LPCC_E_INVAL;
+  c->time_family = name ? name : "";
+  c->ev_used = 0;
+  c->time_units = 0;
+  return LPCC_OK;
+}
+
+int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* units) {
+  if (!c) return LPCC_E_INVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LPCC_E_DEVICE;
+  double tot = 0;
+  for (size_t i = 0; i < c->ev_used; i++) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev[i].first, c->ev[i].second) != hipSuccess) return LPCC_E_DEVICE;
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)c->ev_used;
+  if (total_ms) *total_ms = tot;
+  if (units) *units = c->time_units;
+  c->ev_used = 0;
+  c->time_units = 0;
+  return LPCC_OK;
+}
+
+// Exponent table of the integer softmax as the library builds it (host only).
+int lpcc_softmax_table(int32_t* out) {
+  if (!out) return LPCC_E_INVAL;
+  softmax_table(out);
+  return LPCC_OK;
+}
+
+}  // extern "C"

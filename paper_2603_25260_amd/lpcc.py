@@ -1,0 +1,299 @@
+"""Python binding of the gfx950 C ABI (``include/lpcc.h``): argument marshalling only.
+
+Every step of encoding, decoding and probability evaluation runs in the HIP
+library ``liblpcc.so``; this module only passes pointers and sizes.  Inputs
+may be numpy arrays (host memory) or torch tensors (host or device); device
+tensors are passed by pointer, so the library reads them in place.  There is
+no fallback: if the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblpcc.so")
+
+OK, E_INVAL, E_CAPACITY, E_CORRUPT, E_MODEL, E_DEVICE, E_NOMEM = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {E_INVAL: "LPCC_E_INVAL", E_CAPACITY: "LPCC_E_CAPACITY", E_CORRUPT: "LPCC_E_CORRUPT",
+          E_MODEL: "LPCC_E_MODEL", E_DEVICE: "LPCC_E_DEVICE", E_NOMEM: "LPCC_E_NOMEM"}
+
+EXPORTS = ["lpcc_model_load", "lpcc_model_free", "lpcc_model_info", "lpcc_ctx_create", "lpcc_ctx_free",
+           "lpcc_last_error", "lpcc_encode_frame", "lpcc_decode_frame", "lpcc_level_probs", "lpcc_peek_header",
+           "lpcc_encode_batch", "lpcc_decode_batch", "lpcc_timing_enable", "lpcc_timing_read"]
+
+
+class LpccError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"{_NAMES.get(code, code)} {msg}".strip())
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load liblpcc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2603_25260_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i64, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int
+        L.lpcc_model_load.argtypes = [vp, sz, i32, ctypes.POINTER(vp)]
+        L.lpcc_model_free.argtypes = [vp]
+        L.lpcc_model_free.restype = None
+        L.lpcc_model_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      ctypes.POINTER(ctypes.c_uint32)]
+        L.lpcc_ctx_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+        L.lpcc_ctx_free.argtypes = [vp]
+        L.lpcc_ctx_free.restype = None
+        L.lpcc_last_error.argtypes = [vp]
+        L.lpcc_last_error.restype = ctypes.c_char_p
+        L.lpcc_encode_frame.argtypes = [vp, vp, vp, i64, i32, vp, sz, ctypes.POINTER(sz)]
+        L.lpcc_decode_frame.argtypes = [vp, vp, vp, sz, vp, i64, ctypes.POINTER(i64)]
+        L.lpcc_level_probs.argtypes = [vp, vp, vp, i64, i32, vp, i64, ctypes.POINTER(i64)]
+        L.lpcc_peek_header.argtypes = [vp, sz, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.lpcc_encode_batch.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp, vp, vp]
+        L.lpcc_decode_batch.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.lpcc_timing_enable.argtypes = [vp, ctypes.c_char_p]
+        L.lpcc_timing_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(i64)]
+        L.lpcc_softmax_table.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    """(pointer, keepalive) of a numpy array or torch tensor."""
+    if a is None:
+        return None, None
+    if isinstance(a, np.ndarray):
+        a = np.ascontiguousarray(a)
+        return a.ctypes.data, a
+    if hasattr(a, "data_ptr"):
+        if not a.is_contiguous():
+            a = a.contiguous()
+        return a.data_ptr(), a
+    if isinstance(a, (bytes, bytearray)):
+        b = np.frombuffer(a, np.uint8) if len(a) else np.zeros(1, np.uint8)
+        return b.ctypes.data, b
+    raise TypeError(type(a))
+
+
+def _is_torch(a):
+    return hasattr(a, "data_ptr") and hasattr(a, "device")
+
+
+def softmax_table() -> np.ndarray:
+    """The library's integer exponent table (host computation)."""
+    out = np.zeros(256, np.int32)
+    _check(lib().lpcc_softmax_table(out.ctypes.data))
+    return out
+
+
+def _check(st, ctx=None):
+    if st != OK:
+        msg = ""
+        if ctx is not None:
+            m = lib().lpcc_last_error(ctx)
+            msg = m.decode() if m else ""
+        raise LpccError(st, msg)
+
+
+class Model:
+    def __init__(self, blob: bytes, device: int = 0):
+        self._blob = np.frombuffer(blob, np.uint8).copy()
+        h = ctypes.c_void_p()
+        _check(lib().lpcc_model_load(self._blob.ctypes.data, len(blob), device, ctypes.byref(h)))
+        self.handle = h
+        C, D, nd, bid = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_uint32()
+        _check(lib().lpcc_model_info(h, ctypes.byref(C), ctypes.byref(D), ctypes.byref(nd), ctypes.byref(bid)))
+        self.C, self.D, self.n_deep, self.blob_id = C.value, D.value, nd.value, bid.value
+
+    def close(self):
+        if self.handle:
+            lib().lpcc_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """Device, stream and workspace.  ``stream`` is a hipStream_t handle (int)
+    or None; with torch, pass ``torch.cuda.current_stream().cuda_stream``."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().lpcc_ctx_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().lpcc_ctx_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- timing of one kernel family (HIP events on the context's stream)
+    def timing_enable(self, family: str):
+        _check(lib().lpcc_timing_enable(self.handle, family.encode()))
+
+    def timing_read(self):
+        n, ms, u = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().lpcc_timing_read(self.handle, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(u)), self.handle)
+        return n.value, ms.value, u.value
+
+
+def _n_points(xyz):
+    return int(xyz.shape[0]) if xyz is not None else 0
+
+
+def encode_frame(ctx: Context, model: Model, xyz, chunk_log2: int = 10, out=None):
+    """Bitstream of one frame.  With ``out`` (a uint8 buffer, host or device)
+    the stream is written there and its length returned; otherwise bytes."""
+    p, keep = _ptr(xyz)
+    n = _n_points(xyz)
+    L = lib()
+    if out is None:
+        cap = 64 + 4 * model.D + 4 * max(n, 1) + 16 * model.D
+        buf = np.zeros(cap, np.uint8)
+        ln = ctypes.c_size_t()
+        st = L.lpcc_encode_frame(ctx.handle, model.handle, p, n, chunk_log2, buf.ctypes.data, cap, ctypes.byref(ln))
+        if st == E_CAPACITY:
+            buf = np.zeros(ln.value, np.uint8)
+            st = L.lpcc_encode_frame(ctx.handle, model.handle, p, n, chunk_log2, buf.ctypes.data, ln.value,
+                                     ctypes.byref(ln))
+        _check(st, ctx.handle)
+        return buf[:ln.value].tobytes()
+    op, okeep = _ptr(out)
+    ln = ctypes.c_size_t()
+    cap = out.numel() if _is_torch(out) else out.size
+    _check(L.lpcc_encode_frame(ctx.handle, model.handle, p, n, chunk_log2, op, cap, ctypes.byref(ln)), ctx.handle)
+    return ln.value
+
+
+def decode_frame(ctx: Context, model: Model, bs, length=None, out=None):
+    """Voxel coordinates [N, 3] int32 in Morton order.  ``bs`` is bytes, a
+    numpy uint8 array or a torch uint8 tensor (host or device)."""
+    p, keep = _ptr(bs)
+    ln = length if length is not None else (bs.numel() if _is_torch(bs) else len(bs))
+    L = lib()
+    nout = ctypes.c_int64()
+    if out is None:
+        D, npts = ctypes.c_int(), ctypes.c_int64()
+        if _is_torch(bs) and bs.is_cuda:
+            hdr = bs[:16].cpu().numpy()
+            npts_v = int(hdr[12:16].view(np.uint32)[0])
+        else:
+            hb = np.frombuffer(bytes(bs[:16]) if not isinstance(bs, np.ndarray) else bs[:16].tobytes(), np.uint8)
+            st = L.lpcc_peek_header(hb.ctypes.data, 16, ctypes.byref(D), ctypes.byref(npts))
+            _check(st)
+            npts_v = npts.value
+        res = np.zeros((max(npts_v, 1), 3), np.int32)
+        _check(L.lpcc_decode_frame(ctx.handle, model.handle, p, ln, res.ctypes.data, res.shape[0],
+                                   ctypes.byref(nout)), ctx.handle)
+        return res[:nout.value]
+    op, okeep = _ptr(out)
+    cap = out.shape[0]
+    _check(L.lpcc_decode_frame(ctx.handle, model.handle, p, ln, op, cap, ctypes.byref(nout)), ctx.handle)
+    return nout.value
+
+
+def level_probs(ctx: Context, model: Model, xyz, level: int, out=None):
+    """CDF rows int32 [N_level, 256] of one depth (the encoder's model output)."""
+    p, keep = _ptr(xyz)
+    n = _n_points(xyz)
+    L = lib()
+    nn = ctypes.c_int64()
+    if out is None:
+        st = L.lpcc_level_probs(ctx.handle, model.handle, p, n, level, None, 0, ctypes.byref(nn))
+        if st not in (OK, E_CAPACITY):
+            _check(st, ctx.handle)
+        res = np.zeros((max(nn.value, 1), 256), np.int32)
+        _check(L.lpcc_level_probs(ctx.handle, model.handle, p, n, level, res.ctypes.data, res.shape[0],
+                                  ctypes.byref(nn)), ctx.handle)
+        return res[:nn.value]
+    op, okeep = _ptr(out)
+    _check(L.lpcc_level_probs(ctx.handle, model.handle, p, n, level, op, out.shape[0], ctypes.byref(nn)), ctx.handle)
+    return nn.value
+
+
+def encode_batch(ctx: Context, model: Model, frames, chunk_log2: int = 10, outs=None):
+    """Encode several frames in shared launches.  Returns a list of bytes
+    (or of lengths when device ``outs`` are given) and the status list."""
+    nf = len(frames)
+    ptrs, keep = [], []
+    for x in frames:
+        p, k = _ptr(x)
+        ptrs.append(p or 0)
+        keep.append(k)
+    n = np.array([_n_points(x) for x in frames], np.int64)
+    xp = (ctypes.c_void_p * nf)(*ptrs)
+    status = np.zeros(nf, np.int32)
+    lens = np.zeros(nf, np.uint64)
+    L = lib()
+    if outs is None:
+        caps = np.array([64 + 4 * model.D + 4 * max(int(v), 1) + 16 * model.D for v in n], np.uint64)
+        bufs = [np.zeros(int(c_), np.uint8) for c_ in caps]
+        op = (ctypes.c_void_p * nf)(*[b.ctypes.data for b in bufs])
+        st = L.lpcc_encode_batch(ctx.handle, model.handle, nf, xp, n.ctypes.data, chunk_log2, op, caps.ctypes.data,
+                                 lens.ctypes.data, status.ctypes.data)
+        if st not in (OK, E_CAPACITY):
+            _check(st, ctx.handle)
+        return [bufs[i][:int(lens[i])].tobytes() if status[i] == OK else None for i in range(nf)], status.tolist()
+    okeep = [_ptr(o) for o in outs]
+    op = (ctypes.c_void_p * nf)(*[k[0] for k in okeep])
+    caps = np.array([o.numel() if _is_torch(o) else o.size for o in outs], np.uint64)
+    st = L.lpcc_encode_batch(ctx.handle, model.handle, nf, xp, n.ctypes.data, chunk_log2, op, caps.ctypes.data,
+                             lens.ctypes.data, status.ctypes.data)
+    if st not in (OK, E_CAPACITY):
+        _check(st, ctx.handle)
+    return [int(v) for v in lens], status.tolist()
+
+
+def decode_batch(ctx: Context, model: Model, streams, lengths=None, outs=None):
+    nf = len(streams)
+    ptrs, keep = [], []
+    for x in streams:
+        p, k = _ptr(x)
+        ptrs.append(p)
+        keep.append(k)
+    if lengths is None:
+        lengths = [(s.numel() if _is_torch(s) else len(s)) for s in streams]
+    ln = np.array(lengths, np.uint64)
+    bp = (ctypes.c_void_p * nf)(*ptrs)
+    status = np.zeros(nf, np.int32)
+    nout = np.zeros(nf, np.int64)
+    L = lib()
+    if outs is None:
+        caps = []
+        for s_ in streams:
+            hb = (s_[:16].cpu().numpy() if _is_torch(s_) else np.frombuffer(bytes(s_[:16]), np.uint8))
+            caps.append(max(1, int(np.asarray(hb[12:16], np.uint8).view(np.uint32)[0])) if len(hb) >= 16 else 1)
+        res = [np.zeros((c_, 3), np.int32) for c_ in caps]
+        op = (ctypes.c_void_p * nf)(*[r.ctypes.data for r in res])
+        cp = np.array(caps, np.int64)
+        st = L.lpcc_decode_batch(ctx.handle, model.handle, nf, bp, ln.ctypes.data, op, cp.ctypes.data,
+                                 nout.ctypes.data, status.ctypes.data)
+        if st not in (OK, E_CAPACITY, E_CORRUPT, E_MODEL):
+            _check(st, ctx.handle)
+        return [res[i][:nout[i]] if status[i] == OK else None for i in range(nf)], status.tolist()
+    okeep = [_ptr(o) for o in outs]
+    op = (ctypes.c_void_p * nf)(*[k[0] for k in okeep])
+    cp = np.array([o.shape[0] for o in outs], np.int64)
+    st = L.lpcc_decode_batch(ctx.handle, model.handle, nf, bp, ln.ctypes.data, op, cp.ctypes.data, nout.ctypes.data,
+                             status.ctypes.data)
+    if st not in (OK, E_CAPACITY, E_CORRUPT, E_MODEL):
+        _check(st, ctx.handle)
+    return nout.tolist(), status.tolist()
