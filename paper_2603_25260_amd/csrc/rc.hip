@@ -55,29 +55,45 @@ struct RcEnc {
   }
 };
 
+constexpr int kEncBlock = 32;  // symbols staged per lane and block
+
 __global__ __launch_bounds__(64) void k_rc_encode(const Chunk* __restrict__ chunks, int nch,
                                                   const uint32_t* __restrict__ sf, uint8_t* __restrict__ scratch,
                                                   uint32_t* __restrict__ lens) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nch) return;
-  const Chunk ch = chunks[c];
+  // lane-private rows, padded to 33 words so that lanes reading the same
+  // column hit different banks
+  __shared__ uint32_t stg[64][kEncBlock + 1];
+  const int lane = threadIdx.x;
+  const int c = blockIdx.x * blockDim.x + lane;
+  const bool live = c < nch;
+  Chunk ch;
+  ch.node0 = 0;
+  ch.count = 0;
+  ch.scratch = 0;
+  if (live) ch = chunks[c];
   ByteSink o{(uint32_t*)(scratch + ch.scratch), 0u, 0u};
   RcEnc e{0ull, 0xFFFFFFFFu, 0u, 1u};
   const uint32_t* p = sf + ch.node0;
   const int n = ch.count;
-  // symbols in groups of 8, the next group loaded while the current is coded
-  uint32_t cur[8], nxt[8];
+  // every lane takes part in the staging rounds of the longest chunk
+  int nmax = n;
 #pragma unroll
-  for (int k = 0; k < 8; k++) cur[k] = k < n ? p[k] : 0u;
-  for (int base = 0; base < n; base += 8) {
+  for (int o2 = 32; o2 > 0; o2 >>= 1) nmax = max(nmax, __shfl_xor(nmax, o2));
+  for (int base = 0; base < nmax; base += kEncBlock) {
+    const int cnt = min(kEncBlock, max(n - base, 0));
+    uint32_t t[kEncBlock];
 #pragma unroll
-    for (int k = 0; k < 8; k++) nxt[k] = base + 8 + k < n ? p[base + 8 + k] : 0u;
+    for (int k = 0; k < kEncBlock; k++) t[k] = cnt > 0 ? p[base + min(k, cnt - 1)] : 0u;
 #pragma unroll
-    for (int k = 0; k < 8; k++)
-      if (base + k < n) e.encode(cur[k], o);
-#pragma unroll
-    for (int k = 0; k < 8; k++) cur[k] = nxt[k];
+    for (int k = 0; k < kEncBlock; k++) stg[lane][k] = t[k];
+    uint32_t nxt = stg[lane][0];
+    for (int k = 0; k < cnt; k++) {
+      const uint32_t v = nxt;
+      nxt = stg[lane][min(k + 1, kEncBlock - 1)];
+      e.encode(v, o);
+    }
   }
+  if (!live) return;
   for (int k = 0; k < 5; k++) e.shift_low(o);
   if (o.pos & 3u) o.out[o.pos >> 2] = o.word;
   lens[c] = o.pos;
@@ -108,87 +124,160 @@ hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scrat
 }
 
 // ---------------------------------------------------------------------------
-// Decoder: one wave per chunk.  The chunk's bytes are staged in LDS; lane l
-// holds cdf[4l .. 4l+3] of the current node (cdf[255] = 65536 implied).
-// The symbol is the number of entries with r * cdf[s] <= code, minus one,
-// counted with four ballots.  CDF rows are prefetched 8 nodes ahead.
+// Decoder: one wave per chunk.  The chunk's bytes are staged in LDS (zero
+// padded: bytes past the end read as 0) and consumed through a dword window.
+// CDF rows are copied into LDS kDecBlock at a time (unconditional loads, one
+// memory round trip per block); lane l reads cdf[4l .. 4l+3] of the current
+// node from there (cdf[255] = 65536 implied).  The symbol is the number of
+// entries with r * cdf[s] <= code, minus one, counted with four ballots
+// (r, cdf < 2^16, so 24-bit multiplies are exact).  Decoded codes are
+// collected one per lane and stored 64 at a time.
 // Chunk.pad_ carries the payload length in bytes, Chunk.scratch its offset.
 // ---------------------------------------------------------------------------
+constexpr int kDecBlock = 32;
+
 __device__ __forceinline__ uint2 ld_row(const uint16_t* cdf16, int64_t node, int lane) {
   return *(const uint2*)(cdf16 + node * 256 + 4 * lane);
 }
 
+// PW > 0: the payload (at most 64*PW dwords) sits in VGPRs, dword w in lane
+// w%64 of register w/64, read with v_readlane; PW = 0 reads it from LDS (long
+// chunks).  Every per-symbol step is written to keep the dependent chain of
+// scalar <-> vector transfers short: the four ballot masks are nested (the CDF
+// increases), so popcount(b0) - 1 is already the lane holding cdf[s]; the
+// renormalisation takes 0, 1 or 2 bytes from a 64-bit buffer without branches.
+template <int PW>
 __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chunks,
                                                   const uint8_t* __restrict__ payload,
                                                   const uint16_t* __restrict__ cdf16, uint8_t* __restrict__ codes,
-                                                  uint32_t* __restrict__ err) {
-  extern __shared__ uint8_t buf[];
+                                                  uint32_t* __restrict__ err, int lds_words) {
+  extern __shared__ uint32_t buf[];
+  __shared__ uint2 rows[kDecBlock][64];
   const Chunk ch = chunks[blockIdx.x];
   const int lane = threadIdx.x;
   const uint32_t len = (uint32_t)ch.pad_;
   const uint8_t* src = payload + ch.scratch;
-  for (uint32_t i = lane; i < len; i += 64) buf[i] = src[i];
-  __syncthreads();
-
-  uint32_t range = 0xFFFFFFFFu, code = 0, pos = 0;
-  for (int k = 0; k < 5; k++) {
-    code = (code << 8) | (pos < len ? (uint32_t)buf[pos] : 0u);
-    pos++;
+  for (int w = lane; w < lds_words; w += 64) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t b = 4u * (uint32_t)w + (uint32_t)k;
+      if (b < len) v |= (uint32_t)src[b] << (8 * k);
+    }
+    buf[w] = v;
   }
+  __syncthreads();
+  uint32_t pw[PW > 0 ? PW : 1];
+#pragma unroll
+  for (int j = 0; j < (PW > 0 ? PW : 1); j++) pw[j] = (PW > 0 && 64 * j + lane < lds_words) ? buf[64 * j + lane] : 0u;
+
+  // payload dwords in stream order; byte 0 of the stream is the low byte of dword 0
+  uint32_t cj = 0, creg = pw[0];
+  auto dword = [&](uint32_t w) -> uint32_t {
+    if (PW == 0) return (int)w < lds_words ? buf[w] : 0u;
+    if ((int)w >= 64 * PW) return 0u;
+    if ((w >> 6) != cj) {  // rare: next register of the payload
+      cj = w >> 6;
+#pragma unroll
+      for (int j = 0; j < (PW > 0 ? PW : 1); j++)
+        if ((uint32_t)j == cj) creg = pw[j];
+    }
+    return (uint32_t)__builtin_amdgcn_readlane((int)creg, (int)(w & 63u));
+  };
+  // bit buffer: the next `nb` stream bytes, first byte in bits 63..56
+  uint64_t bb = 0;
+  uint32_t nb = 0, wnext = 0;
+  auto refill = [&]() {  // append one dword (4 bytes, stream order)
+    const uint32_t d = dword(wnext++);
+    const uint32_t be = __builtin_bswap32(d);
+    bb |= (uint64_t)be << (32 - 8 * nb);
+    nb += 4;
+  };
+  refill();
+  refill();
+  // the first 5 bytes: the first is always 0 and shifts out of 32 bits
+  uint32_t code = (uint32_t)(bb >> 24);
+  bb <<= 40;
+  nb -= 5;
+  uint32_t range = 0xFFFFFFFFu;
+
   const int n = ch.count;
   const int64_t node0 = ch.node0;
-  uint2 cur[8], nxt[8];
-#pragma unroll
-  for (int k = 0; k < 8; k++) cur[k] = k < n ? ld_row(cdf16, node0 + k, lane) : make_uint2(0, 0);
   bool bad = false;
-  for (int base = 0; base < n && !bad; base += 8) {
+  uint32_t mine = 0;  // code of symbol i with i % 64 == lane
+  uint2 t[kDecBlock];
 #pragma unroll
-    for (int k = 0; k < 8; k++)
-      nxt[k] = base + 8 + k < n ? ld_row(cdf16, node0 + base + 8 + k, lane) : make_uint2(0, 0);
+  for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(k, max(n - 1, 0)), lane);
+  for (int base = 0; base < n && !bad; base += kDecBlock) {
+    const int cnt = min(kDecBlock, n - base);
+    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 8; k++) {
-      if (base + k >= n || bad) break;
-      const uint32_t c0 = cur[k].x & 0xFFFFu, c1 = cur[k].x >> 16, c2 = cur[k].y & 0xFFFFu;
-      const uint32_t c3 = lane == 63 ? 65536u : (cur[k].y >> 16);
+    for (int k = 0; k < kDecBlock; k++) rows[k][lane] = t[k];
+    __syncthreads();
+    {
+      const int nbk = base + kDecBlock;
+      const int last = max(n - 1, 0);
+#pragma unroll
+      for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(nbk + k, last), lane);
+    }
+    uint2 nxt = rows[0][lane];
+    for (int k = 0; k < cnt; k++) {
+      const int i = base + k;
+      const uint2 row = nxt;
+      nxt = rows[min(k + 1, kDecBlock - 1)][lane];
+      if (nb < 2) refill();
       const uint32_t r = range >> 16;
-      if ((uint64_t)code >= ((uint64_t)r << 16)) {
-        bad = true;
-        break;
-      }
-      const uint64_t b0 = __ballot(r * c0 <= code), b1 = __ballot(r * c1 <= code);
-      const uint64_t b2 = __ballot(r * c2 <= code);
-      const uint64_t b3 = __ballot(lane != 63 && r * c3 <= code);
+      // entries 4l..4l+3 of the CDF in lane l; slot 255 (lane 63, last) is not
+      // an entry (cdf[255] = 65536 is implied) and is masked out of b3
+      const uint64_t b0 = __ballot(__umul24(r, row.x & 0xFFFFu) <= code);
+      const uint64_t b1 = __ballot(__umul24(r, row.x >> 16) <= code);
+      const uint64_t b2 = __ballot(__umul24(r, row.y & 0xFFFFu) <= code);
+      const uint64_t b3 = __ballot(__umul24(r, row.y >> 16) <= code) & 0x7FFFFFFFFFFFFFFFull;
       const int s = __popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3) - 1;
-      const int es = s & 3, es1 = (s + 1) & 3;
-      const uint32_t vs = es == 0 ? c0 : (es == 1 ? c1 : (es == 2 ? c2 : c3));
-      const uint32_t vs1 = es1 == 0 ? c0 : (es1 == 1 ? c1 : (es1 == 2 ? c2 : c3));
-      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)vs, s >> 2);
-      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)vs1, (s + 1) >> 2);
-      if (hi <= lo) {  // not a valid CDF row: stop instead of looping
-        bad = true;
-        break;
-      }
+      const int L = s >> 2, e = s & 3;
+      // lane L's four entries as two packed pairs, and the first entry of lane L+1
+      const int Lc = s < 0 ? 0 : L;
+      const uint32_t X = (uint32_t)__builtin_amdgcn_readlane((int)row.x, Lc);
+      const uint32_t Y = (uint32_t)__builtin_amdgcn_readlane((int)row.y, Lc);
+      const uint32_t Z = (uint32_t)__builtin_amdgcn_readlane((int)row.x, min(Lc + 1, 63));
+      const uint32_t P = e < 2 ? X : Y;
+      const uint32_t lo = (P >> (16 * (e & 1))) & 0xFFFFu;
+      const uint32_t hi = e == 0 ? (X >> 16) : (e == 1 ? (Y & 0xFFFFu) : (e == 2 ? (s == 254 ? 65536u : (Y >> 16))
+                                                                                 : (Z & 0xFFFFu)));
       code -= r * lo;
       range = r * (hi - lo);
-      while (range < (1u << 24)) {
-        code = (code << 8) | (pos < len ? (uint32_t)buf[pos] : 0u);
-        pos++;
-        range <<= 8;
+      // a valid stream keeps code < range; anything else is corrupt
+      if ((code >= range) | (s < 0)) {
+        bad = true;
+        break;
       }
-      if (lane == 0) codes[node0 + base + k] = (uint8_t)(s + 1);
+      // renormalise: range >= 2^8 here, so take 0, 1 or 2 bytes
+      const uint32_t kb = (range < (1u << 24) ? 1u : 0u) + (range < (1u << 16) ? 1u : 0u);
+      const uint32_t sh = 8u * kb;
+      code = (uint32_t)(((uint64_t)code << sh) | ((bb >> 32) >> (32 - sh)));
+      bb <<= sh;
+      nb -= kb;
+      range <<= sh;
+      if ((i & 63) == lane) mine = (uint32_t)(s + 1);
+      if ((i & 63) == 63) codes[node0 + (i & ~63) + lane] = (uint8_t)mine;
     }
-#pragma unroll
-    for (int k = 0; k < 8; k++) cur[k] = nxt[k];
   }
+  const int done = n & ~63;
+  if (!bad && done < n && lane < n - done) codes[node0 + done + lane] = (uint8_t)mine;
   if (bad && lane == 0) atomicOr(err, ERR_CORRUPT);
 }
 
 hipError_t launch_rc_decode_sized(const Chunk* chunks, int nchunks, const uint8_t* payload, const uint16_t* cdf16,
                                   uint8_t* codes, uint32_t* err, size_t max_len, hipStream_t s) {
   if (nchunks <= 0) return hipSuccess;
-  size_t lds = (max_len + 15) & ~(size_t)15;
-  if (lds == 0) lds = 16;
-  hipLaunchKernelGGL(k_rc_decode, dim3(nchunks), dim3(64), lds, s, chunks, payload, cdf16, codes, err);
+  const int words = (int)((max_len + 3) / 4) + 4;
+  if (words <= 64 * 12) {
+    hipLaunchKernelGGL((k_rc_decode<12>), dim3(nchunks), dim3(64), (size_t)words * 4, s, chunks, payload, cdf16,
+                       codes, err, words);
+  } else {
+    hipLaunchKernelGGL((k_rc_decode<0>), dim3(nchunks), dim3(64), (size_t)words * 4, s, chunks, payload, cdf16,
+                       codes, err, words);
+  }
   return hipGetLastError();
 }
 

@@ -20,9 +20,25 @@ OK, E_INVAL, E_CAPACITY, E_CORRUPT, E_MODEL, E_DEVICE, E_NOMEM = 0, -1, -2, -3, 
 _NAMES = {E_INVAL: "LPCC_E_INVAL", E_CAPACITY: "LPCC_E_CAPACITY", E_CORRUPT: "LPCC_E_CORRUPT",
           E_MODEL: "LPCC_E_MODEL", E_DEVICE: "LPCC_E_DEVICE", E_NOMEM: "LPCC_E_NOMEM"}
 
-EXPORTS = ["lpcc_model_load", "lpcc_model_free", "lpcc_model_info", "lpcc_ctx_create", "lpcc_ctx_free",
-           "lpcc_last_error", "lpcc_encode_frame", "lpcc_decode_frame", "lpcc_level_probs", "lpcc_peek_header",
-           "lpcc_encode_batch", "lpcc_decode_batch", "lpcc_timing_enable", "lpcc_timing_read"]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("model", ctypes.c_int), ("inp", ctypes.c_void_p),
+                ("n_points", ctypes.c_int64), ("in_len", ctypes.c_size_t), ("out", ctypes.c_void_p),
+                ("out_cap", ctypes.c_size_t), ("t_arrival_ns", ctypes.c_int64), ("chunk_log2", ctypes.c_int)]
+
+
+class Done(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int), ("kind", ctypes.c_int),
+                ("out_len", ctypes.c_size_t), ("n_points", ctypes.c_int64), ("t_arrival_ns", ctypes.c_int64),
+                ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64), ("batch", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("mpts_per_s", ctypes.c_double), ("completed", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t),
+                ("bytes_budget", ctypes.c_size_t)]
 
 
 class LpccError(RuntimeError):
@@ -62,6 +78,13 @@ def lib():
         L.lpcc_timing_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64)]
         L.lpcc_softmax_table.argtypes = [vp]
+        L.lpcc_server_create.argtypes = [i32, vp, i32, i32, i32, sz, ctypes.POINTER(vp)]
+        L.lpcc_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
+        L.lpcc_server_poll.argtypes = [vp, ctypes.POINTER(Done), i32, ctypes.POINTER(i32), i32]
+        L.lpcc_server_drain.argtypes = [vp]
+        L.lpcc_server_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.lpcc_server_free.argtypes = [vp]
+        L.lpcc_server_free.restype = None
         _lib = L
     return _lib
 
@@ -297,3 +320,64 @@ def decode_batch(ctx: Context, model: Model, streams, lengths=None, outs=None):
     if st not in (OK, E_CAPACITY, E_CORRUPT, E_MODEL):
         _check(st, ctx.handle)
     return nout.tolist(), status.tolist()
+
+
+class Server:
+    """Continuous-batching server (see lpcc_server_* in include/lpcc.h).
+    Buffers handed to ``submit`` must stay alive until the job is polled."""
+
+    def __init__(self, models, device: int = 0, slots: int = 4, max_batch: int = 4, hbm_budget: int = 0):
+        self.models = list(models)
+        arr = (ctypes.c_void_p * len(self.models))(*[m.handle.value for m in self.models])
+        h = ctypes.c_void_p()
+        _check(lib().lpcc_server_create(device, arr, len(self.models), slots, max_batch, hbm_budget,
+                                        ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, kind: int, model: int, inp, out, *, n_points=0, in_len=0, chunk_log2=8, t_arrival_ns=0):
+        ip, ik = _ptr(inp)
+        op, ok = _ptr(out)
+        if kind == 0:
+            n_points = n_points or _n_points(inp)
+            cap = out.numel() if _is_torch(out) else out.size
+        else:
+            in_len = in_len or (inp.numel() if _is_torch(inp) else len(inp))
+            cap = out.shape[0]
+        j = Job(kind, model, ip, n_points, in_len, op, cap, t_arrival_ns, chunk_log2)
+        t = ctypes.c_uint64()
+        _check(lib().lpcc_server_submit(self.handle, ctypes.byref(j), ctypes.byref(t)))
+        self._keep[t.value] = (ik, ok)
+        return t.value
+
+    def poll(self, max_n: int = 256, wait_ms: int = 0):
+        buf = (Done * max_n)()
+        n = ctypes.c_int()
+        _check(lib().lpcc_server_poll(self.handle, buf, max_n, ctypes.byref(n), wait_ms))
+        out = []
+        for i in range(n.value):
+            d = buf[i]
+            self._keep.pop(d.ticket, None)
+            out.append({"ticket": d.ticket, "status": d.status, "kind": d.kind, "out_len": d.out_len,
+                        "n_points": d.n_points, "t_arrival_ns": d.t_arrival_ns, "t_start_ns": d.t_start_ns,
+                        "t_done_ns": d.t_done_ns, "batch": d.batch})
+        return out
+
+    def drain(self):
+        _check(lib().lpcc_server_drain(self.handle))
+
+    def stats(self):
+        st = Stats()
+        _check(lib().lpcc_server_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().lpcc_server_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
