@@ -153,6 +153,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
                                                   uint32_t* __restrict__ err, int lds_words) {
   extern __shared__ uint32_t buf[];
   __shared__ uint2 rows[kDecBlock][64];
+  __shared__ uint8_t cbuf[kDecBlock];  // decoded codes of the current block
   const Chunk ch = chunks[blockIdx.x];
   const int lane = threadIdx.x;
   const uint32_t len = (uint32_t)ch.pad_;
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   uint32_t nb = 0, wnext = 0;
   auto refill = [&]() {  // append one dword (4 bytes, stream order)
     const uint32_t d = dword(wnext++);
-    const uint32_t be = __builtin_bswap32(d);
+    const uint32_t be = (d << 24) | ((d & 0xFF00u) << 8) | ((d >> 8) & 0xFF00u) | (d >> 24);
     bb |= (uint64_t)be << (32 - 8 * nb);
     nb += 4;
   };
@@ -204,7 +205,6 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   const int n = ch.count;
   const int64_t node0 = ch.node0;
   bool bad = false;
-  uint32_t mine = 0;  // code of symbol i with i % 64 == lane
   uint2 t[kDecBlock];
 #pragma unroll
   for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(k, max(n - 1, 0)), lane);
@@ -226,6 +226,11 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
       const uint2 row = nxt;
       nxt = rows[min(k + 1, kDecBlock - 1)][lane];
       if (nb < 2) refill();
+      // the coder state is wave-uniform: keep it in scalar registers
+      code = (uint32_t)__builtin_amdgcn_readfirstlane((int)code);
+      range = (uint32_t)__builtin_amdgcn_readfirstlane((int)range);
+      bb = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(bb >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bb);
       const uint32_t r = range >> 16;
       // entries 4l..4l+3 of the CDF in lane l; slot 255 (lane 63, last) is not
       // an entry (cdf[255] = 65536 is implied) and is masked out of b3
@@ -240,10 +245,12 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
       const uint32_t X = (uint32_t)__builtin_amdgcn_readlane((int)row.x, Lc);
       const uint32_t Y = (uint32_t)__builtin_amdgcn_readlane((int)row.y, Lc);
       const uint32_t Z = (uint32_t)__builtin_amdgcn_readlane((int)row.x, min(Lc + 1, 63));
-      const uint32_t P = e < 2 ? X : Y;
-      const uint32_t lo = (P >> (16 * (e & 1))) & 0xFFFFu;
-      const uint32_t hi = e == 0 ? (X >> 16) : (e == 1 ? (Y & 0xFFFFu) : (e == 2 ? (s == 254 ? 65536u : (Y >> 16))
-                                                                                 : (Z & 0xFFFFu)));
+      // the four entries as one 64-bit word, and the same shifted by one entry
+      const uint64_t W = ((uint64_t)Y << 32) | X;
+      const uint64_t W1 = (W >> 16) | ((uint64_t)(Z & 0xFFFFu) << 48);
+      const uint32_t lo = (uint32_t)(W >> (16 * e)) & 0xFFFFu;
+      const uint32_t hn = (uint32_t)(W1 >> (16 * e)) & 0xFFFFu;
+      const uint32_t hi = s == 254 ? 65536u : hn;
       code -= r * lo;
       range = r * (hi - lo);
       // a valid stream keeps code < range; anything else is corrupt
@@ -252,18 +259,18 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
         break;
       }
       // renormalise: range >= 2^8 here, so take 0, 1 or 2 bytes
-      const uint32_t kb = (range < (1u << 24) ? 1u : 0u) + (range < (1u << 16) ? 1u : 0u);
-      const uint32_t sh = 8u * kb;
+      const uint32_t sh = range < (1u << 16) ? 16u : (range < (1u << 24) ? 8u : 0u);
+      const uint32_t kb = sh >> 3;
       code = (uint32_t)(((uint64_t)code << sh) | ((bb >> 32) >> (32 - sh)));
       bb <<= sh;
       nb -= kb;
       range <<= sh;
-      if ((i & 63) == lane) mine = (uint32_t)(s + 1);
-      if ((i & 63) == 63) codes[node0 + (i & ~63) + lane] = (uint8_t)mine;
+      cbuf[k] = (uint8_t)(s + 1);
+      (void)i;
     }
+    __syncthreads();
+    if (!bad && lane < cnt) codes[node0 + base + lane] = cbuf[lane];
   }
-  const int done = n & ~63;
-  if (!bad && done < n && lane < n - done) codes[node0 + done + lane] = (uint8_t)mine;
   if (bad && lane == 0) atomicOr(err, ERR_CORRUPT);
 }
 
