@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--frames", type=int, default=8)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (counter calibration under a profiler)")
     return ap.parse_args()
 
 
@@ -124,6 +126,12 @@ def main():
         "p99_frame_ms": round(float(np.percentile(frame_ms, 99)), 3),
     }
 
+    if args.calib_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
     # ---- kernel roofline: HIP events around every launch of one family
     fam_stats = {}
     for fam in ("predict", "conv", "rc_decode", "up", "rc_encode"):
@@ -135,15 +143,28 @@ def main():
     ctx.timing_enable("")
     res["kernel_ms_per_frame"] = {f: round(v[1] / len(frames), 4) for f, v in fam_stats.items()}
     launches, ms, units = fam_stats["predict"]
-    # predictor: per node 255 logits x (requant, table, division, scan) -- VALU bound;
-    # algorithmic operations per node counted in the design notes (VALU_OPS_PER_NODE)
-    ops = units * VALU_OPS_PER_NODE
+    # k_predict: per node, fc2 requantisation of 255 logits and the integer
+    # softmax / frequency table (15 integer operations per logit) plus the
+    # fc1 requantisation (6 per channel); the C^2 + 255 C MACs run on MFMA.
+    ops = units * (255 * 15 + 6 * C)
     achieved = ops / (ms / 1e3) / 1e12 if ms > 0 else 0.0
+    avg_ms = ms / max(launches, 1)
+    traffic = None
+    if _source_hash() == PROFILED_MODEL_HIP:
+        traffic = int(PREDICT_BYTES_PER_LAUNCH)
     res["roofline"] = {"kernel": "k_predict", "bound": "alu", "achieved": round(achieved, 3),
-                       "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (32-bit lane ops)",
-                       "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                       "launches": launches, "avg_launch_ms": round(ms / max(launches, 1), 4),
-                       "nodes": units}
+                       "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (32-bit integer lane ops)",
+                       "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                       "launches": launches, "avg_launch_ms": round(avg_ms, 4), "nodes": units,
+                       "ops_per_node": 255 * 15 + 6 * C}
+    # the longest kernel by time is the serial range decoder (latency bound:
+    # one chunk of 2^c symbols per wave, one symbol after the other)
+    dl, dms, dunits = fam_stats["rc_decode"]
+    res["range_decoder"] = {"kernel": "k_rc_decode", "ms_per_frame": round(dms / len(frames), 4),
+                            "symbols_per_chunk": 1 << cl, "launches": dl,
+                            "avg_launch_ms": round(dms / max(dl, 1), 4),
+                            "ns_per_serial_symbol": round(dms * 1e6 / max(dl, 1) / (1 << cl), 1),
+                            "cdf_row_gbs": round(dunits * 512 / (dms / 1e3) / 1e9, 1) if dms > 0 else None}
 
     # ---- bit-exactness of the timed streams against the oracle
     if not args.no_cpu:
@@ -198,7 +219,17 @@ def main():
     print(json.dumps(res))
 
 
-VALU_OPS_PER_NODE = 255 * 24  # refined from the kernel's instruction count in the design notes
+# HBM bytes per k_predict launch (read + write, scaled FETCH_SIZE / WRITE_SIZE
+# counters averaged over the launches of this workload) and the source they
+# were taken on; a changed kernel source reports traffic = null
+PROFILED_MODEL_HIP = "d4245a68180d1d72"
+PREDICT_BYTES_PER_LAUNCH = (60 * (12968.4 + 1364.8) + 840 * (1149.0 + 11817.2)) / 900 * 1024
+
+
+def _source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2603_25260_amd", "csrc", "model.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 if __name__ == "__main__":
     main()
