@@ -33,6 +33,7 @@ struct LayerDev {
   int32_t ksteps;       // Kpad / 64
   int32_t npad;
   int32_t pad_;
+  int64_t rnd;          // 2^(r-1) for r > 0, else 0 (half-up rounding term)
 };
 
 // Requantisation of an int32 accumulator (Eq. 14): sign-selected multiplier,
@@ -43,6 +44,15 @@ __device__ __forceinline__ int requant(int acc, int m_pos, int m_neg, int r, int
   if (r > 0) p = (p + (1ll << (r - 1))) >> r;
   p += z_out;
   return p < -128 ? -128 : (p > 127 ? 127 : (int)p);
+}
+
+// Same, with the layer's rounding term precomputed: one 64-bit multiply-add,
+// one arithmetic shift, zero point and clamp.
+__device__ __forceinline__ int requant_l(int acc, const LayerDev& L) {
+  const long long m = acc >= 0 ? L.m_pos : L.m_neg;
+  const long long p = ((long long)acc * m + L.rnd) >> L.r;
+  const long long q = p + L.z_out;
+  return q < -128 ? -128 : (q > 127 ? 127 : (int)q);
 }
 
 typedef int v4i __attribute__((ext_vector_type(4)));

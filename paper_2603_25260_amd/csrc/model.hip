@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
 #pragma unroll
     for (int q = 0; q < PER; q++) {
       int a = st[wave].v[er][ec + q] + L.bias[ec + q] + zsum[q];
-      int y = requant(a, L.m_pos, L.m_neg, L.r, L.z_out);
+      int y = requant_l(a, L);
       if (S.resid != nullptr) {
         y += res[q];
         y = y < -128 ? -128 : (y > 127 ? 127 : y);
@@ -173,6 +173,10 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
   constexpr int KS = (C + 8 + 63) / 64;
   constexpr int NBS = C / 16;          // column blocks per child slot
   constexpr int NBT = 8 * NBS;         // column blocks of the layer
+  // per wave: the accumulator tile of one slot, and the parents' codes / first children
+  __shared__ int32_t st[4][16][C + 1];
+  __shared__ uint32_t pc[4][16];
+  __shared__ int32_t ps[4][16];
 
   const Tile tl = tiles[blockIdx.x];
   const GemmSeg S = segs[tl.seg];
@@ -183,6 +187,10 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
   const int row = row0 + r;
   const bool rv = row < S.rows;
   const uint32_t code = rv ? S.code[row] : 0u;
+  if (g == 0) {
+    pc[wave][r] = code;
+    ps[wave][r] = rv ? S.cstart[row] : 0;
+  }
 
   v4i a[KS];
 #pragma unroll
@@ -201,20 +209,12 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
       a[s] = v4i{(int)w0, (int)w1, 0, 0};
     }
   }
-  // the parents whose outputs this lane holds: rows 4g+i of the tile
-  uint32_t pcode[4];
-  int pcs[4];
-#pragma unroll
-  for (int i = 0; i < 4; i++) {
-    const int p = row0 + 4 * g + i;
-    pcode[i] = p < S.rows ? S.code[p] : 0u;
-    pcs[i] = p < S.rows ? S.cstart[p] : 0;
-  }
   const v4i* Wp = (const v4i*)L.Wp;
 
   for (int o = 0; o < 8; o++) {
-    // skip a slot that no parent of this wave's tile occupies (wave-uniform)
-    if (__ballot((code >> o) & 1u) == 0ull) continue;
+    // rows of this wave's tile whose parent has child slot o (wave-uniform)
+    const uint32_t m = (uint32_t)(__ballot((code >> o) & 1u) & 0xFFFFull);
+    if (m == 0u) continue;
     v4i acc[NBS];
 #pragma unroll
     for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
@@ -226,17 +226,30 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
         acc[nb] = mfma16(a[s], b, acc[nb]);
       }
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      if (!((pcode[i] >> o) & 1u)) continue;
-      const int crow = pcs[i] + __popc(pcode[i] & ((1u << o) - 1u));
-      if (crow >= S.child_rows) continue;  // only for a corrupt stream
-      int8_t* dst = S.out + (int64_t)crow * S.out_stride;
+    for (int nb = 0; nb < NBS; nb++)
 #pragma unroll
-      for (int nb = 0; nb < NBS; nb++) {
-        const int col = 16 * nb + r;
-        dst[col] = (int8_t)requant(acc[nb][i] + L.bias[o * C + col], L.m_pos, L.m_neg, L.r, L.z_out);
-      }
+      for (int i = 0; i < 4; i++) st[wave][4 * g + i][16 * nb + r] = acc[nb][i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // only the occupied (row, slot) outputs: k rows x C columns over the wave
+    const int k = __popc(m);
+    for (int v = lane; v < k * C; v += 64) {
+      const int j = v / C, col = v - j * C;
+      // row of the j-th set bit of m
+      int pos = 0;
+#pragma unroll
+      for (int w = 8; w >= 1; w >>= 1)
+        if (__popc(m & ((1u << (pos + w)) - 1u)) <= j) pos += w;
+      const uint32_t pcode = pc[wave][pos];
+      const int crow = ps[wave][pos] + __popc(pcode & ((1u << o) - 1u));
+      if (crow >= S.child_rows) continue;  // only for a corrupt stream
+      const int y = requant_l(st[wave][pos][col] + L.bias[o * C + col], L);
+      S.out[(int64_t)crow * S.out_stride + col] = (int8_t)y;
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -266,7 +279,7 @@ __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, c
     int acc = L.bias[o];
     for (int b = 0; b < 8; b++)
       if ((code >> b) & 1u) acc += 127 * (int)L.Wr[b * C + o];
-    S.out[(int64_t)row * S.out_stride + o] = (int8_t)requant(acc, L.m_pos, L.m_neg, L.r, L.z_out);
+    S.out[(int64_t)row * S.out_stride + o] = (int8_t)requant_l(acc, L);
   }
 }
 
@@ -373,7 +386,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int col = 16 * nb + r;
-      hs[wave][4 * g + i][col] = (int8_t)requant(acc1[nb][i] + L1.bias[col], L1.m_pos, L1.m_neg, L1.r, L1.z_out);
+      hs[wave][4 * g + i][col] = (int8_t)requant_l(acc1[nb][i] + L1.bias[col], L1);
     }
   if (C < 64) {  // zero the K padding (columns C..63 of the 16 rows)
     for (int k = lane; k < 16 * (64 - C); k += 64) hs[wave][k / (64 - C)][C + k % (64 - C)] = 0;
@@ -391,7 +404,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
     const int bias = L2.bias[col];
 #pragma unroll
     for (int i = 0; i < 4; i++)
-      lg[i][b] = col < kNSym ? requant(acc[i] + bias, L2.m_pos, L2.m_neg, L2.r, L2.z_out) : -1000;
+      lg[i][b] = col < kNSym ? requant_l(acc[i] + bias, L2) : -1000;
   }
 
 #pragma unroll

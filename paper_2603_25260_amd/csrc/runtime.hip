@@ -1308,6 +1308,7 @@ int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out) 
     D.cout = L.cout;
     D.ksteps = im[i].ksteps;
     D.npad = im[i].npad;
+    D.rnd = L.r > 0 ? (1ll << (L.r - 1)) : 0;
   }
   int32_t lut[256];
   softmax_table(lut);

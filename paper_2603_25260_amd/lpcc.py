@@ -272,6 +272,13 @@ def encode_batch(ctx: Context, model: Model, frames, chunk_log2: int = 10, outs=
         op = (ctypes.c_void_p * nf)(*[b.ctypes.data for b in bufs])
         st = L.lpcc_encode_batch(ctx.handle, model.handle, nf, xp, n.ctypes.data, chunk_log2, op, caps.ctypes.data,
                                  lens.ctypes.data, status.ctypes.data)
+        if st == E_CAPACITY and all(v in (OK, E_CAPACITY) for v in status):
+            # the required sizes were written back: retry with exact buffers
+            caps = lens.copy()
+            bufs = [np.zeros(max(int(c_), 1), np.uint8) for c_ in caps]
+            op = (ctypes.c_void_p * nf)(*[b.ctypes.data for b in bufs])
+            st = L.lpcc_encode_batch(ctx.handle, model.handle, nf, xp, n.ctypes.data, chunk_log2, op,
+                                     caps.ctypes.data, lens.ctypes.data, status.ctypes.data)
         if st not in (OK, E_CAPACITY):
             _check(st, ctx.handle)
         return [bufs[i][:int(lens[i])].tobytes() if status[i] == OK else None for i in range(nf)], status.tolist()
