@@ -100,6 +100,39 @@ struct PredSeg {
   int32_t pad_;
 };
 
+// A launch with a single segment passes it, with its layers, by value in the
+// kernel arguments (no dependent descriptor loads before the first data
+// load); tile t then covers rows [64 t, 64 t + 64).  Otherwise `one` is 0 and
+// blocks read their tile and segment from the descriptor arrays.
+struct GemmArg {
+  GemmSeg seg;
+  LayerDev L;
+  int32_t one;
+  int32_t pad_;
+};
+struct PredArg {
+  PredSeg seg;
+  LayerDev fc1, fc2;
+  int32_t one;
+  int32_t pad_;
+};
+
+// Coordinate hash and 3x3x3 neighbour table of one depth j; several depths
+// share one launch, each starting at its own block.
+struct HashJob {
+  const uint64_t* keys;    // V_j (frame tag above bit 3j)
+  uint64_t* tkeys;
+  int32_t* tvals;
+  int32_t* kmap;           // [27][kstride]
+  int64_t n;
+  int64_t kstride;
+  uint64_t mask;           // table slots - 1
+  int32_t j;
+  int32_t blk_insert;      // first block of this depth in the insertion launch
+  int32_t blk_kmap;        // first block of this depth in the neighbour launch
+  int32_t pad_;
+};
+
 // Range-coder chunk: nodes [begin, begin+count) of one (frame, depth)
 struct Chunk {
   int64_t node0;           // index into the per-call node arrays
@@ -134,29 +167,41 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 
 hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
                               uint64_t mask, hipStream_t s);
+// All jobs' insertions, then all jobs' neighbour tables (two launches); the
+// block offsets in `jobs` must match the host copy used for the grid sizes.
+constexpr int kHashBlock = 256;
+hipError_t launch_hash_multi(const HashJob* jobs_dev, int njobs, int insert_blocks, int kmap_blocks,
+                             hipStream_t s);
 hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* tkeys, const int32_t* tvals,
                        uint64_t mask, int32_t* kmap, int64_t kstride, hipStream_t s);
 
 // GEMM families; `mode` selects the row source
 enum GemmMode { G_CONV = 0, G_DENSE = 1, G_DOWN = 2 };
 hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs_dev, const Tile* tiles_dev,
-                       int ntiles, hipStream_t s);
-hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, hipStream_t s);
-hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, hipStream_t s);
+                       int ntiles, const GemmArg& one, hipStream_t s);
+hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
+                     hipStream_t s);
+hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, const GemmArg& one,
+                      hipStream_t s);
 hipError_t launch_copy_rows(const int8_t* src, int64_t src_stride, int8_t* dst, int64_t dst_stride,
                             int64_t rows, int width, hipStream_t s);
 hipError_t launch_predict(int C, int mode, const PredSeg* segs_dev, const Tile* tiles_dev, int ntiles,
-                          const int32_t* lut, hipStream_t s);
+                          const int32_t* lut, const PredArg& one, hipStream_t s);
 
 hipError_t launch_rc_encode(const Chunk* chunks, int nchunks, const uint32_t* sf, uint8_t* scratch,
                             uint32_t* lens, hipStream_t s);
 hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scratch, const uint32_t* lens,
                           uint8_t* const* dst, hipStream_t s);
+// csum (optional): per chunk, the number of children its decoded codes announce
 hipError_t launch_rc_decode_sized(const Chunk* chunks, int nchunks, const uint8_t* payload, const uint16_t* cdf16,
-                                  uint8_t* codes, uint32_t* err, size_t max_len, hipStream_t s);
-hipError_t launch_expand(const uint64_t* pkeys, const uint8_t* codes, int64_t n, uint64_t* ckeys,
-                         int32_t* cstart, int64_t n_child_expected, uint32_t* scan_tmp, uint32_t* err,
-                         hipStream_t s);
+                                  uint8_t* codes, uint32_t* csum, uint32_t* err, size_t max_len, hipStream_t s);
+// Child expansion by decoded chunk (one block per chunk) from the chunks'
+// child counts: keys of V_{d+1}, first-child rows, and, when tkeys is not
+// null, insertion of the children into the hash table of depth d+1.
+hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t* pkeys, const uint8_t* codes,
+                                int64_t n, uint32_t* csum, uint64_t* ckeys, int32_t* cstart,
+                                int64_t n_child_expected, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
+                                uint32_t* err, hipStream_t s);
 hipError_t launch_keys_to_xyz(const uint64_t* keys, int64_t n, int D, int32_t* xyz, hipStream_t s);
 
 }  // namespace lpcc

@@ -52,8 +52,24 @@ __device__ __forceinline__ int src_row(const GemmSeg& S, int row, int tap) {
   return cr < S.child_rows ? cr : -1;  // out of range only for a corrupt stream
 }
 
+// The block's segment, layer and first row: from the kernel arguments for a
+// single-segment launch, else from the tile and segment arrays.
+__device__ __forceinline__ int pick_seg(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                        const GemmArg& A, GemmSeg& S, LayerDev& L) {
+  if (A.one) {
+    S = A.seg;
+    L = A.L;
+    return (int)blockIdx.x * 64;
+  }
+  const Tile tl = tiles[blockIdx.x];
+  S = segs[tl.seg];
+  L = *S.L;
+  return tl.row0;
+}
+
 template <int MODE, int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles) {
+__global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                              const GemmArg A) {
   constexpr int TAPS = Taps<MODE>::n;
   constexpr int K = TAPS * CIN;
   constexpr int KS = (K + 63) / 64;
@@ -61,14 +77,31 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
   static_assert(CIN % 16 == 0 && COUT % 16 == 0, "widths must be multiples of 16");
   __shared__ Stage<COUT> st[4];
 
-  const Tile tl = tiles[blockIdx.x];
-  const GemmSeg S = segs[tl.seg];
-  const LayerDev L = *S.L;
+  GemmSeg S;
+  LayerDev L;
+  const int tile_row0 = pick_seg(segs, tiles, A, S, L);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  const int row0 = tl.row0 + wave * 16;
+  const int row0 = tile_row0 + wave * 16;
   const int row = row0 + r;
   const bool rv = row < S.rows;
+
+  // epilogue operands first, so that their latency overlaps the main loop
+  constexpr int PER = COUT / 4;
+  const int er = lane >> 2;           // epilogue row within the wave's 16
+  const int ec = (lane & 3) * PER;    // first column
+  const int orow = row0 + er;
+  const bool ov = orow < S.rows;
+  int bia[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) bia[q] = L.bias[ec + q];
+  int8_t res[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) res[q] = 0;
+  if (S.resid != nullptr && ov) {
+#pragma unroll
+    for (int q = 0; q < PER; q++) res[q] = S.resid[(int64_t)orow * S.resid_stride + ec + q];
+  }
 
   v4i acc[NB];
 #pragma unroll
@@ -102,11 +135,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
 #pragma unroll
     for (int i = 0; i < 4; i++) st[wave].v[4 * g + i][16 * nb + r] = acc[nb][i];
   __syncthreads();
-  constexpr int PER = COUT / 4;
-  const int er = lane >> 2;           // epilogue row within the tile
-  const int ec = (lane & 3) * PER;    // first column
-  const int orow = row0 + er;
-  if (orow < S.rows) {
+  if (ov) {
     int zsum[PER];
 #pragma unroll
     for (int q = 0; q < PER; q++) zsum[q] = 0;
@@ -117,17 +146,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
         for (int q = 0; q < PER; q++) zsum[q] += L.zc[t * L.npad + ec + q];
       }
     }
-    int8_t res[PER];
-#pragma unroll
-    for (int q = 0; q < PER; q++) res[q] = 0;
-    if (S.resid != nullptr) {
-#pragma unroll
-      for (int q = 0; q < PER; q++) res[q] = S.resid[(int64_t)orow * S.resid_stride + ec + q];
-    }
     int8_t outv[PER];
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-      int a = st[wave].v[er][ec + q] + L.bias[ec + q] + zsum[q];
+      int a = st[wave].v[er][ec + q] + bia[q] + zsum[q];
       int y = requant_l(a, L);
       if (S.resid != nullptr) {
         y += res[q];
@@ -143,10 +165,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
 
 template <int MODE>
 static hipError_t launch_gemm_mode(int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
-                                   hipStream_t s) {
+                                   const GemmArg& A, hipStream_t s) {
 #define LPCC_G(CI, CO)                                                                          \
   if (cin == CI && cout == CO) {                                                                \
-    hipLaunchKernelGGL((k_gemm<MODE, CI, CO>), dim3(ntiles), dim3(256), 0, s, segs, tiles);     \
+    hipLaunchKernelGGL((k_gemm<MODE, CI, CO>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);  \
     return hipGetLastError();                                                                   \
   }
   LPCC_G(16, 16) LPCC_G(32, 16) LPCC_G(32, 32) LPCC_G(64, 32) LPCC_G(64, 64) LPCC_G(128, 64)
@@ -155,11 +177,11 @@ static hipError_t launch_gemm_mode(int cin, int cout, const GemmSeg* segs, const
 }
 
 hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
-                       hipStream_t s) {
+                       const GemmArg& A, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (mode == G_CONV) return launch_gemm_mode<G_CONV>(cin, cout, segs, tiles, ntiles, s);
-  if (mode == G_DENSE) return launch_gemm_mode<G_DENSE>(cin, cout, segs, tiles, ntiles, s);
-  if (mode == G_DOWN) return launch_gemm_mode<G_DOWN>(cin, cout, segs, tiles, ntiles, s);
+  if (mode == G_CONV) return launch_gemm_mode<G_CONV>(cin, cout, segs, tiles, ntiles, A, s);
+  if (mode == G_DENSE) return launch_gemm_mode<G_DENSE>(cin, cout, segs, tiles, ntiles, A, s);
+  if (mode == G_DOWN) return launch_gemm_mode<G_DOWN>(cin, cout, segs, tiles, ntiles, A, s);
   return hipErrorInvalidValue;
 }
 
@@ -169,7 +191,8 @@ hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs, const T
 // child row = cstart[p] + rank of o among the set bits.
 // ---------------------------------------------------------------------------
 template <int C>
-__global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles) {
+__global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                            const GemmArg A) {
   constexpr int KS = (C + 8 + 63) / 64;
   constexpr int NBS = C / 16;          // column blocks per child slot
   constexpr int NBT = 8 * NBS;         // column blocks of the layer
@@ -178,15 +201,21 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
   __shared__ uint32_t pc[4][16];
   __shared__ int32_t ps[4][16];
 
-  const Tile tl = tiles[blockIdx.x];
-  const GemmSeg S = segs[tl.seg];
-  const LayerDev L = *S.L;
+  GemmSeg S;
+  LayerDev L;
+  const int tile_row0 = pick_seg(segs, tiles, A, S, L);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  const int row0 = tl.row0 + wave * 16;
+  const int row0 = tile_row0 + wave * 16;
   const int row = row0 + r;
   const bool rv = row < S.rows;
   const uint32_t code = rv ? S.code[row] : 0u;
+  // the output loop below gives every lane the fixed column lane % C
+  static_assert(64 % C == 0, "C must divide the wave width");
+  const int ocol = lane % C;
+  int bia[8];
+#pragma unroll
+  for (int o = 0; o < 8; o++) bia[o] = L.bias[o * C + ocol];
   if (g == 0) {
     pc[wave][r] = code;
     ps[wave][r] = rv ? S.cstart[row] : 0;
@@ -210,8 +239,22 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
     }
   }
   const v4i* Wp = (const v4i*)L.Wp;
+  // weights of slot o+1 are in flight while slot o is computed
+  v4i wb[2][KS][NBS];
+#pragma unroll
+  for (int s = 0; s < KS; s++)
+#pragma unroll
+    for (int nb = 0; nb < NBS; nb++) wb[0][s][nb] = Wp[((int64_t)s * NBT + nb) * 64 + lane];
 
+#pragma unroll
   for (int o = 0; o < 8; o++) {
+    if (o + 1 < 8) {
+#pragma unroll
+      for (int s = 0; s < KS; s++)
+#pragma unroll
+        for (int nb = 0; nb < NBS; nb++)
+          wb[(o + 1) & 1][s][nb] = Wp[((int64_t)s * NBT + (o + 1) * NBS + nb) * 64 + lane];
+    }
     // rows of this wave's tile whose parent has child slot o (wave-uniform)
     const uint32_t m = (uint32_t)(__ballot((code >> o) & 1u) & 0xFFFFull);
     if (m == 0u) continue;
@@ -221,10 +264,7 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
 #pragma unroll
     for (int s = 0; s < KS; s++)
 #pragma unroll
-      for (int nb = 0; nb < NBS; nb++) {
-        v4i b = Wp[((int64_t)s * NBT + o * NBS + nb) * 64 + lane];
-        acc[nb] = mfma16(a[s], b, acc[nb]);
-      }
+      for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(a[s], wb[o & 1][s][nb], acc[nb]);
 #pragma unroll
     for (int nb = 0; nb < NBS; nb++)
 #pragma unroll
@@ -244,7 +284,7 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
       const uint32_t pcode = pc[wave][pos];
       const int crow = ps[wave][pos] + __popc(pcode & ((1u << o) - 1u));
       if (crow >= S.child_rows) continue;  // only for a corrupt stream
-      const int y = requant_l(st[wave][pos][col] + L.bias[o * C + col], L);
+      const int y = requant_l(st[wave][pos][col] + bia[o], L);
       S.out[(int64_t)crow * S.out_stride + col] = (int8_t)y;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -253,11 +293,11 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
   }
 }
 
-hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, hipStream_t s) {
+hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (C == 16) hipLaunchKernelGGL((k_up<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles);
-  else if (C == 32) hipLaunchKernelGGL((k_up<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles);
-  else if (C == 64) hipLaunchKernelGGL((k_up<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles);
+  if (C == 16) hipLaunchKernelGGL((k_up<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else if (C == 32) hipLaunchKernelGGL((k_up<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else if (C == 64) hipLaunchKernelGGL((k_up<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -268,12 +308,12 @@ hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, 
 // One thread per output element.  Tiles cover 64 rows.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
-                                             int C) {
-  const Tile tl = tiles[blockIdx.x];
-  const GemmSeg S = segs[tl.seg];
-  const LayerDev L = *S.L;
+                                             int C, const GemmArg A) {
+  GemmSeg S;
+  LayerDev L;
+  const int tile_row0 = pick_seg(segs, tiles, A, S, L);
   for (int e = threadIdx.x; e < 64 * C; e += blockDim.x) {
-    const int row = tl.row0 + e / C, o = e % C;
+    const int row = tile_row0 + e / C, o = e % C;
     if (row >= S.rows) continue;
     const uint32_t code = S.code[row];
     int acc = L.bias[o];
@@ -283,9 +323,9 @@ __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, c
   }
 }
 
-hipError_t launch_emb(const GemmSeg* segs, const Tile* tiles, int ntiles, int C, hipStream_t s) {
+hipError_t launch_emb(const GemmSeg* segs, const Tile* tiles, int ntiles, int C, const GemmArg& A, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_emb, dim3(ntiles), dim3(256), 0, s, segs, tiles, C);
+  hipLaunchKernelGGL(k_emb, dim3(ntiles), dim3(256), 0, s, segs, tiles, C, A);
   return hipGetLastError();
 }
 
@@ -356,19 +396,30 @@ enum { P_ENCODE = 0, P_CDF16 = 1, P_CDF32 = 2 };
 
 template <int C, int MODE>
 __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ segs, const Tile* __restrict__ tiles,
-                                                 const int32_t* __restrict__ lut_g) {
+                                                 const int32_t* __restrict__ lut_g, const PredArg A) {
   __shared__ int32_t lut[256];
   __shared__ int8_t hs[4][16][64];
-  __shared__ uint16_t fs[MODE == P_ENCODE ? 1 : 4][16][256];
+  __shared__ __attribute__((aligned(16))) uint16_t fs[MODE == P_ENCODE ? 1 : 4][16][256];
   lut[threadIdx.x] = lut_g[threadIdx.x];
 
-  const Tile tl = tiles[blockIdx.x];
-  const PredSeg S = segs[tl.seg];
-  const LayerDev L1 = *S.fc1;
-  const LayerDev L2 = *S.fc2;
+  PredSeg S;
+  LayerDev L1, L2;
+  int tile_row0;
+  if (A.one) {
+    S = A.seg;
+    L1 = A.fc1;
+    L2 = A.fc2;
+    tile_row0 = (int)blockIdx.x * 64;
+  } else {
+    const Tile tl = tiles[blockIdx.x];
+    S = segs[tl.seg];
+    L1 = *S.fc1;
+    L2 = *S.fc2;
+    tile_row0 = tl.row0;
+  }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  const int row0 = tl.row0 + wave * 16;
+  const int row0 = tile_row0 + wave * 16;
   const int row = row0 + r;
   const bool rv = row < S.rows;
 
@@ -407,38 +458,53 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
       lg[i][b] = col < kNSym ? requant_l(acc[i] + bias, L2) : -1000;
   }
 
+  // per row: max, lowest argmax, E_i = LUT[M - l_i] (replacing the logits), S
+  int arg[4];
+  uint32_t Sr[4];
 #pragma unroll
   for (int i = 0; i < 4; i++) {
-    const int nrow = row0 + 4 * g + i;
     int M = -1000;
 #pragma unroll
     for (int b = 0; b < 16; b++) M = max(M, lg[i][b]);
     M = red16_max(M);
-    int arg = 1000;
+    int am = 1000;
 #pragma unroll
     for (int b = 0; b < 16; b++)
-      if (lg[i][b] == M) arg = min(arg, 16 * b + r);
-    arg = red16_min(arg);
-    int E[16];
-    int Ssum = 0;
+      if (lg[i][b] == M) am = min(am, 16 * b + r);
+    arg[i] = red16_min(am);
+    int sum = 0;
 #pragma unroll
     for (int b = 0; b < 16; b++) {
-      E[b] = (16 * b + r < kNSym) ? lut[M - lg[i][b]] : 0;
-      Ssum += E[b];
+      const int e = (16 * b + r < kNSym) ? lut[M - lg[i][b]] : 0;
+      lg[i][b] = e;
+      sum += e;
     }
-    const uint32_t S_ = (uint32_t)red16_sum(Ssum);
-    const uint32_t inv = recip32(S_);
+    Sr[i] = (uint32_t)red16_sum(sum);
+  }
+  // one reciprocal per lane (lane r computes row r % 4 of its group), shared
+  // within the group of 16 lanes
+  const int ri = r & 3;
+  const uint32_t Ssel = ri == 0 ? Sr[0] : (ri == 1 ? Sr[1] : (ri == 2 ? Sr[2] : Sr[3]));
+  const uint32_t invsel = recip32(Ssel);
+  uint32_t inv[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) inv[i] = (uint32_t)__shfl((int)invsel, (lane & 48) | i);
+
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const int nrow = row0 + 4 * g + i;
+    const uint32_t S_ = Sr[i];
     int f[16];
     int fsum = 0;
 #pragma unroll
     for (int b = 0; b < 16; b++) {
-      f[b] = (16 * b + r < kNSym) ? 1 + (int)divS((uint32_t)E[b] * 65281u, S_, inv) : 0;
+      f[b] = (16 * b + r < kNSym) ? 1 + (int)divS((uint32_t)lg[i][b] * 65281u, S_, inv[i]) : 0;
       fsum += f[b];
     }
     const int R = 65536 - red16_sum(fsum);
 #pragma unroll
     for (int b = 0; b < 16; b++)
-      if (16 * b + r == arg) f[b] += R;
+      if (16 * b + r == arg[i]) f[b] += R;
 
     if (MODE == P_ENCODE) {
       const int sym = nrow < S.rows ? (int)S.code[nrow] - 1 : 0;
@@ -459,51 +525,55 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
     }
   }
   if (MODE != P_ENCODE) {
-    __syncthreads();
-    // lane -> row lane/4, entries [64q, 64q+64) with q = lane%4: serial
-    // exclusive prefix, then the offsets of the preceding quarters
-    const int prow = lane >> 2, q = lane & 3;
-    uint16_t* fr = &fs[wave][prow][64 * q];
-    uint32_t acc = 0;
-    for (int e = 0; e < 64; e++) {
-      const uint32_t v = fr[e];
-      fr[e] = (uint16_t)acc;   // partial sums < 2^16 until the last entry
-      acc += v;
-    }
-    uint32_t incl = acc;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // four passes of four rows; lane (q = lane/16, r) owns the 16 consecutive
+    // entries 16r..16r+15 of row 4p+q: serial prefix in registers, exclusive
+    // scan of the lane totals across the 16 lanes of the row
 #pragma unroll
-    for (int o = 1; o < 4; o <<= 1) {
-      const uint32_t v = __shfl_up(incl, o, 4);
-      if (q >= o) incl += v;
-    }
-    const uint32_t off = incl - acc;
-    const int nrow = row0 + prow;
-    if (nrow < S.rows) {
-      if (MODE == P_CDF16) {
-        uint16_t* dst = S.cdf16 + (int64_t)nrow * 256 + 64 * q;
+    for (int p = 0; p < 4; p++) {
+      const int prow = 4 * p + g;
+      const uint4* src = (const uint4*)&fs[wave][prow][16 * r];
+      const uint4 u0 = src[0], u1 = src[1];
+      const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      uint32_t ex[16];  // exclusive prefix within the lane
+      uint32_t run = 0;
 #pragma unroll
-        for (int e = 0; e < 64; e += 8) {
-          uint32_t w[4];
+      for (int k = 0; k < 8; k++) {
+        ex[2 * k] = run;
+        run += w[k] & 0xFFFFu;
+        ex[2 * k + 1] = run;
+        run += w[k] >> 16;
+      }
+      uint32_t incl = run;
 #pragma unroll
-          for (int k = 0; k < 4; k++) {
-            const int c0 = 64 * q + e + 2 * k;
-            const uint32_t lo = c0 < kNSym ? off + fr[e + 2 * k] : 0u;
-            const uint32_t hi = c0 + 1 < kNSym ? off + fr[e + 2 * k + 1] : 0u;
-            w[k] = (lo & 0xFFFFu) | (hi << 16);
+      for (int o = 1; o < 16; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 16);
+        if (r >= o) incl += v;
+      }
+      const uint32_t off = incl - run;
+      const int nrow = row0 + prow;
+      if (nrow < S.rows) {
+        if (MODE == P_CDF16) {
+          // entry 255 is not a symbol boundary: stored as 0
+          uint32_t o2[8];
+#pragma unroll
+          for (int k = 0; k < 8; k++) {
+            const uint32_t lo = off + ex[2 * k];
+            const uint32_t hi = (r == 15 && k == 7) ? 0u : off + ex[2 * k + 1];
+            o2[k] = (lo & 0xFFFFu) | (hi << 16);
           }
-          *(v4i*)(dst + e) = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-        }
-      } else {
-        int32_t* dst = S.cdf32 + (int64_t)nrow * 256 + 64 * q;
+          uint4* dst = (uint4*)(S.cdf16 + (int64_t)nrow * 256 + 16 * r);
+          dst[0] = make_uint4(o2[0], o2[1], o2[2], o2[3]);
+          dst[1] = make_uint4(o2[4], o2[5], o2[6], o2[7]);
+        } else {
+          uint32_t o4[16];
 #pragma unroll
-        for (int e = 0; e < 64; e += 4) {
-          int w[4];
+          for (int k = 0; k < 16; k++) o4[k] = (r == 15 && k == 15) ? 65536u : off + ex[k];
+          uint4* dst = (uint4*)(S.cdf32 + (int64_t)nrow * 256 + 16 * r);
 #pragma unroll
-          for (int k = 0; k < 4; k++) {
-            const int c0 = 64 * q + e + k;
-            w[k] = c0 < kNSym ? (int)(off + fr[e + k]) : 65536;
-          }
-          *(v4i*)(dst + e) = v4i{w[0], w[1], w[2], w[3]};
+          for (int k = 0; k < 4; k++) dst[k] = make_uint4(o4[4 * k], o4[4 * k + 1], o4[4 * k + 2], o4[4 * k + 3]);
         }
       }
     }
@@ -511,12 +581,12 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
 }
 
 hipError_t launch_predict(int C, int mode, const PredSeg* segs, const Tile* tiles, int ntiles, const int32_t* lut,
-                          hipStream_t s) {
+                          const PredArg& A, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-#define LPCC_P(CC, MM)                                                                            \
-  if (C == CC && mode == MM) {                                                                    \
-    hipLaunchKernelGGL((k_predict<CC, MM>), dim3(ntiles), dim3(256), 0, s, segs, tiles, lut);     \
-    return hipGetLastError();                                                                     \
+#define LPCC_P(CC, MM)                                                                               \
+  if (C == CC && mode == MM) {                                                                       \
+    hipLaunchKernelGGL((k_predict<CC, MM>), dim3(ntiles), dim3(256), 0, s, segs, tiles, lut, A);     \
+    return hipGetLastError();                                                                        \
   }
   LPCC_P(16, 0) LPCC_P(16, 1) LPCC_P(16, 2)
   LPCC_P(32, 0) LPCC_P(32, 1) LPCC_P(32, 2)

@@ -236,21 +236,24 @@ __device__ __forceinline__ uint64_t hmix(uint64_t k) {
   return k;
 }
 
-__global__ void k_hash_insert(const uint64_t* __restrict__ keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
-                              uint64_t mask) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint64_t k = keys[i];
+__device__ __forceinline__ void hash_put(uint64_t k, int32_t row, uint64_t* tkeys, int32_t* tvals, uint64_t mask) {
   uint64_t slot = hmix(k) & mask;
   for (uint64_t probe = 0; probe <= mask; probe++) {
     unsigned long long prev = atomicCAS((unsigned long long*)&tkeys[slot], (unsigned long long)kEmpty,
                                         (unsigned long long)k);
     if (prev == kEmpty || prev == k) {
-      tvals[slot] = (int32_t)i;
+      tvals[slot] = row;
       return;
     }
     slot = (slot + 1) & mask;
   }
+}
+
+__global__ void k_hash_insert(const uint64_t* __restrict__ keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
+                              uint64_t mask) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  hash_put(keys[i], (int32_t)i, tkeys, tvals, mask);
 }
 
 hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
@@ -263,11 +266,9 @@ hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, 
 
 // One lane per (node, tap): neighbour (dx,dy,dz) of tap 9(dx+1)+3(dy+1)+(dz+1);
 // kmap[tap * kstride + node] = its row, or -1 when empty / outside [0,2^j)^3.
-__global__ void k_kmap(const uint64_t* __restrict__ keys, int64_t n, int j, const uint64_t* __restrict__ tkeys,
-                       const int32_t* __restrict__ tvals, uint64_t mask, int32_t* __restrict__ kmap,
-                       int64_t kstride) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n * 27) return;
+__device__ __forceinline__ void kmap_one(const uint64_t* __restrict__ keys, int64_t gid, int j,
+                                         const uint64_t* __restrict__ tkeys, const int32_t* __restrict__ tvals,
+                                         uint64_t mask, int32_t* __restrict__ kmap, int64_t kstride) {
   int64_t i = gid / 27;
   int t = (int)(gid - i * 27);
   uint64_t key = keys[i];
@@ -291,6 +292,47 @@ __global__ void k_kmap(const uint64_t* __restrict__ keys, int64_t n, int j, cons
   kmap[(int64_t)t * kstride + i] = r;
 }
 
+__global__ void k_kmap(const uint64_t* __restrict__ keys, int64_t n, int j, const uint64_t* __restrict__ tkeys,
+                       const int32_t* __restrict__ tvals, uint64_t mask, int32_t* __restrict__ kmap,
+                       int64_t kstride) {
+  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n * 27) return;
+  kmap_one(keys, gid, j, tkeys, tvals, mask, kmap, kstride);
+}
+
+// Several depths per launch: block b belongs to the last job whose first
+// block is <= b (jobs are in increasing block order).
+__device__ __forceinline__ int job_of(const HashJob* __restrict__ jobs, int njobs, bool kmap_blocks) {
+  int q = 0;
+  for (int k = 1; k < njobs; k++) {
+    const int b0 = kmap_blocks ? jobs[k].blk_kmap : jobs[k].blk_insert;
+    if ((int)blockIdx.x >= b0) q = k;
+  }
+  return q;
+}
+
+__global__ __launch_bounds__(kHashBlock) void k_hash_insert_multi(const HashJob* __restrict__ jobs, int njobs) {
+  const HashJob J = jobs[job_of(jobs, njobs, false)];
+  const int64_t i = (int64_t)((int)blockIdx.x - J.blk_insert) * kHashBlock + threadIdx.x;
+  if (i >= J.n) return;
+  hash_put(J.keys[i], (int32_t)i, J.tkeys, J.tvals, J.mask);
+}
+
+__global__ __launch_bounds__(kHashBlock) void k_kmap_multi(const HashJob* __restrict__ jobs, int njobs) {
+  const HashJob J = jobs[job_of(jobs, njobs, true)];
+  const int64_t gid = (int64_t)((int)blockIdx.x - J.blk_kmap) * kHashBlock + threadIdx.x;
+  if (gid >= J.n * 27) return;
+  kmap_one(J.keys, gid, J.j, J.tkeys, J.tvals, J.mask, J.kmap, J.kstride);
+}
+
+hipError_t launch_hash_multi(const HashJob* jobs_dev, int njobs, int insert_blocks, int kmap_blocks,
+                             hipStream_t s) {
+  if (njobs <= 0 || insert_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_insert_multi, dim3(insert_blocks), dim3(kHashBlock), 0, s, jobs_dev, njobs);
+  hipLaunchKernelGGL(k_kmap_multi, dim3(kmap_blocks), dim3(kHashBlock), 0, s, jobs_dev, njobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* tkeys, const int32_t* tvals,
                        uint64_t mask, int32_t* kmap, int64_t kstride, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -303,23 +345,8 @@ hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* t
 // ---------------------------------------------------------------------------
 // Child expansion (decode): children of parent p are (key_p << 3) | o for the
 // set bits o of X[p], ascending, which keeps Morton order (Sec. S3.2).
-// Three passes: per-tile popcount sums, one-block scan, write.
 // ---------------------------------------------------------------------------
-constexpr int kExpandTile = 2048;
-
-__global__ void k_expand_sum(const uint8_t* __restrict__ codes, int64_t n, uint32_t* __restrict__ sums) {
-  __shared__ uint32_t ws[4];
-  int64_t base = (int64_t)blockIdx.x * kExpandTile;
-  uint32_t c = 0;
-  for (int k = threadIdx.x; k < kExpandTile; k += blockDim.x) {
-    int64_t i = base + k;
-    if (i < n) c += __popc((uint32_t)codes[i]);
-  }
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
-}
+// In place: per-chunk child counts -> exclusive offsets; checks the total.
 
 __global__ void k_expand_scan(uint32_t* __restrict__ sums, int nb, int64_t expected, uint32_t* err) {
   __shared__ uint32_t part[256];
@@ -340,40 +367,66 @@ __global__ void k_expand_scan(uint32_t* __restrict__ sums, int nb, int64_t expec
   for (int t = t0; t < t1; t++) { uint32_t v = sums[t]; sums[t] = acc; acc += v; }
 }
 
-__global__ void k_expand_write(const uint64_t* __restrict__ pkeys, const uint8_t* __restrict__ codes, int64_t n,
-                               const uint32_t* __restrict__ offs, uint64_t* __restrict__ ckeys,
-                               int32_t* __restrict__ cstart, int64_t expected) {
+// One block per decoded chunk.  The chunk's first child row is the sum of
+// the child counts of the chunks before it: summed here when there are few
+// chunks, else `csum` already holds exclusive offsets (k_expand_scan).
+constexpr int kExpandDirect = 2048;
+
+__global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__ chunks, int nchunks,
+                                                       const uint64_t* __restrict__ pkeys,
+                                                       const uint8_t* __restrict__ codes, int64_t n,
+                                                       const uint32_t* __restrict__ csum, int sums_are_offsets,
+                                                       uint64_t* __restrict__ ckeys, int32_t* __restrict__ cstart,
+                                                       int64_t expected, uint64_t* tkeys, int32_t* tvals,
+                                                       uint64_t mask, uint32_t* err) {
   __shared__ uint32_t wtot[4];
   __shared__ uint32_t run;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) run = offs[blockIdx.x];
+  const int cb = blockIdx.x;
+  const Chunk ch = chunks[cb];
+  if (sums_are_offsets) {
+    if (threadIdx.x == 0) run = csum[cb];
+  } else {
+    uint32_t part = 0;
+    for (int k = threadIdx.x; k < cb; k += 256) part += csum[k];
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (lane == 0) wtot[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) run = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+  }
   __syncthreads();
-  int64_t base = (int64_t)blockIdx.x * kExpandTile;
-  for (int k0 = 0; k0 < kExpandTile; k0 += blockDim.x) {
-    int64_t i = base + k0 + threadIdx.x;
-    uint32_t code = i < n ? codes[i] : 0u;
-    uint32_t c = __popc(code);
-    // inclusive wave scan
+  for (int k0 = 0; k0 < ch.count; k0 += 256) {
+    const int64_t i = ch.node0 + k0 + threadIdx.x;
+    const bool valid = k0 + (int)threadIdx.x < ch.count && i < n;
+    const uint32_t code = valid ? codes[i] : 0u;
+    const uint32_t c = __popc(code);
     uint32_t inc = c;
     for (int off = 1; off < 64; off <<= 1) {
-      uint32_t v = __shfl_up(inc, off);
+      const uint32_t v = __shfl_up(inc, off);
       if (lane >= off) inc += v;
     }
     if (lane == 63) wtot[wave] = inc;
     __syncthreads();
     uint32_t before = run;
     for (int w = 0; w < wave; w++) before += wtot[w];
-    uint32_t first = before + inc - c;
-    if (i < n) {
+    const uint32_t first = before + inc - c;
+    if (valid) {
       cstart[i] = (int32_t)first;
-      uint64_t pk = pkeys[i];
+      const uint64_t pk = pkeys[i];
       uint32_t r = first;
       for (int o = 0; o < 8; o++)
         if ((code >> o) & 1u) {
-          if ((int64_t)r < expected) ckeys[r] = (pk << 3) | (uint64_t)o;
+          if ((int64_t)r < expected) {
+            const uint64_t k = (pk << 3) | (uint64_t)o;
+            ckeys[r] = k;
+            if (tkeys != nullptr) hash_put(k, (int32_t)r, tkeys, tvals, mask);
+          }
           r++;
         }
-      if (i == n - 1) cstart[n] = (int32_t)(first + c);
+      if (i == n - 1) {
+        cstart[n] = (int32_t)(first + c);
+        if ((int64_t)(first + c) != expected) atomicOr(err, ERR_COUNT);
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) run += wtot[0] + wtot[1] + wtot[2] + wtot[3];
@@ -381,14 +434,18 @@ __global__ void k_expand_write(const uint64_t* __restrict__ pkeys, const uint8_t
   }
 }
 
-hipError_t launch_expand(const uint64_t* pkeys, const uint8_t* codes, int64_t n, uint64_t* ckeys, int32_t* cstart,
-                         int64_t n_child_expected, uint32_t* scan_tmp, uint32_t* err, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  int nb = (int)((n + kExpandTile - 1) / kExpandTile);
-  hipLaunchKernelGGL(k_expand_sum, dim3(nb), dim3(256), 0, s, codes, n, scan_tmp);
-  hipLaunchKernelGGL(k_expand_scan, dim3(1), dim3(256), 0, s, scan_tmp, nb, n_child_expected, err);
-  hipLaunchKernelGGL(k_expand_write, dim3(nb), dim3(256), 0, s, pkeys, codes, n, scan_tmp, ckeys, cstart,
-                     n_child_expected);
+hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t* pkeys, const uint8_t* codes,
+                                int64_t n, uint32_t* csum, uint64_t* ckeys, int32_t* cstart,
+                                int64_t n_child_expected, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
+                                uint32_t* err, hipStream_t s) {
+  if (nchunks <= 0 || n <= 0) return hipSuccess;
+  int offs = 0;
+  if (nchunks > kExpandDirect) {
+    hipLaunchKernelGGL(k_expand_scan, dim3(1), dim3(256), 0, s, csum, nchunks, n_child_expected, err);
+    offs = 1;
+  }
+  hipLaunchKernelGGL(k_expand_chunks, dim3(nchunks), dim3(256), 0, s, chunks, nchunks, pkeys, codes, n,
+                     (const uint32_t*)csum, offs, ckeys, cstart, n_child_expected, tkeys, tvals, mask, err);
   return hipGetLastError();
 }
 

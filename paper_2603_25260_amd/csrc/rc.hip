@@ -150,7 +150,8 @@ template <int PW>
 __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chunks,
                                                   const uint8_t* __restrict__ payload,
                                                   const uint16_t* __restrict__ cdf16, uint8_t* __restrict__ codes,
-                                                  uint32_t* __restrict__ err, int lds_words) {
+                                                  uint32_t* __restrict__ csum, uint32_t* __restrict__ err,
+                                                  int lds_words) {
   extern __shared__ uint32_t buf[];
   __shared__ uint2 rows[kDecBlock][64];
   __shared__ uint8_t cbuf[kDecBlock];  // decoded codes of the current block
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   const int n = ch.count;
   const int64_t node0 = ch.node0;
   bool bad = false;
+  uint32_t kids = 0;  // children announced by this lane's share of the codes
   uint2 t[kDecBlock];
 #pragma unroll
   for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(k, max(n - 1, 0)), lane);
@@ -269,21 +271,29 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
       (void)i;
     }
     __syncthreads();
-    if (!bad && lane < cnt) codes[node0 + base + lane] = cbuf[lane];
+    if (!bad && lane < cnt) {
+      const uint32_t cv = cbuf[lane];
+      codes[node0 + base + lane] = (uint8_t)cv;
+      kids += __popc(cv);
+    }
   }
   if (bad && lane == 0) atomicOr(err, ERR_CORRUPT);
+  if (csum != nullptr) {
+    for (int off = 32; off > 0; off >>= 1) kids += __shfl_xor(kids, off);
+    if (lane == 0) csum[blockIdx.x] = kids;
+  }
 }
 
 hipError_t launch_rc_decode_sized(const Chunk* chunks, int nchunks, const uint8_t* payload, const uint16_t* cdf16,
-                                  uint8_t* codes, uint32_t* err, size_t max_len, hipStream_t s) {
+                                  uint8_t* codes, uint32_t* csum, uint32_t* err, size_t max_len, hipStream_t s) {
   if (nchunks <= 0) return hipSuccess;
   const int words = (int)((max_len + 3) / 4) + 4;
   if (words <= 64 * 12) {
     hipLaunchKernelGGL((k_rc_decode<12>), dim3(nchunks), dim3(64), (size_t)words * 4, s, chunks, payload, cdf16,
-                       codes, err, words);
+                       codes, csum, err, words);
   } else {
     hipLaunchKernelGGL((k_rc_decode<0>), dim3(nchunks), dim3(64), (size_t)words * 4, s, chunks, payload, cdf16,
-                       codes, err, words);
+                       codes, csum, err, words);
   }
   return hipGetLastError();
 }

@@ -31,6 +31,7 @@ struct lpcc_model {
   std::vector<int> first;        // first layer index of each depth (size D+1)
   std::vector<HostLayer> host;   // parsed layers
   LayerDev* d_layers = nullptr;  // device copies of the descriptors
+  std::vector<LayerDev> h_layers;  // the same descriptors on the host (kernel arguments)
   void* d_mem = nullptr;         // packed weights, biases, corrections, table
   int32_t* d_lut = nullptr;
 };
@@ -378,6 +379,8 @@ struct ModelBufs {
   uint64_t* hkeys[kMaxD + 1] = {};
   int32_t* hvals[kMaxD + 1] = {};
   uint64_t hmask[kMaxD + 1] = {};
+  uint64_t* hash_lo = nullptr;        // first word of the contiguous key arrays
+  size_t hash_words = 0;              // their extent in u64 words
   int8_t *h = nullptr, *S = nullptr;  // shallow ResBlock temporaries
   // deep temporaries per target depth d
   int8_t* G[kMaxD + 1][kMaxD + 1] = {};  // [d][j] embedding / down-sampled features at depth j
@@ -402,15 +405,23 @@ void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, cons
   }
   B.h = A.take<int8_t>((size_t)tmax * C);
   B.S = A.take<int8_t>((size_t)tmax * C);
+  // all hash-table key arrays first and contiguous, so that one fill clears them
   const int kmax = std::min(last, k0);
+  auto hashed = [&](int j) { return need_kmap(m, j) && !(j >= last && !(j == k0 && last > k0)); };
+  B.hash_lo = nullptr;
+  B.hash_words = 0;
   for (int j = 0; j <= kmax; j++) {
-    if (!need_kmap(m, j)) continue;
-    if (j >= last && !(j == k0 && last > k0)) continue;  // only depths that feed a wanted depth
+    if (!hashed(j)) continue;  // only depths that feed a wanted depth
     uint64_t sz = 1;
     while (sz < (uint64_t)std::max<int64_t>(2 * fr.tot[j], 2)) sz <<= 1;
     B.hmask[j] = sz - 1;
     B.hkeys[j] = A.take<uint64_t>(sz);
-    B.hvals[j] = A.take<int32_t>(sz);
+    if (!B.hash_lo) B.hash_lo = B.hkeys[j];
+    B.hash_words = (size_t)(B.hkeys[j] + sz - B.hash_lo);
+  }
+  for (int j = 0; j <= kmax; j++) {
+    if (!hashed(j)) continue;
+    B.hvals[j] = A.take<int32_t>(B.hmask[j] + 1);
     B.kmap[j] = A.take<int32_t>((size_t)27 * fr.tot[j]);
   }
   for (int d = k0 + 1; d <= last; d++) {
@@ -431,25 +442,63 @@ GemmSeg seg0() {
   return s;
 }
 
-// Hash + neighbour table of depth j
-void plan_kmap(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, int j, hipStream_t st) {
-  const int64_t n = fr.tot[j];
-  uint64_t* hk = B.hkeys[j];
-  int32_t* hv = B.hvals[j];
-  const uint64_t mask = B.hmask[j];
-  int32_t* km = B.kmap[j];
-  const uint64_t* keys = lv.key[j];
-  b.launch("hash", n, [=](const uint8_t*) {
-    hipError_t e = launch_fill_u64(hk, (int64_t)mask + 1, ~0ull, st);
-    if (e != hipSuccess) return e;
-    e = launch_hash_insert(keys, n, hk, hv, mask, st);
-    if (e != hipSuccess) return e;
-    return launch_kmap(keys, n, j, hk, hv, mask, km, n, st);
+// Clear every hash table of the call (one fill over the contiguous keys)
+void plan_hash_clear(Batch& b, ModelBufs& B, hipStream_t st) {
+  if (!B.hash_lo) return;
+  uint64_t* p = B.hash_lo;
+  const int64_t words = (int64_t)B.hash_words;
+  b.launch("hash", 0, [=](const uint8_t*) { return launch_fill_u64(p, words, ~0ull, st); });
+}
+
+// Hash + neighbour tables of all depths in `js` whose keys are known: one
+// insertion launch and one neighbour launch for all of them (tables cleared)
+void plan_kmaps(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, const std::vector<int>& js,
+                hipStream_t st) {
+  std::vector<HashJob> jobs;
+  int ib = 0, kb = 0;
+  int64_t units = 0;
+  for (int j : js) {
+    if (!B.kmap[j] || fr.tot[j] == 0) continue;
+    HashJob h;
+    memset(&h, 0, sizeof(h));
+    h.keys = lv.key[j];
+    h.tkeys = B.hkeys[j];
+    h.tvals = B.hvals[j];
+    h.kmap = B.kmap[j];
+    h.n = fr.tot[j];
+    h.kstride = fr.tot[j];
+    h.mask = B.hmask[j];
+    h.j = j;
+    h.blk_insert = ib;
+    h.blk_kmap = kb;
+    ib += (int)((h.n + kHashBlock - 1) / kHashBlock);
+    kb += (int)((27 * h.n + kHashBlock - 1) / kHashBlock);
+    units += h.n;
+    jobs.push_back(h);
+  }
+  if (jobs.empty()) return;
+  const size_t jo = b.add(jobs);
+  const int nj = (int)jobs.size();
+  b.launch("hash", units, [=](const uint8_t* base) {
+    return launch_hash_multi((const HashJob*)(base + jo), nj, ib, kb, st);
   });
 }
 
-void plan_gemm(Batch& b, const char* fam, int mode, int cin, int cout, const std::vector<GemmSeg>& segs,
-               hipStream_t st) {
+// Neighbour table of depth j whose hash table is already filled
+void plan_kmap_only(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, int j, hipStream_t st) {
+  const int64_t n = fr.tot[j];
+  const uint64_t* hk = B.hkeys[j];
+  const int32_t* hv = B.hvals[j];
+  const uint64_t mask = B.hmask[j];
+  int32_t* km = B.kmap[j];
+  const uint64_t* keys = lv.key[j];
+  b.launch("hash", n, [=](const uint8_t*) { return launch_kmap(keys, n, j, hk, hv, mask, km, n, st); });
+}
+
+const LayerDev& hlayer(const lpcc_model* m, const LayerDev* dev) { return m->h_layers[dev - m->d_layers]; }
+
+void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin, int cout,
+               const std::vector<GemmSeg>& segs, hipStream_t st) {
   std::vector<int64_t> rows;
   int64_t units = 0;
   for (auto& s : segs) {
@@ -458,15 +507,25 @@ void plan_gemm(Batch& b, const char* fam, int mode, int cin, int cout, const std
   }
   auto tiles = make_tiles(rows);
   if (tiles.empty()) return;
-  const size_t so = b.add(segs), to = b.add(tiles);
   const int nt = (int)tiles.size();
+  GemmArg one;
+  memset(&one, 0, sizeof(one));
+  size_t so = 0, to = 0;
+  if (segs.size() == 1) {  // by value: no descriptor loads in the kernel
+    one.seg = segs[0];
+    one.L = hlayer(m, segs[0].L);
+    one.one = 1;
+  } else {
+    so = b.add(segs);
+    to = b.add(tiles);
+  }
   std::string f(fam);
   b.launch(f, units, [=](const uint8_t* base) {
     const GemmSeg* S = (const GemmSeg*)(base + so);
     const Tile* T = (const Tile*)(base + to);
-    if (f == "up") return launch_up(cout, S, T, nt, st);
-    if (f == "emb") return launch_emb(S, T, nt, cout, st);
-    return launch_gemm(mode, cin, cout, S, T, nt, st);
+    if (f == "up") return launch_up(cout, S, T, nt, one, st);
+    if (f == "emb") return launch_emb(S, T, nt, cout, one, st);
+    return launch_gemm(mode, cin, cout, S, T, nt, one, st);
   });
 }
 
@@ -485,13 +544,13 @@ void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames&
   s.out = B.h;
   s.out_stride = C;
   s.rows = rows;
-  plan_gemm(b, "conv", G_CONV, C, C, {s}, st);
+  plan_gemm(b, m, "conv", G_CONV, C, C, {s}, st);
   s.in = B.h;
   s.L = dlayer(m, d, 1);
   s.out = B.S;
   s.resid = B.F[j];
   s.resid_stride = C;
-  plan_gemm(b, "conv", G_CONV, C, C, {s}, st);
+  plan_gemm(b, m, "conv", G_CONV, C, C, {s}, st);
   GemmSeg u = seg0();
   u.in = B.S;
   u.in_stride = C;
@@ -502,7 +561,7 @@ void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames&
   u.out_stride = C;
   u.rows = rows;
   u.child_rows = (int)fr.tot[d];
-  plan_gemm(b, "up", 0, C, C, {u}, st);
+  plan_gemm(b, m, "up", 0, C, C, {u}, st);
 }
 
 // Deep depths `ds` (all > k0), stage by stage; every launch covers all of them.
@@ -527,7 +586,7 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
       s.rows = (int)fr.tot[d - 1];
       v.push_back(s);
     }
-    plan_gemm(b, "emb", 0, 8, C, v, st);
+    plan_gemm(b, m, "emb", 0, 8, C, v, st);
   }
   // stride-2 steps j -> j-1 for j = d-1 .. k0+1; step t handles j = d - t
   int maxsteps = 0;
@@ -550,7 +609,7 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
       s.child_rows = (int)fr.tot[j];
       v.push_back(s);
     }
-    plan_gemm(b, "down", G_DOWN, C, C, v, st);
+    plan_gemm(b, m, "down", G_DOWN, C, C, v, st);
   }
   // [F_k0 | G]
   for (int d : dset) {
@@ -594,9 +653,9 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
     s2.rows = (int)fr.tot[k0];
     c2.push_back(s2);
   }
-  plan_gemm(b, "conv", G_CONV, 2 * C, C, c1, st);
-  plan_gemm(b, "skip", G_DENSE, 2 * C, C, sk, st);
-  plan_gemm(b, "conv", G_CONV, C, C, c2, st);
+  plan_gemm(b, m, "conv", G_CONV, 2 * C, C, c1, st);
+  plan_gemm(b, m, "skip", G_DENSE, 2 * C, C, sk, st);
+  plan_gemm(b, m, "conv", G_CONV, C, C, c2, st);
   // upsample + prune k0 -> d
   int maxup = 0;
   for (int d : dset) maxup = std::max(maxup, d - k0);
@@ -618,7 +677,7 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
       u.child_rows = (int)fr.tot[j + 1];
       v.push_back(u);
     }
-    plan_gemm(b, "up", 0, C, C, v, st);
+    plan_gemm(b, m, "up", 0, C, C, v, st);
   }
 }
 
@@ -635,11 +694,22 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
   }
   auto tiles = make_tiles(rows);
   if (tiles.empty()) return;
-  const size_t so = b.add(segs), to = b.add(tiles);
   const int nt = (int)tiles.size(), C = m->C;
+  PredArg one;
+  memset(&one, 0, sizeof(one));
+  size_t so = 0, to = 0;
+  if (segs.size() == 1) {
+    one.seg = segs[0];
+    one.fc1 = hlayer(m, segs[0].fc1);
+    one.fc2 = hlayer(m, segs[0].fc2);
+    one.one = 1;
+  } else {
+    so = b.add(segs);
+    to = b.add(tiles);
+  }
   const int32_t* lut = m->d_lut;
   b.launch("predict", units, [=](const uint8_t* base) {
-    return launch_predict(C, mode, (const PredSeg*)(base + so), (const Tile*)(base + to), nt, lut, st);
+    return launch_predict(C, mode, (const PredSeg*)(base + so), (const Tile*)(base + to), nt, lut, one, st);
   });
 }
 
@@ -666,7 +736,7 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
   size_t sort_tmp = 0;
   HIPC(hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                                          (int)std::max<int64_t>(ntot, 1), 0, std::max(end_bit, 1), st));
-  const int tile = 2048;
+  const int tile = 256;  // one element per thread: many blocks even for one frame
   const int64_t ntiles = (ntot + tile - 1) / tile;
   // upper bounds of the node count per depth
   std::vector<int64_t> ub(D + 1, 0);
@@ -683,18 +753,22 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
   uint64_t *kin = nullptr, *kout = nullptr;
   void* tmp = nullptr;
   uint32_t *err = nullptr, *hist = nullptr, *totals = nullptr, *foff = nullptr;
+  char *zero_lo = nullptr, *zero_hi = nullptr;
   auto carve = [&](Arena& A) {
     if (need_stage) xyz_stage = A.take<int32_t>((size_t)ntot * 3);
     kin = A.take<uint64_t>(ntot);
     kout = A.take<uint64_t>(ntot);
     tmp = A.take<char>(sort_tmp);
-    err = A.take<uint32_t>(nf);
     hist = A.take<uint32_t>((size_t)std::max<int64_t>(ntiles, 1) * (D + 1));
-    totals = A.take<uint32_t>(D + 1);
     foff = A.take<uint32_t>((size_t)nf * (D + 1));
+    // zero-initialised block: error words, totals and all code arrays
+    err = A.take<uint32_t>(nf);
+    zero_lo = (char*)err;
+    totals = A.take<uint32_t>(D + 1);
+    for (int d = 0; d <= D; d++) lv.code[d] = A.take<uint8_t>(align_up(ub[d], 4) + 4);
+    zero_hi = (char*)(lv.code[D] + align_up(ub[D], 4) + 4);
     for (int d = 0; d <= D; d++) {
       lv.key[d] = A.take<uint64_t>(ub[d]);
-      lv.code[d] = A.take<uint8_t>(align_up(ub[d], 4) + 4);
       lv.cstart[d] = A.take<int32_t>(ub[d] + 1);
     }
   };
@@ -708,10 +782,8 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
   A.cap = c->cap[0];
   carve(A);
 
-  HIPC(launch_fill_u32(err, nf, 0, st));
   HIPC(launch_fill_u32(foff, (int64_t)nf * (D + 1), 0xFFFFFFFFu, st));
-  HIPC(launch_fill_u32(totals, D + 1, 0, st));
-  for (int d = 0; d <= D; d++) HIPC(launch_fill_u32((uint32_t*)lv.code[d], (int64_t)(align_up(ub[d], 4) + 4) / 4, 0, st));
+  HIPC(launch_fill_u32((uint32_t*)zero_lo, (int64_t)(align_up((size_t)(zero_hi - zero_lo), 4) / 4), 0, st));
   for (int f = 0; f < nf; f++) {
     if (n[f] <= 0) continue;
     const int32_t* src = xyz[f];
@@ -879,8 +951,13 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     const int64_t bytes = fr.tot[0] * C;
     b.launch("fill", 0, [=](const uint8_t*) { return launch_fill_u32((uint32_t*)f0, (bytes + 3) / 4, 0, st); });
   }
-  for (int j = 0; j <= std::min(last, k0); j++)
-    if (B.kmap[j]) plan_kmap(b, lv, fr, B, j, st);
+  {
+    std::vector<int> js;
+    for (int j = 0; j <= std::min(last, k0); j++)
+      if (B.kmap[j]) js.push_back(j);
+    plan_hash_clear(b, B, st);
+    plan_kmaps(b, lv, fr, B, js, st);
+  }
   for (int d = 1; d <= std::min(last, k0); d++) plan_shallow(b, m, lv, fr, B, d, st);
   std::vector<int> dset;
   for (int d = k0 + 1; d <= last; d++)
@@ -1125,9 +1202,11 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   ModelBufs B;
   uint8_t* payload = nullptr;
   uint16_t* cdf16 = nullptr;
-  uint32_t *err = nullptr, *scan_tmp = nullptr;
+  uint32_t *err = nullptr, *csum = nullptr;
   int32_t* xyz_stage = nullptr;
   int64_t maxN = 0;
+  size_t maxch = 0;
+  for (int d = 0; d < D; d++) maxch = std::max(maxch, dchunks[d].size());
   for (int d = 0; d <= D; d++) maxN = std::max(maxN, fr.tot[d]);
   std::vector<bool> wanted(D, true);
   std::vector<bool> xdev(nf, false);
@@ -1145,7 +1224,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     payload = A.take<uint8_t>(paybytes);
     cdf16 = A.take<uint16_t>((size_t)maxN * 256);
     err = A.take<uint32_t>(4);
-    scan_tmp = A.take<uint32_t>((size_t)(maxN / 2048 + 2));
+    csum = A.take<uint32_t>(maxch + 1);
     if (any_host_out) xyz_stage = A.take<int32_t>((size_t)fr.tot[D] * 3);
     carve_model(A, m, fr, D - 1, wanted, B);
   };
@@ -1185,7 +1264,8 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     const int64_t bytes = fr.tot[0] * C;
     b.launch("fill", 0, [=](const uint8_t*) { return launch_fill_u32((uint32_t*)f0, (bytes + 3) / 4, 0, st); });
   }
-  if (B.kmap[0]) plan_kmap(b, lv, fr, B, 0, st);
+  plan_hash_clear(b, B, st);
+  if (B.kmap[0]) plan_kmaps(b, lv, fr, B, {0}, st);
   for (int d = 0; d < D; d++) {
     if (d >= 1 && d <= k0) plan_shallow(b, m, lv, fr, B, d, st);
     if (d > k0) plan_deep(b, m, lv, fr, B, {d}, st);
@@ -1197,26 +1277,36 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     p.rows = (int)fr.tot[d];
     p.cdf16 = cdf16;
     plan_predict(b, m, {p}, 1, st);
+    const size_t co = b.add(dchunks[d]);
+    const int nch = (int)dchunks[d].size();
     {
-      const size_t co = b.add(dchunks[d]);
-      const int nch = (int)dchunks[d].size();
       const size_t ml = dmaxlen[d];
       uint8_t* codes = lv.code[d];
+      uint32_t* cs = csum;
       b.launch("rc_decode", fr.tot[d], [=](const uint8_t* base) {
-        return launch_rc_decode_sized((const Chunk*)(base + co), nch, payload, cdf16, codes, err + 0, ml, st);
+        return launch_rc_decode_sized((const Chunk*)(base + co), nch, payload, cdf16, codes, cs, err + 0, ml, st);
       });
     }
     {
+      // children of depth d from the chunks' child counts; when depth d+1
+      // convolves, its hash table is filled on the way
       const uint64_t* pk = lv.key[d];
       const uint8_t* codes = lv.code[d];
       const int64_t np = fr.tot[d], nc = fr.tot[d + 1];
       uint64_t* ck = lv.key[d + 1];
-      int32_t* cs = lv.cstart[d];
+      int32_t* cst = lv.cstart[d];
       uint32_t* e1 = err + 1;
-      uint32_t* tmp = scan_tmp;
-      b.launch("expand", np, [=](const uint8_t*) { return launch_expand(pk, codes, np, ck, cs, nc, tmp, e1, st); });
+      uint32_t* cs = csum;
+      const bool hashed = d + 1 <= k0 && B.kmap[d + 1];
+      uint64_t* tk = hashed ? B.hkeys[d + 1] : nullptr;
+      int32_t* tv = hashed ? B.hvals[d + 1] : nullptr;
+      const uint64_t hm = hashed ? B.hmask[d + 1] : 0;
+      b.launch("expand", np, [=](const uint8_t* base) {
+        return launch_expand_chunks((const Chunk*)(base + co), nch, pk, codes, np, cs, ck, cst, nc, tk, tv, hm, e1,
+                                    st);
+      });
     }
-    if (d + 1 <= k0 && B.kmap[d + 1]) plan_kmap(b, lv, fr, B, d + 1, st);
+    if (d + 1 <= k0 && B.kmap[d + 1]) plan_kmap_only(b, lv, fr, B, d + 1, st);
   }
   s = run_batch(c, b, &desc_off);
   if (s) return s;
@@ -1314,6 +1404,7 @@ int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out) 
   softmax_table(lut);
   m->d_lut = (int32_t*)put(lut, sizeof(lut));
   m->d_layers = (LayerDev*)put(ld.data(), ld.size() * sizeof(LayerDev));
+  m->h_layers = ld;
   if (hipMemcpy(m->d_mem, host.data(), off, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(m->d_mem);
     return LPCC_E_DEVICE;
