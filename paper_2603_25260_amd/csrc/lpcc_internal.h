@@ -72,8 +72,12 @@ struct Tile {
 
 // Gather-GEMM segment: out[row] = epilogue(sum over taps of in[src(row,t)] W[t])
 struct GemmSeg {
-  const int8_t* in;        // input rows
+  const int8_t* in;        // input rows (channels below `split`)
   int64_t in_stride;       // bytes between input rows
+  const int8_t* in2;       // channels from `split` on, when split < cin: [in | in2]
+  int64_t in2_stride;
+  int32_t split;           // first channel read from in2 (cin when unused)
+  int32_t pad_;
   const int32_t* kmap;     // conv: [27][kstride] source rows (-1 = empty)
   int64_t kstride;
   const uint8_t* code;     // down/up: occupancy codes of the parents
@@ -183,8 +187,6 @@ hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int 
                      hipStream_t s);
 hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, const GemmArg& one,
                       hipStream_t s);
-hipError_t launch_copy_rows(const int8_t* src, int64_t src_stride, int8_t* dst, int64_t dst_stride,
-                            int64_t rows, int width, hipStream_t s);
 hipError_t launch_predict(int C, int mode, const PredSeg* segs_dev, const Tile* tiles_dev, int ntiles,
                           const int32_t* lut, const PredArg& one, hipStream_t s);
 

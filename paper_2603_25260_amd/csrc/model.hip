@@ -121,7 +121,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
     const int k0 = 64 * s + 16 * g;
     const int c0 = k0 % CIN;
     v4i a = v4i{0, 0, 0, 0};
-    if (src[s] >= 0) a = ld16(S.in + (int64_t)src[s] * S.in_stride + c0);
+    if (src[s] >= 0)
+      a = c0 < S.split ? ld16(S.in + (int64_t)src[s] * S.in_stride + c0)
+                       : ld16(S.in2 + (int64_t)src[s] * S.in2_stride + (c0 - S.split));
 #pragma unroll
     for (int nb = 0; nb < NB; nb++) {
       v4i b = Wp[((int64_t)s * NB + nb) * 64 + lane];
@@ -312,8 +314,9 @@ __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, c
   GemmSeg S;
   LayerDev L;
   const int tile_row0 = pick_seg(segs, tiles, A, S, L);
+  const int cs = __builtin_ctz((unsigned)C);  // C is a power of two
   for (int e = threadIdx.x; e < 64 * C; e += blockDim.x) {
-    const int row = tile_row0 + e / C, o = e % C;
+    const int row = tile_row0 + (e >> cs), o = e & (C - 1);
     if (row >= S.rows) continue;
     const uint32_t code = S.code[row];
     int acc = L.bias[o];
@@ -326,24 +329,6 @@ __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, c
 hipError_t launch_emb(const GemmSeg* segs, const Tile* tiles, int ntiles, int C, const GemmArg& A, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_emb, dim3(ntiles), dim3(256), 0, s, segs, tiles, C, A);
-  return hipGetLastError();
-}
-
-__global__ void k_copy_rows(const int8_t* __restrict__ src, int64_t ss, int8_t* __restrict__ dst, int64_t ds,
-                            int64_t rows, int width) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t words = width / 4;
-  if (e >= rows * words) return;
-  int64_t row = e / words, w = e % words;
-  *(int32_t*)(dst + row * ds + 4 * w) = *(const int32_t*)(src + row * ss + 4 * w);
-}
-
-hipError_t launch_copy_rows(const int8_t* src, int64_t src_stride, int8_t* dst, int64_t dst_stride, int64_t rows,
-                            int width, hipStream_t s) {
-  if (rows <= 0) return hipSuccess;
-  int64_t tot = rows * (width / 4);
-  hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, src, src_stride, dst,
-                     dst_stride, rows, width);
   return hipGetLastError();
 }
 

@@ -95,7 +95,7 @@ hipError_t launch_level_hist(const uint64_t* keys, int64_t n, int D, int tile, u
 __global__ void k_level_scan(uint32_t* __restrict__ hist, int nb, int D, uint32_t* __restrict__ totals) {
   __shared__ uint32_t part[kLevelThreads][kMaxD + 1];
   int tid = threadIdx.x;
-  int per = (nb + blockDim.x - 1) / blockDim.x;
+  int per = (nb + kLevelThreads - 1) / kLevelThreads;
   int t0 = tid * per, t1 = min(nb, t0 + per);
   uint32_t run[kMaxD + 1];
   for (int d = 0; d <= D; d++) run[d] = 0;

@@ -127,11 +127,17 @@ hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scrat
 // Decoder: one wave per chunk.  The chunk's bytes are staged in LDS (zero
 // padded: bytes past the end read as 0) and consumed through a dword window.
 // CDF rows are copied into LDS kDecBlock at a time (unconditional loads, one
-// memory round trip per block); lane l reads cdf[4l .. 4l+3] of the current
-// node from there (cdf[255] = 65536 implied).  The symbol is the number of
-// entries with r * cdf[s] <= code, minus one, counted with four ballots
-// (r, cdf < 2^16, so 24-bit multiplies are exact).  Decoded codes are
-// collected one per lane and stored 64 at a time.
+// memory round trip per block).  Lane l holds the boundaries
+// b_j = cdf[4l + j], j = 0..4, of the current node (cdf[255] = 65536; lane 63
+// has no b_4).  The symbol s is the last index with r * cdf[s] <= code
+// (r, cdf < 2^17, so 24-bit multiplies are exact).  Every lane resolves the
+// candidate inside its own four entries (lo, freq) with compares and selects;
+// the owning lane is popcount(ballot(r * b_0 <= code)) - 1, and a single
+// readlane brings its packed (lo, freq) to the scalar coder state, so the
+// dependent chain per symbol is: multiply-compare, ballot, readlane, two
+// multiplies, renormalise.  A corrupt stream (code >= range after a step) is
+// noted per symbol and acted on once per block.  Decoded codes are collected
+// one per lane and stored kDecBlock at a time.
 // Chunk.pad_ carries the payload length in bytes, Chunk.scratch its offset.
 // ---------------------------------------------------------------------------
 constexpr int kDecBlock = 32;
@@ -142,10 +148,8 @@ __device__ __forceinline__ uint2 ld_row(const uint16_t* cdf16, int64_t node, int
 
 // PW > 0: the payload (at most 64*PW dwords) sits in VGPRs, dword w in lane
 // w%64 of register w/64, read with v_readlane; PW = 0 reads it from LDS (long
-// chunks).  Every per-symbol step is written to keep the dependent chain of
-// scalar <-> vector transfers short: the four ballot masks are nested (the CDF
-// increases), so popcount(b0) - 1 is already the lane holding cdf[s]; the
-// renormalisation takes 0, 1 or 2 bytes from a 64-bit buffer without branches.
+// chunks).  The renormalisation takes 0, 1 or 2 bytes from a 64-bit buffer
+// without branches.
 template <int PW>
 __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chunks,
                                                   const uint8_t* __restrict__ payload,
@@ -153,8 +157,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
                                                   uint32_t* __restrict__ csum, uint32_t* __restrict__ err,
                                                   int lds_words) {
   extern __shared__ uint32_t buf[];
-  __shared__ uint2 rows[kDecBlock][64];
-  __shared__ uint8_t cbuf[kDecBlock];  // decoded codes of the current block
+  __shared__ uint2 rows[kDecBlock][65];  // entry 64 pads the neighbour read of lane 63
   const Chunk ch = chunks[blockIdx.x];
   const int lane = threadIdx.x;
   const uint32_t len = (uint32_t)ch.pad_;
@@ -164,16 +167,18 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       const uint32_t b = 4u * (uint32_t)w + (uint32_t)k;
-      if (b < len) v |= (uint32_t)src[b] << (8 * k);
+      if (b < len) v |= (uint32_t)src[b] << (24 - 8 * k);
     }
     buf[w] = v;
   }
+  if (lane < kDecBlock) rows[lane][64] = make_uint2(0u, 0u);
   __syncthreads();
   uint32_t pw[PW > 0 ? PW : 1];
 #pragma unroll
   for (int j = 0; j < (PW > 0 ? PW : 1); j++) pw[j] = (PW > 0 && 64 * j + lane < lds_words) ? buf[64 * j + lane] : 0u;
 
-  // payload dwords in stream order; byte 0 of the stream is the low byte of dword 0
+  // payload dwords in stream order, big-endian: byte 0 of the stream is the
+  // high byte of dword 0
   uint32_t cj = 0, creg = pw[0];
   auto dword = [&](uint32_t w) -> uint32_t {
     if (PW == 0) return (int)w < lds_words ? buf[w] : 0u;
@@ -190,9 +195,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   uint64_t bb = 0;
   uint32_t nb = 0, wnext = 0;
   auto refill = [&]() {  // append one dword (4 bytes, stream order)
-    const uint32_t d = dword(wnext++);
-    const uint32_t be = (d << 24) | ((d & 0xFF00u) << 8) | ((d >> 8) & 0xFF00u) | (d >> 24);
-    bb |= (uint64_t)be << (32 - 8 * nb);
+    bb |= (uint64_t)dword(wnext++) << (32 - 8 * nb);
     nb += 4;
   };
   refill();
@@ -206,10 +209,11 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   const int n = ch.count;
   const int64_t node0 = ch.node0;
   bool bad = false;
-  uint32_t kids = 0;  // children announced by this lane's share of the codes
+  uint32_t kids = 0;  // children announced by the codes this lane stored
   uint2 t[kDecBlock];
 #pragma unroll
   for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(k, max(n - 1, 0)), lane);
+  const bool last_lane = lane == 63;
   for (int base = 0; base < n && !bad; base += kDecBlock) {
     const int cnt = min(kDecBlock, n - base);
     __syncthreads();
@@ -223,58 +227,50 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
       for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(nbk + k, last), lane);
     }
     uint2 nxt = rows[0][lane];
+    uint32_t nx4 = rows[0][lane + 1].x;
+    uint32_t cv = 0;  // decoded code k of this block in lane k
+    uint32_t badv = 0;
     for (int k = 0; k < cnt; k++) {
-      const int i = base + k;
       const uint2 row = nxt;
-      nxt = rows[min(k + 1, kDecBlock - 1)][lane];
+      const uint32_t x4 = nx4;
+      const int kn = min(k + 1, kDecBlock - 1);
+      nxt = rows[kn][lane];
+      nx4 = rows[kn][lane + 1].x;
       if (nb < 2) refill();
-      // the coder state is wave-uniform: keep it in scalar registers
       code = (uint32_t)__builtin_amdgcn_readfirstlane((int)code);
       range = (uint32_t)__builtin_amdgcn_readfirstlane((int)range);
-      bb = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(bb >> 32)) << 32) |
-           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)bb);
       const uint32_t r = range >> 16;
-      // entries 4l..4l+3 of the CDF in lane l; slot 255 (lane 63, last) is not
-      // an entry (cdf[255] = 65536 is implied) and is masked out of b3
-      const uint64_t b0 = __ballot(__umul24(r, row.x & 0xFFFFu) <= code);
-      const uint64_t b1 = __ballot(__umul24(r, row.x >> 16) <= code);
-      const uint64_t b2 = __ballot(__umul24(r, row.y & 0xFFFFu) <= code);
-      const uint64_t b3 = __ballot(__umul24(r, row.y >> 16) <= code) & 0x7FFFFFFFFFFFFFFFull;
-      const int s = __popcll(b0) + __popcll(b1) + __popcll(b2) + __popcll(b3) - 1;
-      const int L = s >> 2, e = s & 3;
-      // lane L's four entries as two packed pairs, and the first entry of lane L+1
-      const int Lc = s < 0 ? 0 : L;
-      const uint32_t X = (uint32_t)__builtin_amdgcn_readlane((int)row.x, Lc);
-      const uint32_t Y = (uint32_t)__builtin_amdgcn_readlane((int)row.y, Lc);
-      const uint32_t Z = (uint32_t)__builtin_amdgcn_readlane((int)row.x, min(Lc + 1, 63));
-      // the four entries as one 64-bit word, and the same shifted by one entry
-      const uint64_t W = ((uint64_t)Y << 32) | X;
-      const uint64_t W1 = (W >> 16) | ((uint64_t)(Z & 0xFFFFu) << 48);
-      const uint32_t lo = (uint32_t)(W >> (16 * e)) & 0xFFFFu;
-      const uint32_t hn = (uint32_t)(W1 >> (16 * e)) & 0xFFFFu;
-      const uint32_t hi = s == 254 ? 65536u : hn;
-      code -= r * lo;
-      range = r * (hi - lo);
+      // this lane's boundaries; slot 255 is the total 65536, and lane 63 has no b_4
+      const uint32_t b0 = row.x & 0xFFFFu, b1 = row.x >> 16, b2 = row.y & 0xFFFFu;
+      const uint32_t b3 = last_lane ? 65536u : (row.y >> 16);
+      const uint32_t b4 = last_lane ? 65536u : (x4 & 0xFFFFu);
+      const bool m0 = __umul24(r, b0) <= code;
+      const bool m1 = __umul24(r, b1) <= code;
+      const bool m2 = __umul24(r, b2) <= code;
+      const bool m3 = __umul24(r, b3) <= code;
+      const uint32_t lo = m3 ? b3 : (m2 ? b2 : (m1 ? b1 : b0));
+      const uint32_t hi = m3 ? b4 : (m2 ? b3 : (m1 ? b2 : b1));
+      const uint32_t sub = (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
+      // lanes 0..L have b_0 <= code / r; lane 0 always (cdf[0] = 0)
+      const int L = max((int)__popcll(__ballot(m0)) - 1, 0);
+      const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)(lo | ((hi - lo) << 16)), L);
+      code -= r * (P & 0xFFFFu);
+      range = r * (P >> 16);
       // a valid stream keeps code < range; anything else is corrupt
-      if ((code >= range) | (s < 0)) {
-        bad = true;
-        break;
-      }
+      badv |= (uint32_t)(((uint64_t)range - (uint64_t)code - 1ull) >> 63);
       // renormalise: range >= 2^8 here, so take 0, 1 or 2 bytes
       const uint32_t sh = range < (1u << 16) ? 16u : (range < (1u << 24) ? 8u : 0u);
-      const uint32_t kb = sh >> 3;
-      code = (uint32_t)(((uint64_t)code << sh) | ((bb >> 32) >> (32 - sh)));
+      code = (uint32_t)((((uint64_t)code << 32) | (bb >> 32)) >> (32 - sh));
       bb <<= sh;
-      nb -= kb;
+      nb -= sh >> 3;
       range <<= sh;
-      cbuf[k] = (uint8_t)(s + 1);
-      (void)i;
+      const int sym = 4 * L + __builtin_amdgcn_readlane((int)sub, L);
+      cv = lane == k ? (uint32_t)(sym + 1) : cv;
     }
-    __syncthreads();
+    bad = badv != 0;
     if (!bad && lane < cnt) {
-      const uint32_t cv = cbuf[lane];
       codes[node0 + base + lane] = (uint8_t)cv;
-      kids += __popc(cv);
+      kids += __popc(cv & 0xFFu);
     }
   }
   if (bad && lane == 0) atomicOr(err, ERR_CORRUPT);

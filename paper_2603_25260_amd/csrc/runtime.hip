@@ -384,7 +384,7 @@ struct ModelBufs {
   int8_t *h = nullptr, *S = nullptr;  // shallow ResBlock temporaries
   // deep temporaries per target depth d
   int8_t* G[kMaxD + 1][kMaxD + 1] = {};  // [d][j] embedding / down-sampled features at depth j
-  int8_t* cat[kMaxD + 1] = {};           // [tot[k0]][2C]
+  int8_t* Gk[kMaxD + 1] = {};            // [tot[k0]][C]: G of target d at depth k0
   int8_t* dh[kMaxD + 1] = {};
   int8_t* ds[kMaxD + 1] = {};
   int8_t* Z[kMaxD + 1][kMaxD + 1] = {};  // [d][j] upsampled features at depth j (j = k0 is H)
@@ -427,7 +427,7 @@ void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, cons
   for (int d = k0 + 1; d <= last; d++) {
     if (!wanted[d]) continue;
     for (int j = d - 1; j > k0; j--) B.G[d][j] = A.take<int8_t>((size_t)fr.tot[j] * C);
-    B.cat[d] = A.take<int8_t>((size_t)fr.tot[k0] * 2 * C);
+    B.Gk[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
     B.dh[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
     B.ds[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
     for (int j = k0; j <= d; j++) B.Z[d][j] = A.take<int8_t>((size_t)fr.tot[j] * C);
@@ -439,6 +439,7 @@ const LayerDev* dlayer(const lpcc_model* m, int d, int k) { return m->d_layers +
 GemmSeg seg0() {
   GemmSeg s;
   memset(&s, 0, sizeof(s));
+  s.split = 1 << 30;  // single input unless set
   return s;
 }
 
@@ -570,7 +571,7 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
   if (dset.empty()) return;
   const int C = m->C, k0 = m->k0;
   auto Gout = [&](int d, int j) -> std::pair<int8_t*, int64_t> {  // destination of depth-j G of target d
-    if (j == k0) return {B.cat[d] + C, 2 * C};
+    if (j == k0) return {B.Gk[d], C};
     return {B.G[d][j], C};
   };
   // occupancy embedding at depth d-1
@@ -611,20 +612,16 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
     }
     plan_gemm(b, m, "down", G_DOWN, C, C, v, st);
   }
-  // [F_k0 | G]
-  for (int d : dset) {
-    const int8_t* src = B.F[k0];
-    int8_t* dst = B.cat[d];
-    const int64_t rows = fr.tot[k0];
-    b.launch("copy", rows, [=](const uint8_t*) { return launch_copy_rows(src, C, dst, 2 * C, rows, C, st); });
-  }
   // ResBlock at k0: conv1 (2C -> C), skip (2C -> C), conv2 (+ skip)
   std::vector<GemmSeg> c1, sk, c2;
   for (int d : dset) {
     const int base = 1 + (d - 1 - k0);  // index of conv1 in depth d's layer list
     GemmSeg s = seg0();
-    s.in = B.cat[d];
-    s.in_stride = 2 * C;
+    s.in = B.F[k0];  // [F_k0 | G] without materialising the concatenation
+    s.in_stride = C;
+    s.in2 = B.Gk[d];
+    s.in2_stride = C;
+    s.split = C;
     s.kmap = B.kmap[k0];
     s.kstride = fr.tot[k0];
     s.L = dlayer(m, d, base);
@@ -633,8 +630,11 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
     s.rows = (int)fr.tot[k0];
     c1.push_back(s);
     GemmSeg k = seg0();
-    k.in = B.cat[d];
-    k.in_stride = 2 * C;
+    k.in = B.F[k0];
+    k.in_stride = C;
+    k.in2 = B.Gk[d];
+    k.in2_stride = C;
+    k.split = C;
     k.L = dlayer(m, d, base + 2);
     k.out = B.ds[d];
     k.out_stride = C;
