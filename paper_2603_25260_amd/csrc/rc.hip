@@ -126,18 +126,19 @@ hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scrat
 // ---------------------------------------------------------------------------
 // Decoder: one wave per chunk.  The chunk's bytes are staged in LDS (zero
 // padded: bytes past the end read as 0) and consumed through a dword window.
-// CDF rows are copied into LDS kDecBlock at a time (unconditional loads, one
-// memory round trip per block).  Lane l holds the boundaries
-// b_j = cdf[4l + j], j = 0..4, of the current node (cdf[255] = 65536; lane 63
-// has no b_4).  The symbol s is the last index with r * cdf[s] <= code
-// (r, cdf < 2^17, so 24-bit multiplies are exact).  Every lane resolves the
-// candidate inside its own four entries (lo, freq) with compares and selects;
-// the owning lane is popcount(ballot(r * b_0 <= code)) - 1, and a single
-// readlane brings its packed (lo, freq) to the scalar coder state, so the
-// dependent chain per symbol is: multiply-compare, ballot, readlane, two
-// multiplies, renormalise.  A corrupt stream (code >= range after a step) is
-// noted per symbol and acted on once per block.  Decoded codes are collected
-// one per lane and stored kDecBlock at a time.
+// CDF rows are loaded kDecBlock at a time straight into registers (one
+// memory round trip per block, the next block in flight while this one is
+// decoded).  Lane l holds the boundaries b_j = cdf[4l + j], j = 0..4, of the
+// current node (b_4 is lane l+1's b_0; cdf[255] = 65536 and lane 63 has no
+// b_4).  The symbol s is the last index with r * cdf[s] <= code (r, cdf <
+// 2^17, so 24-bit multiplies are exact).  Every lane resolves the candidate
+// inside its own four entries (lo, freq) with compares and selects; the
+// owning lane is popcount(ballot(r * b_0 <= code)) - 1 (lane 0 always
+// qualifies, cdf[0] = 0), and one readlane brings its packed (lo, freq) to
+// the scalar coder state.  A corrupt stream is one where no symbol fits
+// (code >= r * 2^16): lane 63 then resolves to lo = 65536, freq = 0, the
+// range becomes 0 and stays 0, which is checked once per block.  Decoded
+// codes are collected one per lane and stored kDecBlock at a time.
 // Chunk.pad_ carries the payload length in bytes, Chunk.scratch its offset.
 // ---------------------------------------------------------------------------
 constexpr int kDecBlock = 32;
@@ -157,11 +158,19 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
                                                   uint32_t* __restrict__ csum, uint32_t* __restrict__ err,
                                                   int lds_words) {
   extern __shared__ uint32_t buf[];
-  __shared__ uint2 rows[kDecBlock][65];  // entry 64 pads the neighbour read of lane 63
   const Chunk ch = chunks[blockIdx.x];
   const int lane = threadIdx.x;
   const uint32_t len = (uint32_t)ch.pad_;
   const uint8_t* src = payload + ch.scratch;
+  const int n = ch.count;
+  const int64_t node0 = ch.node0;
+  const int last = max(n - 1, 0);
+  // rows of the first two blocks in flight before the payload is staged
+  uint2 ta[kDecBlock], tb[kDecBlock];
+#pragma unroll
+  for (int k = 0; k < kDecBlock; k++) ta[k] = ld_row(cdf16, node0 + min(k, last), lane);
+#pragma unroll
+  for (int k = 0; k < kDecBlock; k++) tb[k] = ld_row(cdf16, node0 + min(kDecBlock + k, last), lane);
   for (int w = lane; w < lds_words; w += 64) {
     uint32_t v = 0;
 #pragma unroll
@@ -171,7 +180,6 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
     }
     buf[w] = v;
   }
-  if (lane < kDecBlock) rows[lane][64] = make_uint2(0u, 0u);
   __syncthreads();
   uint32_t pw[PW > 0 ? PW : 1];
 #pragma unroll
@@ -206,72 +214,58 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   nb -= 5;
   uint32_t range = 0xFFFFFFFFu;
 
-  const int n = ch.count;
-  const int64_t node0 = ch.node0;
-  bool bad = false;
   uint32_t kids = 0;  // children announced by the codes this lane stored
-  uint2 t[kDecBlock];
-#pragma unroll
-  for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(k, max(n - 1, 0)), lane);
   const bool last_lane = lane == 63;
-  for (int base = 0; base < n && !bad; base += kDecBlock) {
+  bool bad = false;
+
+  // one block of up to kDecBlock symbols from the rows in t (fully unrolled:
+  // row k is register t[k]); then t is reloaded with the block two ahead
+  auto block = [&](uint2 (&t)[kDecBlock], int base) {
     const int cnt = min(kDecBlock, n - base);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kDecBlock; k++) rows[k][lane] = t[k];
-    __syncthreads();
-    {
-      const int nbk = base + kDecBlock;
-      const int last = max(n - 1, 0);
-#pragma unroll
-      for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(nbk + k, last), lane);
-    }
-    uint2 nxt = rows[0][lane];
-    uint32_t nx4 = rows[0][lane + 1].x;
     uint32_t cv = 0;  // decoded code k of this block in lane k
-    uint32_t badv = 0;
-    for (int k = 0; k < cnt; k++) {
-      const uint2 row = nxt;
-      const uint32_t x4 = nx4;
-      const int kn = min(k + 1, kDecBlock - 1);
-      nxt = rows[kn][lane];
-      nx4 = rows[kn][lane + 1].x;
-      if (nb < 2) refill();
-      code = (uint32_t)__builtin_amdgcn_readfirstlane((int)code);
-      range = (uint32_t)__builtin_amdgcn_readfirstlane((int)range);
-      const uint32_t r = range >> 16;
-      // this lane's boundaries; slot 255 is the total 65536, and lane 63 has no b_4
-      const uint32_t b0 = row.x & 0xFFFFu, b1 = row.x >> 16, b2 = row.y & 0xFFFFu;
-      const uint32_t b3 = last_lane ? 65536u : (row.y >> 16);
-      const uint32_t b4 = last_lane ? 65536u : (x4 & 0xFFFFu);
-      const bool m0 = __umul24(r, b0) <= code;
-      const bool m1 = __umul24(r, b1) <= code;
-      const bool m2 = __umul24(r, b2) <= code;
-      const bool m3 = __umul24(r, b3) <= code;
-      const uint32_t lo = m3 ? b3 : (m2 ? b2 : (m1 ? b1 : b0));
-      const uint32_t hi = m3 ? b4 : (m2 ? b3 : (m1 ? b2 : b1));
-      const uint32_t sub = (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
-      // lanes 0..L have b_0 <= code / r; lane 0 always (cdf[0] = 0)
-      const int L = max((int)__popcll(__ballot(m0)) - 1, 0);
-      const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)(lo | ((hi - lo) << 16)), L);
-      code -= r * (P & 0xFFFFu);
-      range = r * (P >> 16);
-      // a valid stream keeps code < range; anything else is corrupt
-      badv |= (uint32_t)(((uint64_t)range - (uint64_t)code - 1ull) >> 63);
-      // renormalise: range >= 2^8 here, so take 0, 1 or 2 bytes
-      const uint32_t sh = range < (1u << 16) ? 16u : (range < (1u << 24) ? 8u : 0u);
-      code = (uint32_t)((((uint64_t)code << 32) | (bb >> 32)) >> (32 - sh));
-      bb <<= sh;
-      nb -= sh >> 3;
-      range <<= sh;
-      const int sym = 4 * L + __builtin_amdgcn_readlane((int)sub, L);
-      cv = lane == k ? (uint32_t)(sym + 1) : cv;
+#pragma unroll
+    for (int k = 0; k < kDecBlock; k++) {
+      if (k < cnt) {
+        const uint2 row = t[k];
+        const uint32_t nx = (uint32_t)__builtin_amdgcn_mov_dpp((int)row.x, 0x130, 0xF, 0xF, false);  // lane+1
+        if (nb < 2) refill();
+        const uint32_t r = range >> 16;
+        const uint32_t b0 = row.x & 0xFFFFu, b1 = row.x >> 16, b2 = row.y & 0xFFFFu;
+        const uint32_t b3 = last_lane ? 65536u : (row.y >> 16);
+        const uint32_t b4 = last_lane ? 65536u : (nx & 0xFFFFu);
+        const bool m0 = __umul24(r, b0) <= code;
+        const bool m1 = __umul24(r, b1) <= code;
+        const bool m2 = __umul24(r, b2) <= code;
+        const bool m3 = __umul24(r, b3) <= code;
+        const uint32_t lo = m3 ? b3 : (m2 ? b2 : (m1 ? b1 : b0));
+        const uint32_t hi = m3 ? b4 : (m2 ? b3 : (m1 ? b2 : b1));
+        const uint32_t sub = (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
+        const int L = (int)__popcll(__ballot(m0)) - 1;
+        const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)(lo | ((hi - lo) << 16)), L);
+        code -= r * (P & 0xFFFFu);
+        range = r * (P >> 16);
+        // renormalise: a valid step leaves range >= 2^8, so take 0, 1 or 2 bytes
+        const uint32_t sh = range < (1u << 16) ? 16u : (range < (1u << 24) ? 8u : 0u);
+        code = (uint32_t)((((uint64_t)code << 32) | (bb >> 32)) >> (32 - sh));
+        bb <<= sh;
+        nb -= sh >> 3;
+        range <<= sh;
+        const int sym = 4 * L + __builtin_amdgcn_readlane((int)sub, L);
+        cv = lane == k ? (uint32_t)(sym + 1) : cv;
+      }
     }
-    bad = badv != 0;
+    bad = range == 0u;
     if (!bad && lane < cnt) {
       codes[node0 + base + lane] = (uint8_t)cv;
       kids += __popc(cv & 0xFFu);
     }
+    const int nbk = base + 2 * kDecBlock;
+#pragma unroll
+    for (int k = 0; k < kDecBlock; k++) t[k] = ld_row(cdf16, node0 + min(nbk + k, last), lane);
+  };
+  for (int base = 0; base < n && !bad; base += 2 * kDecBlock) {
+    block(ta, base);
+    if (base + kDecBlock < n && !bad) block(tb, base + kDecBlock);
   }
   if (bad && lane == 0) atomicOr(err, ERR_CORRUPT);
   if (csum != nullptr) {
