@@ -8,7 +8,10 @@ cycle through the 8 seeded scans of that workload.  Reported:
   timed steps, with frames/s, per-frame p50/p99 ms, encode and decode rates;
 * batched vs plain: the uneven 32-frame batch (16/32/64 beams, 14-level
   octrees, C = 32) through the batched calls against the same frames one by
-  one;
+  one, and 8 frames of the 128-beam, 18-level, C = 64 workload per batch;
+* served: a Poisson stream of encode/decode requests from 24 simulated
+  sensors (16-128 beams, 14-18 levels, C = 32/64) through the continuous-
+  batching server, with p50/p99 request latency and sustained Mpts/s;
 * roofline of the dominant kernel, timed with HIP events on the library's
   stream, against MI355X peaks;
 * cpu_baseline: the CPU oracle on one frame of the same workload.
@@ -39,7 +42,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--chunk-log2", type=int, default=8)
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparisons")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) run")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
@@ -216,7 +221,61 @@ def main():
                           "points": bpts, "batched_mpts_s": round(bpts / tb / 1e6, 3),
                           "plain_mpts_s": round(bpts / tp / 1e6, 3), "speedup": round(tp / tb, 3),
                           "same_lengths": plain_lens == ln}
+        res["batched_128beam"] = _bench_128beam(lpcc, synth, torch, dev, ctx)
+    if not args.no_serve:
+        from paper_2603_25260_amd import serve
+        rep_ = serve.run(duration_s=args.serve_seconds, n_sensors=24, rate_hz=10.0, seed=5000, slots=4,
+                         max_batch=4, chunk_log2=cl, frames_per_sensor=1, verify=False, realtime=True)
+        res["served"] = {"workload": "Poisson arrivals, 24 sensors x 10 Hz, 16-128 beams, 14-18 levels, "
+                                     "C=32 (D<=16) / 64, 50% encode / 50% decode",
+                         "seconds": args.serve_seconds, **{k: rep_[k] for k in (
+                             "requests", "ok", "p50_ms", "p99_ms", "sustained_mpts_s", "offered_req_s",
+                             "mean_batch", "slots", "max_batch")}}
     print(json.dumps(res))
+
+
+def _bench_128beam(lpcc, synth, torch, dev, ctx):
+    """8 frames of the 128-beam, 18-level (1 mm), C = 64 workload: batched
+    (one launch per level family for all 8) against the plain per-frame path;
+    the stream of the first frame is checked against the oracle's digest."""
+    import hashlib
+    cfg = synth.CONFIGS["cfg4"]
+    D, C = cfg.scan.D, cfg.C
+    model = lpcc.Model(synth.make_weights(cfg.weight_seed, C, D, cfg.n_deep), 0)
+    frames = [synth.make_scan(cfg.scan, s) for s in cfg.seeds[:8]]
+    bd = [torch.from_numpy(f).to(dev) for f in frames]
+    pts = sum(len(f) for f in frames)
+    outs = [torch.zeros(len(f) * 8 + 65536, dtype=torch.uint8, device=dev) for f in frames]
+    decs = [torch.zeros((len(f), 3), dtype=torch.int32, device=dev) for f in frames]
+    ln, st = lpcc.encode_batch(ctx, model, bd, 8, outs=outs)
+    lpcc.decode_batch(ctx, model, outs, lengths=ln, outs=decs)
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ln, st = lpcc.encode_batch(ctx, model, bd, 8, outs=outs)
+        nout, st2 = lpcc.decode_batch(ctx, model, outs, lengths=ln, outs=decs)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    assert st == [0] * 8 and st2 == [0] * 8
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for i in range(8):
+            n = lpcc.encode_frame(ctx, model, bd[i], 8, out=outs[i])
+            lpcc.decode_frame(ctx, model, outs[i], length=n, out=decs[i])
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / reps
+    exact = None
+    dig = os.path.join(ROOT, "tests", "golden", "digests.json")
+    if os.path.exists(dig):
+        want = json.load(open(dig)).get("cfg4", {}).get(str(cfg.seeds[0]))
+        if want:
+            got = hashlib.sha256(bytes(outs[0][:ln[0]].cpu().numpy())).hexdigest()
+            exact = got == want["stream_c8"]["sha256"]
+    return {"workload": "8 frames, 128-beam x 2048-az, 18-level octree (1 mm), C=64, 5 re-densified depths",
+            "points": pts, "batched_mpts_s": round(pts / tb / 1e6, 3), "plain_mpts_s": round(pts / tp / 1e6, 3),
+            "speedup": round(tp / tb, 3), "batched_ms_per_frame": round(tb / 8 * 1e3, 3),
+            "bit_exact_first_frame": exact}
 
 
 # HBM bytes per k_predict launch (read + write, scaled FETCH_SIZE / WRITE_SIZE

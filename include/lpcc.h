@@ -192,6 +192,24 @@ int lpcc_timing_enable(lpcc_ctx* c, const char* name);
 int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* units);
 
 /*
+ * Tile shapes of the gather-GEMM and up-convolution kernels.  A wave computes
+ * rb blocks of 16 rows (rb = 1, 2 or 4); larger rb re-uses every weight
+ * fragment across more rows and suits large launches, rb = 1 has the
+ * shortest per-wave chain and suits small ones.  rb = 0 (the default)
+ * autotunes: the first launch of every (kernel, widths, log2 rows) class on
+ * this context runs each candidate, timed with HIP events on the context's
+ * stream, and later launches of the class use the fastest.  Every choice
+ * computes identical outputs.  Returns LPCC_E_INVAL for other values.
+ *
+ * lpcc_ctx_tuning reports the table: 6 ints per class (kind 0 gemm / 1 up,
+ * mode, cin, cout, log2 rows, chosen rb or 0 while undecided) into out
+ * (host, 6 * cap ints), the number of classes into *n; LPCC_E_CAPACITY when
+ * cap is too small (the first cap rows are written).
+ */
+int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb);
+int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n);
+
+/*
  * The integer exponent table of the softmax (Eq. 15) as the library builds
  * it: out[i] = round(2^15 e^{-i/16}), i = 0..255, computed on the host with
  * an integer recurrence.  Host memory; needs no device.

@@ -57,6 +57,38 @@ __device__ __forceinline__ int requant_l(int acc, const LayerDev& L) {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// Every device array is global memory.  Pointers that arrive inside
+// descriptor structs lose that fact, and the compiler would fall back to
+// FLAT accesses (which also count against the LDS counter, so every LDS wait
+// would drain all outstanding memory loads); gp() restores the address space.
+#define GAS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GAS T* gp(const T* p) { return (const GAS T*)p; }
+template <class T>
+__device__ __forceinline__ GAS T* gp(T* p) { return (GAS T*)p; }
+
+// A layer descriptor read from global memory, field by field
+__device__ __forceinline__ LayerDev load_layer(const LayerDev* p) {
+  const GAS LayerDev* q = (const GAS LayerDev*)p;
+  LayerDev L;
+  L.Wp = q->Wp;
+  L.Wr = q->Wr;
+  L.bias = q->bias;
+  L.zc = q->zc;
+  L.m_pos = q->m_pos;
+  L.m_neg = q->m_neg;
+  L.r = q->r;
+  L.z_out = q->z_out;
+  L.taps = q->taps;
+  L.cin = q->cin;
+  L.cout = q->cout;
+  L.ksteps = q->ksteps;
+  L.npad = q->npad;
+  L.pad_ = q->pad_;
+  L.rnd = q->rnd;
+  return L;
+}
+
 __device__ __forceinline__ v4i mfma16(v4i a, v4i b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
@@ -181,10 +213,11 @@ hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* t
 
 // GEMM families; `mode` selects the row source
 enum GemmMode { G_CONV = 0, G_DENSE = 1, G_DOWN = 2 };
+// rb: 16-row blocks per wave (1, 2 or 4); tiles then cover 64 * rb rows
 hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs_dev, const Tile* tiles_dev,
-                       int ntiles, const GemmArg& one, hipStream_t s);
+                       int ntiles, const GemmArg& one, int rb, hipStream_t s);
 hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
-                     hipStream_t s);
+                     int rb, hipStream_t s);
 hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, const GemmArg& one,
                       hipStream_t s);
 hipError_t launch_predict(int C, int mode, const PredSeg* segs_dev, const Tile* tiles_dev, int ntiles,

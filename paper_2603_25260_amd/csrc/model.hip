@@ -17,7 +17,7 @@ namespace lpcc {
 // l%16, 16 consecutive k of group l/16; B lane l holds column l%16, the same
 // k; the accumulator lane l holds rows 4(l/16)+i (i = 0..3) of column l%16.
 
-__device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const v4i*)p; }
+__device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const GAS v4i*)p; }
 
 // Epilogue: one wave's 16 x COUT int32 tile staged in LDS, then every lane
 // handles a contiguous run of COUT/4 columns of one row.
@@ -44,26 +44,38 @@ struct Taps<G_DOWN> { static constexpr int n = 8; };
 
 template <int MODE>
 __device__ __forceinline__ int src_row(const GemmSeg& S, int row, int tap) {
-  if (MODE == G_CONV) return S.kmap[(int64_t)tap * S.kstride + row];
+  if (MODE == G_CONV) return gp(S.kmap)[(int64_t)tap * S.kstride + row];
   if (MODE == G_DENSE) return row;
-  uint32_t code = S.code[row];
+  uint32_t code = gp(S.code)[row];
   if (!((code >> tap) & 1u)) return -1;
-  const int cr = S.cstart[row] + __popc(code & ((1u << tap) - 1u));
+  const int cr = gp(S.cstart)[row] + __popc(code & ((1u << tap) - 1u));
   return cr < S.child_rows ? cr : -1;  // out of range only for a corrupt stream
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
+// b % 8), each with its own L2.  Tile t of a launch goes to the block that
+// gives every XCD one contiguous run of tiles: neighbouring tiles (close in
+// Morton order, sharing most of their 3x3x3 neighbours) then hit one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile() {
+  const int G = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q = G / kXcds, rem = G % kXcds, x = b % kXcds;
+  return x * q + min(x, rem) + b / kXcds;
 }
 
 // The block's segment, layer and first row: from the kernel arguments for a
 // single-segment launch, else from the tile and segment arrays.
 __device__ __forceinline__ int pick_seg(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
-                                        const GemmArg& A, GemmSeg& S, LayerDev& L) {
+                                        const GemmArg& A, GemmSeg& S, LayerDev& L, int tile_rows = 64) {
+  const int t = xcd_tile();
   if (A.one) {
     S = A.seg;
     L = A.L;
-    return (int)blockIdx.x * 64;
+    return t * tile_rows;
   }
-  const Tile tl = tiles[blockIdx.x];
+  const Tile tl = tiles[t];
   S = segs[tl.seg];
-  L = *S.L;
+  L = load_layer(S.L);
   return tl.row0;
 }
 
@@ -94,13 +106,13 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
   const bool ov = orow < S.rows;
   int bia[PER];
 #pragma unroll
-  for (int q = 0; q < PER; q++) bia[q] = L.bias[ec + q];
+  for (int q = 0; q < PER; q++) bia[q] = gp(L.bias)[ec + q];
   int8_t res[PER];
 #pragma unroll
   for (int q = 0; q < PER; q++) res[q] = 0;
   if (S.resid != nullptr && ov) {
 #pragma unroll
-    for (int q = 0; q < PER; q++) res[q] = S.resid[(int64_t)orow * S.resid_stride + ec + q];
+    for (int q = 0; q < PER; q++) res[q] = gp(S.resid)[(int64_t)orow * S.resid_stride + ec + q];
   }
 
   v4i acc[NB];
@@ -115,7 +127,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
     const int tap = k0 / CIN;
     src[s] = (rv && tap < TAPS) ? src_row<MODE>(S, row, tap) : -1;
   }
-  const v4i* Wp = (const v4i*)L.Wp;
+  const GAS v4i* Wp = (const GAS v4i*)L.Wp;
 #pragma unroll
   for (int s = 0; s < KS; s++) {
     const int k0 = 64 * s + 16 * g;
@@ -145,7 +157,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
       for (int t = 0; t < TAPS; t++) {
         if (src_row<MODE>(S, orow, t) < 0) continue;
 #pragma unroll
-        for (int q = 0; q < PER; q++) zsum[q] += L.zc[t * L.npad + ec + q];
+        for (int q = 0; q < PER; q++) zsum[q] += gp(L.zc)[t * L.npad + ec + q];
       }
     }
     int8_t outv[PER];
@@ -159,19 +171,176 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
       }
       outv[q] = (int8_t)y;
     }
-    int8_t* dst = S.out + (int64_t)orow * S.out_stride + ec;
+    GAS int8_t* dst = gp(S.out) + (int64_t)orow * S.out_stride + ec;
 #pragma unroll
     for (int q = 0; q < PER; q++) dst[q] = outv[q];
   }
 }
 
+// Register-blocked variant for large launches: a wave computes RB blocks of
+// 16 rows, so every weight fragment it loads serves RB MFMAs (the weights
+// are re-read from L2 by every wave; with RB = 1 that traffic exceeds the
+// gathered activations several times over for C >= 32).  The neighbour
+// table of the wave's rows is staged in LDS first (one coalesced load per
+// tap), then each k-step gathers the RB A fragments through it.
+template <int MODE, int CIN, int COUT, int RB>
+__global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                                 const GemmArg A) {
+  constexpr int TAPS = Taps<MODE>::n;
+  constexpr int K = TAPS * CIN;
+  constexpr int KS = (K + 63) / 64;
+  constexpr int NB = COUT / 16;
+  constexpr int WR = 16 * RB;  // rows per wave
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0 && (CIN & (CIN - 1)) == 0, "widths");
+  static_assert(WR <= 64, "at most 64 rows per wave");
+  __shared__ Stage<COUT> st[4];
+  __shared__ int32_t skm[MODE == G_CONV ? 4 : 1][MODE == G_CONV ? TAPS : 1][WR];
+
+  GemmSeg S;
+  LayerDev L;
+  const int tile_row0 = pick_seg(segs, tiles, A, S, L, 4 * WR);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int wrow0 = tile_row0 + wave * WR;
+
+  // epilogue operands first
+  constexpr int PER = COUT / 4;
+  const int er = lane >> 2, ec = (lane & 3) * PER;
+  int bia[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) bia[q] = gp(L.bias)[ec + q];
+  int8_t res[RB][PER];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+    const int orow = wrow0 + 16 * rb + er;
+#pragma unroll
+    for (int q = 0; q < PER; q++) res[rb][q] = 0;
+    if (S.resid != nullptr && orow < S.rows) {
+#pragma unroll
+      for (int q = 0; q < PER; q++) res[rb][q] = gp(S.resid)[(int64_t)orow * S.resid_stride + ec + q];
+    }
+  }
+
+  // per row block: the row of this lane, and for the child convolution its
+  // parent's code and first child
+  uint32_t pcode[RB];
+  int pcs[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+    const int row = wrow0 + 16 * rb + r;
+    pcode[rb] = 0u;
+    pcs[rb] = 0;
+    if (MODE == G_DOWN && row < S.rows) {
+      pcode[rb] = gp(S.code)[row];
+      pcs[rb] = gp(S.cstart)[row];
+    }
+  }
+  if (MODE == G_CONV) {
+    if (lane < WR) {
+      const int row = wrow0 + lane;
+      const bool ok = row < S.rows;
+#pragma unroll
+      for (int t = 0; t < TAPS; t++) skm[wave][t][lane] = ok ? gp(S.kmap)[(int64_t)t * S.kstride + row] : -1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  auto src_of = [&](int rb, int tap) -> int {
+    const int row = wrow0 + 16 * rb + r;
+    if (tap >= TAPS || row >= S.rows) return -1;
+    if (MODE == G_CONV) return skm[MODE == G_CONV ? wave : 0][MODE == G_CONV ? tap : 0][16 * rb + r];
+    if (MODE == G_DENSE) return row;
+    if (!((pcode[rb] >> tap) & 1u)) return -1;
+    const int cr = pcs[rb] + __popc(pcode[rb] & ((1u << tap) - 1u));
+    return cr < S.child_rows ? cr : -1;
+  };
+
+  v4i acc[RB][NB];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) acc[rb][nb] = v4i{0, 0, 0, 0};
+  const GAS v4i* Wp = (const GAS v4i*)L.Wp;
+  constexpr int LC = __builtin_ctz(CIN);
+#pragma unroll 2
+  for (int s = 0; s < KS; s++) {
+    const int k0 = 64 * s + 16 * g;
+    const int tap = k0 >> LC, c0 = k0 & (CIN - 1);
+    v4i a[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++) {
+      const int sr = src_of(rb, tap);
+      a[rb] = v4i{0, 0, 0, 0};
+      if (sr >= 0)
+        a[rb] = c0 < S.split ? ld16(S.in + (int64_t)sr * S.in_stride + c0)
+                             : ld16(S.in2 + (int64_t)sr * S.in2_stride + (c0 - S.split));
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+      const v4i b = Wp[((int64_t)s * NB + nb) * 64 + lane];
+#pragma unroll
+      for (int rb = 0; rb < RB; rb++) acc[rb][nb] = mfma16(a[rb], b, acc[rb][nb]);
+    }
+  }
+
+  // epilogue, one row block at a time through the wave's LDS stage
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) st[wave].v[4 * g + i][16 * nb + r] = acc[rb][nb][i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int orow = wrow0 + 16 * rb + er;
+    if (orow < S.rows) {
+      int zsum[PER];
+#pragma unroll
+      for (int q = 0; q < PER; q++) zsum[q] = 0;
+      if (L.zc != nullptr) {
+        for (int t = 0; t < TAPS; t++) {
+          int present;
+          if (MODE == G_CONV) present = skm[MODE == G_CONV ? wave : 0][MODE == G_CONV ? t : 0][16 * rb + er] >= 0;
+          else present = src_row<MODE>(S, orow, t) >= 0;
+          if (!present) continue;
+#pragma unroll
+          for (int q = 0; q < PER; q++) zsum[q] += gp(L.zc)[t * L.npad + ec + q];
+        }
+      }
+      int8_t outv[PER];
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        int y = requant_l(st[wave].v[er][ec + q] + bia[q] + zsum[q], L);
+        if (S.resid != nullptr) {
+          y += res[rb][q];
+          y = y < -128 ? -128 : (y > 127 ? 127 : y);
+        }
+        outv[q] = (int8_t)y;
+      }
+      GAS int8_t* dst = gp(S.out) + (int64_t)orow * S.out_stride + ec;
+#pragma unroll
+      for (int q = 0; q < PER; q++) dst[q] = outv[q];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 template <int MODE>
 static hipError_t launch_gemm_mode(int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
-                                   const GemmArg& A, hipStream_t s) {
-#define LPCC_G(CI, CO)                                                                          \
-  if (cin == CI && cout == CO) {                                                                \
-    hipLaunchKernelGGL((k_gemm<MODE, CI, CO>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);  \
-    return hipGetLastError();                                                                   \
+                                   const GemmArg& A, int rb, hipStream_t s) {
+#define LPCC_G(CI, CO)                                                                                    \
+  if (cin == CI && cout == CO) {                                                                          \
+    if (rb == 4)                                                                                          \
+      hipLaunchKernelGGL((k_gemm_rb<MODE, CI, CO, 4>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);    \
+    else if (rb == 2)                                                                                     \
+      hipLaunchKernelGGL((k_gemm_rb<MODE, CI, CO, 2>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);    \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_gemm<MODE, CI, CO>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);          \
+    return hipGetLastError();                                                                             \
   }
   LPCC_G(16, 16) LPCC_G(32, 16) LPCC_G(32, 32) LPCC_G(64, 32) LPCC_G(64, 64) LPCC_G(128, 64)
 #undef LPCC_G
@@ -179,11 +348,11 @@ static hipError_t launch_gemm_mode(int cin, int cout, const GemmSeg* segs, const
 }
 
 hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
-                       const GemmArg& A, hipStream_t s) {
+                       const GemmArg& A, int rb, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (mode == G_CONV) return launch_gemm_mode<G_CONV>(cin, cout, segs, tiles, ntiles, A, s);
-  if (mode == G_DENSE) return launch_gemm_mode<G_DENSE>(cin, cout, segs, tiles, ntiles, A, s);
-  if (mode == G_DOWN) return launch_gemm_mode<G_DOWN>(cin, cout, segs, tiles, ntiles, A, s);
+  if (mode == G_CONV) return launch_gemm_mode<G_CONV>(cin, cout, segs, tiles, ntiles, A, rb, s);
+  if (mode == G_DENSE) return launch_gemm_mode<G_DENSE>(cin, cout, segs, tiles, ntiles, A, rb, s);
+  if (mode == G_DOWN) return launch_gemm_mode<G_DOWN>(cin, cout, segs, tiles, ntiles, A, rb, s);
   return hipErrorInvalidValue;
 }
 
@@ -192,55 +361,67 @@ hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs, const T
 // out block o (columns oC..oC+C-1) is child slot o; occupied slots only,
 // child row = cstart[p] + rank of o among the set bits.
 // ---------------------------------------------------------------------------
-template <int C>
+template <int C, int RB>
 __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
                                             const GemmArg A) {
   constexpr int KS = (C + 8 + 63) / 64;
   constexpr int NBS = C / 16;          // column blocks per child slot
   constexpr int NBT = 8 * NBS;         // column blocks of the layer
+  constexpr int WR = 16 * RB;          // parent rows per wave
   // per wave: the accumulator tile of one slot, and the parents' codes / first children
   __shared__ int32_t st[4][16][C + 1];
-  __shared__ uint32_t pc[4][16];
-  __shared__ int32_t ps[4][16];
+  __shared__ uint32_t pc[4][WR];
+  __shared__ int32_t ps[4][WR];
 
   GemmSeg S;
   LayerDev L;
-  const int tile_row0 = pick_seg(segs, tiles, A, S, L);
+  const int tile_row0 = pick_seg(segs, tiles, A, S, L, 4 * WR);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  const int row0 = tile_row0 + wave * 16;
-  const int row = row0 + r;
-  const bool rv = row < S.rows;
-  const uint32_t code = rv ? S.code[row] : 0u;
+  const int wrow0 = tile_row0 + wave * WR;
+  uint32_t code[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+    const int row = wrow0 + 16 * rb + r;
+    code[rb] = row < S.rows ? gp(S.code)[row] : 0u;
+    if (g == 0) {
+      pc[wave][16 * rb + r] = code[rb];
+      ps[wave][16 * rb + r] = row < S.rows ? gp(S.cstart)[row] : 0;
+    }
+  }
   // the output loop below gives every lane the fixed column lane % C
   static_assert(64 % C == 0, "C must divide the wave width");
   const int ocol = lane % C;
   int bia[8];
 #pragma unroll
-  for (int o = 0; o < 8; o++) bia[o] = L.bias[o * C + ocol];
-  if (g == 0) {
-    pc[wave][r] = code;
-    ps[wave][r] = rv ? S.cstart[row] : 0;
-  }
+  for (int o = 0; o < 8; o++) bia[o] = gp(L.bias)[o * C + ocol];
 
-  v4i a[KS];
+  v4i a[RB][KS];
 #pragma unroll
-  for (int s = 0; s < KS; s++) {
-    const int k0 = 64 * s + 16 * g;
-    a[s] = v4i{0, 0, 0, 0};
-    if (rv && k0 < C) {
-      a[s] = ld16(S.in + (int64_t)row * S.in_stride + k0);
-    } else if (rv && k0 == C) {  // occupancy bits as int8 {0,127}, then zeros
-      uint32_t w0 = 0, w1 = 0;
+  for (int rb = 0; rb < RB; rb++) {
+    const int row = wrow0 + 16 * rb + r;
+    const bool rv = row < S.rows;
 #pragma unroll
-      for (int b = 0; b < 4; b++) {
-        if ((code >> b) & 1u) w0 |= 127u << (8 * b);
-        if ((code >> (b + 4)) & 1u) w1 |= 127u << (8 * b);
+    for (int s = 0; s < KS; s++) {
+      const int k0 = 64 * s + 16 * g;
+      a[rb][s] = v4i{0, 0, 0, 0};
+      if (rv && k0 < C) {
+        a[rb][s] = ld16(S.in + (int64_t)row * S.in_stride + k0);
+      } else if (rv && k0 == C) {  // occupancy bits as int8 {0,127}, then zeros
+        uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          if ((code[rb] >> b) & 1u) w0 |= 127u << (8 * b);
+          if ((code[rb] >> (b + 4)) & 1u) w1 |= 127u << (8 * b);
+        }
+        a[rb][s] = v4i{(int)w0, (int)w1, 0, 0};
       }
-      a[s] = v4i{(int)w0, (int)w1, 0, 0};
     }
   }
-  const v4i* Wp = (const v4i*)L.Wp;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const GAS v4i* Wp = (const GAS v4i*)L.Wp;
   // weights of slot o+1 are in flight while slot o is computed
   v4i wb[2][KS][NBS];
 #pragma unroll
@@ -257,51 +438,60 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
         for (int nb = 0; nb < NBS; nb++)
           wb[(o + 1) & 1][s][nb] = Wp[((int64_t)s * NBT + (o + 1) * NBS + nb) * 64 + lane];
     }
-    // rows of this wave's tile whose parent has child slot o (wave-uniform)
-    const uint32_t m = (uint32_t)(__ballot((code >> o) & 1u) & 0xFFFFull);
-    if (m == 0u) continue;
-    v4i acc[NBS];
 #pragma unroll
-    for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
+    for (int rb = 0; rb < RB; rb++) {
+      // rows of this block whose parent has child slot o (wave-uniform)
+      const uint32_t m = (uint32_t)(__ballot((code[rb] >> o) & 1u) & 0xFFFFull);
+      if (m == 0u) continue;
+      v4i acc[NBS];
 #pragma unroll
-    for (int s = 0; s < KS; s++)
+      for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
 #pragma unroll
-      for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(a[s], wb[o & 1][s][nb], acc[nb]);
+      for (int s = 0; s < KS; s++)
 #pragma unroll
-    for (int nb = 0; nb < NBS; nb++)
+        for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(a[rb][s], wb[o & 1][s][nb], acc[nb]);
 #pragma unroll
-      for (int i = 0; i < 4; i++) st[wave][4 * g + i][16 * nb + r] = acc[nb][i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // only the occupied (row, slot) outputs: k rows x C columns over the wave
-    const int k = __popc(m);
-    for (int v = lane; v < k * C; v += 64) {
-      const int j = v / C, col = v - j * C;
-      // row of the j-th set bit of m
-      int pos = 0;
+      for (int nb = 0; nb < NBS; nb++)
 #pragma unroll
-      for (int w = 8; w >= 1; w >>= 1)
-        if (__popc(m & ((1u << (pos + w)) - 1u)) <= j) pos += w;
-      const uint32_t pcode = pc[wave][pos];
-      const int crow = ps[wave][pos] + __popc(pcode & ((1u << o) - 1u));
-      if (crow >= S.child_rows) continue;  // only for a corrupt stream
-      const int y = requant_l(st[wave][pos][col] + bia[o], L);
-      S.out[(int64_t)crow * S.out_stride + col] = (int8_t)y;
+        for (int i = 0; i < 4; i++) st[wave][4 * g + i][16 * nb + r] = acc[nb][i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // only the occupied (row, slot) outputs: k rows x C columns over the wave
+      const int k = __popc(m);
+      for (int v = lane; v < k * C; v += 64) {
+        const int j = v / C, col = v - j * C;
+        // row of the j-th set bit of m
+        int pos = 0;
+#pragma unroll
+        for (int w = 8; w >= 1; w >>= 1)
+          if (__popc(m & ((1u << (pos + w)) - 1u)) <= j) pos += w;
+        const uint32_t pcode = pc[wave][16 * rb + pos];
+        const int crow = ps[wave][16 * rb + pos] + __popc(pcode & ((1u << o) - 1u));
+        if (crow >= S.child_rows) continue;  // only for a corrupt stream
+        const int y = requant_l(st[wave][pos][col] + bia[o], L);
+        gp(S.out)[(int64_t)crow * S.out_stride + col] = (int8_t)y;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
-hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, hipStream_t s) {
+hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, int rb,
+                     hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (C == 16) hipLaunchKernelGGL((k_up<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else if (C == 32) hipLaunchKernelGGL((k_up<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else if (C == 64) hipLaunchKernelGGL((k_up<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+#define LPCC_U(CC)                                                                                 \
+  if (C == CC) {                                                                                   \
+    if (rb == 4) hipLaunchKernelGGL((k_up<CC, 4>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A); \
+    else if (rb == 2) hipLaunchKernelGGL((k_up<CC, 2>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A); \
+    else hipLaunchKernelGGL((k_up<CC, 1>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);         \
+    return hipGetLastError();                                                                      \
+  }
+  LPCC_U(16) LPCC_U(32) LPCC_U(64)
+#undef LPCC_U
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -318,11 +508,11 @@ __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, c
   for (int e = threadIdx.x; e < 64 * C; e += blockDim.x) {
     const int row = tile_row0 + (e >> cs), o = e & (C - 1);
     if (row >= S.rows) continue;
-    const uint32_t code = S.code[row];
-    int acc = L.bias[o];
+    const uint32_t code = gp(S.code)[row];
+    int acc = gp(L.bias)[o];
     for (int b = 0; b < 8; b++)
-      if ((code >> b) & 1u) acc += 127 * (int)L.Wr[b * C + o];
-    S.out[(int64_t)row * S.out_stride + o] = (int8_t)requant_l(acc, L);
+      if ((code >> b) & 1u) acc += 127 * (int)gp(L.Wr)[b * C + o];
+    gp(S.out)[(int64_t)row * S.out_stride + o] = (int8_t)requant_l(acc, L);
   }
 }
 
@@ -385,7 +575,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   __shared__ int32_t lut[256];
   __shared__ int8_t hs[4][16][64];
   __shared__ __attribute__((aligned(16))) uint16_t fs[MODE == P_ENCODE ? 1 : 4][16][256];
-  lut[threadIdx.x] = lut_g[threadIdx.x];
+  lut[threadIdx.x] = gp(lut_g)[threadIdx.x];
 
   PredSeg S;
   LayerDev L1, L2;
@@ -398,8 +588,8 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   } else {
     const Tile tl = tiles[blockIdx.x];
     S = segs[tl.seg];
-    L1 = *S.fc1;
-    L2 = *S.fc2;
+    L1 = load_layer(S.fc1);
+    L2 = load_layer(S.fc2);
     tile_row0 = tl.row0;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -413,7 +603,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   v4i a = v4i{0, 0, 0, 0};
   if (rv && 16 * g < C) a = ld16(S.F + (int64_t)row * C + 16 * g);
   v4i acc1[NB1];
-  const v4i* W1 = (const v4i*)L1.Wp;
+  const GAS v4i* W1 = (const GAS v4i*)L1.Wp;
 #pragma unroll
   for (int nb = 0; nb < NB1; nb++) acc1[nb] = mfma16(a, W1[nb * 64 + lane], v4i{0, 0, 0, 0});
   // requantise straight from the accumulator layout into the A layout of fc2
@@ -422,7 +612,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int col = 16 * nb + r;
-      hs[wave][4 * g + i][col] = (int8_t)requant_l(acc1[nb][i] + L1.bias[col], L1);
+      hs[wave][4 * g + i][col] = (int8_t)requant_l(acc1[nb][i] + gp(L1.bias)[col], L1);
     }
   if (C < 64) {  // zero the K padding (columns C..63 of the 16 rows)
     for (int k = lane; k < 16 * (64 - C); k += 64) hs[wave][k / (64 - C)][C + k % (64 - C)] = 0;
@@ -431,13 +621,13 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   v4i h = *(const v4i*)&hs[wave][r][16 * g];
 
   // fc2: 16 column blocks of 16 logits
-  const v4i* W2 = (const v4i*)L2.Wp;
+  const GAS v4i* W2 = (const GAS v4i*)L2.Wp;
   int lg[4][16];
 #pragma unroll
   for (int b = 0; b < 16; b++) {
     v4i acc = mfma16(h, W2[b * 64 + lane], v4i{0, 0, 0, 0});
     const int col = 16 * b + r;
-    const int bias = L2.bias[col];
+    const int bias = gp(L2.bias)[col];
 #pragma unroll
     for (int i = 0; i < 4; i++)
       lg[i][b] = col < kNSym ? requant_l(acc[i] + bias, L2) : -1000;
@@ -492,7 +682,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
       if (16 * b + r == arg[i]) f[b] += R;
 
     if (MODE == P_ENCODE) {
-      const int sym = nrow < S.rows ? (int)S.code[nrow] - 1 : 0;
+      const int sym = nrow < S.rows ? (int)gp(S.code)[nrow] - 1 : 0;
       int st_ = 0, fr = 0;
 #pragma unroll
       for (int b = 0; b < 16; b++) {
@@ -502,7 +692,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
       }
       st_ = red16_sum(st_);
       fr = red16_sum(fr);
-      if (r == 0 && nrow < S.rows) S.sf[nrow] = (uint32_t)st_ | ((uint32_t)fr << 16);
+      if (r == 0 && nrow < S.rows) gp(S.sf)[nrow] = (uint32_t)st_ | ((uint32_t)fr << 16);
     } else {
       // frequencies of row 4g+i into LDS for the row-wise prefix below
 #pragma unroll
@@ -549,16 +739,17 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
             const uint32_t hi = (r == 15 && k == 7) ? 0u : off + ex[2 * k + 1];
             o2[k] = (lo & 0xFFFFu) | (hi << 16);
           }
-          uint4* dst = (uint4*)(S.cdf16 + (int64_t)nrow * 256 + 16 * r);
-          dst[0] = make_uint4(o2[0], o2[1], o2[2], o2[3]);
-          dst[1] = make_uint4(o2[4], o2[5], o2[6], o2[7]);
+          GAS v4i* dst = (GAS v4i*)(S.cdf16 + (int64_t)nrow * 256 + 16 * r);
+          dst[0] = v4i{(int)o2[0], (int)o2[1], (int)o2[2], (int)o2[3]};
+          dst[1] = v4i{(int)o2[4], (int)o2[5], (int)o2[6], (int)o2[7]};
         } else {
           uint32_t o4[16];
 #pragma unroll
           for (int k = 0; k < 16; k++) o4[k] = (r == 15 && k == 15) ? 65536u : off + ex[k];
-          uint4* dst = (uint4*)(S.cdf32 + (int64_t)nrow * 256 + 16 * r);
+          GAS v4i* dst = (GAS v4i*)(S.cdf32 + (int64_t)nrow * 256 + 16 * r);
 #pragma unroll
-          for (int k = 0; k < 4; k++) dst[k] = make_uint4(o4[4 * k], o4[4 * k + 1], o4[4 * k + 2], o4[4 * k + 3]);
+          for (int k = 0; k < 4; k++)
+            dst[k] = v4i{(int)o4[4 * k], (int)o4[4 * k + 1], (int)o4[4 * k + 2], (int)o4[4 * k + 3]};
         }
       }
     }

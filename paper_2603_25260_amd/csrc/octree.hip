@@ -239,10 +239,11 @@ __device__ __forceinline__ uint64_t hmix(uint64_t k) {
 __device__ __forceinline__ void hash_put(uint64_t k, int32_t row, uint64_t* tkeys, int32_t* tvals, uint64_t mask) {
   uint64_t slot = hmix(k) & mask;
   for (uint64_t probe = 0; probe <= mask; probe++) {
-    unsigned long long prev = atomicCAS((unsigned long long*)&tkeys[slot], (unsigned long long)kEmpty,
-                                        (unsigned long long)k);
+    unsigned long long prev = kEmpty;
+    __hip_atomic_compare_exchange_strong((GAS unsigned long long*)&tkeys[slot], &prev, (unsigned long long)k,
+                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == kEmpty || prev == k) {
-      tvals[slot] = row;
+      gp(tvals)[slot] = row;
       return;
     }
     slot = (slot + 1) & mask;
@@ -271,7 +272,7 @@ __device__ __forceinline__ void kmap_one(const uint64_t* __restrict__ keys, int6
                                          uint64_t mask, int32_t* __restrict__ kmap, int64_t kstride) {
   int64_t i = gid / 27;
   int t = (int)(gid - i * 27);
-  uint64_t key = keys[i];
+  uint64_t key = gp(keys)[i];
   uint64_t low = j > 0 ? (key & ((1ull << (3 * j)) - 1)) : 0;
   uint64_t tag = key ^ low;
   int x = (int)compact3(low >> 2) + t / 9 - 1;
@@ -283,13 +284,13 @@ __device__ __forceinline__ void kmap_one(const uint64_t* __restrict__ keys, int6
     uint64_t q = tag | (spread3((uint32_t)x) << 2) | (spread3((uint32_t)y) << 1) | spread3((uint32_t)z);
     uint64_t slot = hmix(q) & mask;
     for (uint64_t probe = 0; probe <= mask; probe++) {
-      uint64_t v = tkeys[slot];
-      if (v == q) { r = tvals[slot]; break; }
+      uint64_t v = gp(tkeys)[slot];
+      if (v == q) { r = gp(tvals)[slot]; break; }
       if (v == kEmpty) break;
       slot = (slot + 1) & mask;
     }
   }
-  kmap[(int64_t)t * kstride + i] = r;
+  gp(kmap)[(int64_t)t * kstride + i] = r;
 }
 
 __global__ void k_kmap(const uint64_t* __restrict__ keys, int64_t n, int j, const uint64_t* __restrict__ tkeys,
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(kHashBlock) void k_hash_insert_multi(const HashJob*
   const HashJob J = jobs[job_of(jobs, njobs, false)];
   const int64_t i = (int64_t)((int)blockIdx.x - J.blk_insert) * kHashBlock + threadIdx.x;
   if (i >= J.n) return;
-  hash_put(J.keys[i], (int32_t)i, J.tkeys, J.tvals, J.mask);
+  hash_put(gp(J.keys)[i], (int32_t)i, J.tkeys, J.tvals, J.mask);
 }
 
 __global__ __launch_bounds__(kHashBlock) void k_kmap_multi(const HashJob* __restrict__ jobs, int njobs) {

@@ -113,7 +113,7 @@ __global__ void k_rc_pack(const Chunk* __restrict__ chunks, const uint8_t* __res
   const uint8_t* src = scratch + chunks[c].scratch;
   uint8_t* d = dst[c];
   const uint32_t n = lens[c];
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) d[i] = src[i];
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) gp(d)[i] = src[i];
 }
 
 hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scratch, const uint32_t* lens,

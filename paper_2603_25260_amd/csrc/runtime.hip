@@ -2,6 +2,8 @@
 // level_probs pipelines.  Every stage is one launch per depth (or per layer
 // position) over the rows of all frames of a call, driven by segment and
 // tile tables that are uploaded once per phase.
+#include <array>
+#include <map>
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -226,6 +228,22 @@ struct lpcc_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   size_t ev_used = 0;
   int64_t time_units = 0;
+  // tile autotuner: rows per wave (16 x rb) of the GEMM-type launches, per
+  // (kernel, widths, log2 rows); tiling = 0 tunes, 1/2/4 fixes rb
+  struct TuneRec {
+    int best = 0;
+    double ms[3] = {0, 0, 0};
+    int n[3] = {0, 0, 0};
+  };
+  std::map<std::array<int, 5>, TuneRec> tune;
+  struct Pending {
+    TuneRec* rec;
+    int cand;
+    hipEvent_t a, z;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_free;
+  int tiling = 0;
 };
 
 namespace {
@@ -279,6 +297,7 @@ bool is_device_ptr(const void* p) {
 // Descriptor batch: host bytes uploaded in one copy; launches are closures
 // over offsets into the uploaded block.
 struct Batch {
+  lpcc_ctx* ctx = nullptr;
   std::vector<uint8_t> bytes;
   struct L {
     std::string family;
@@ -351,6 +370,62 @@ std::vector<Tile> make_tiles(const std::vector<int64_t>& rows, int rows_per_tile
 }
 
 int64_t nchunks_of(int64_t N, int c) { return (N + (1ll << c) - 1) >> c; }
+
+// ---- tile autotuner ----
+constexpr int kTileRB[3] = {1, 2, 4};
+
+hipError_t tune_event(lpcc_ctx* c, hipEvent_t* e) {
+  if (!c->ev_free.empty()) {
+    *e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Fold finished measurements into the table; a size class is decided once
+// every candidate has been timed.
+void resolve_tuning(lpcc_ctx* c) {
+  std::vector<lpcc_ctx::Pending> keep;
+  for (auto& p : c->pending) {
+    float ms = 0;
+    hipError_t e = hipEventElapsedTime(&ms, p.a, p.z);
+    if (e == hipErrorNotReady) {
+      keep.push_back(p);
+      continue;
+    }
+    (void)hipGetLastError();
+    if (e == hipSuccess) {
+      p.rec->ms[p.cand] += ms;
+      p.rec->n[p.cand]++;
+    }
+    c->ev_free.push_back(p.a);
+    c->ev_free.push_back(p.z);
+  }
+  c->pending.swap(keep);
+  for (auto& kv : c->tune) {
+    auto& r = kv.second;
+    if (r.best) continue;
+    int bi = -1;
+    double bv = 0;
+    bool all = true;
+    for (int k = 0; k < 3; k++) {
+      if (r.n[k] == 0) {
+        all = false;
+        break;
+      }
+      const double v = r.ms[k] / r.n[k];
+      if (bi < 0 || v < bv) bi = k, bv = v;
+    }
+    if (all) r.best = kTileRB[bi];
+  }
+}
+
+int log2_rows(int64_t rows) {
+  int b = 0;
+  while ((1ll << (b + 1)) <= rows) b++;
+  return b;
+}
 
 }  // namespace
 
@@ -506,27 +581,74 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
     rows.push_back(s.rows);
     units += s.rows;
   }
-  auto tiles = make_tiles(rows);
-  if (tiles.empty()) return;
-  const int nt = (int)tiles.size();
+  if (units == 0) return;
+  std::string f(fam);
   GemmArg one;
   memset(&one, 0, sizeof(one));
-  size_t so = 0, to = 0;
+  size_t so = 0;
   if (segs.size() == 1) {  // by value: no descriptor loads in the kernel
     one.seg = segs[0];
     one.L = hlayer(m, segs[0].L);
     one.one = 1;
   } else {
     so = b.add(segs);
-    to = b.add(tiles);
   }
-  std::string f(fam);
+  if (f == "emb") {
+    auto tiles = make_tiles(rows);
+    const size_t to = segs.size() == 1 ? 0 : b.add(tiles);
+    const int nt = (int)tiles.size();
+    b.launch(f, units, [=](const uint8_t* base) {
+      return launch_emb((const GemmSeg*)(base + so), (const Tile*)(base + to), nt, cout, one, st);
+    });
+    return;
+  }
+  // rows per wave: the tuned choice of this size class, a fixed one, or all
+  // candidates timed (identical outputs: every candidate writes the same rows)
+  lpcc_ctx* c = b.ctx;
+  const bool up = f == "up";
+  lpcc_ctx::TuneRec* rec = nullptr;
+  std::vector<int> cands;
+  if (c->tiling) {
+    cands = {c->tiling};
+  } else {
+    rec = &c->tune[{up ? 1 : 0, mode, cin, cout, log2_rows(units)}];
+    if (rec->best) cands = {rec->best};
+    else cands = {kTileRB[0], kTileRB[1], kTileRB[2]};
+  }
+  std::vector<std::pair<int, size_t>> plan;  // (rb, tile offset)
+  std::vector<int> ntiles;
+  for (int rb : cands) {
+    auto tiles = make_tiles(rows, 64 * rb);
+    plan.push_back({rb, segs.size() == 1 ? 0 : b.add(tiles)});
+    ntiles.push_back((int)tiles.size());
+  }
+  const bool timed = rec != nullptr && cands.size() > 1;
   b.launch(f, units, [=](const uint8_t* base) {
     const GemmSeg* S = (const GemmSeg*)(base + so);
-    const Tile* T = (const Tile*)(base + to);
-    if (f == "up") return launch_up(cout, S, T, nt, one, st);
-    if (f == "emb") return launch_emb(S, T, nt, cout, one, st);
-    return launch_gemm(mode, cin, cout, S, T, nt, one, st);
+    for (size_t k = 0; k < plan.size(); k++) {
+      const Tile* T = (const Tile*)(base + plan[k].second);
+      auto go = [&]() {
+        return up ? launch_up(cout, S, T, ntiles[k], one, plan[k].first, st)
+                  : launch_gemm(mode, cin, cout, S, T, ntiles[k], one, plan[k].first, st);
+      };
+      if (!timed) {
+        hipError_t e = go();
+        if (e != hipSuccess) return e;
+        continue;
+      }
+      hipEvent_t ea, ez;
+      hipError_t e = go();  // untimed first run (code load, caches)
+      if (e == hipSuccess) e = tune_event(c, &ea);
+      if (e == hipSuccess) e = tune_event(c, &ez);
+      if (e == hipSuccess) e = hipEventRecord(ea, st);
+      if (e == hipSuccess) e = go();
+      if (e == hipSuccess) e = hipEventRecord(ez, st);
+      if (e != hipSuccess) return e;
+      int ci = 0;
+      while (kTileRB[ci] != plan[k].first) ci++;
+      c->pending.push_back({rec, ci, ea, ez});
+    }
+    return hipSuccess;
   });
 }
 
@@ -859,6 +981,7 @@ struct OutSpec {
 int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n, int cl,
                 OutSpec os, int* status, int probe_level, int32_t* cdf_out, int64_t cdf_cap, int64_t* n_nodes) {
   const int D = m->D, C = m->C, k0 = m->k0;
+  resolve_tuning(c);
   hipStream_t st = c->stream;
   size_t desc_off = 0;
   Levels lv;
@@ -945,6 +1068,7 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   carve(A);
 
   Batch b;
+  b.ctx = c;
   // F_0 = 0
   {
     int8_t* f0 = B.F[0];
@@ -1140,6 +1264,7 @@ int read_header(lpcc_ctx* c, const uint8_t* bs, size_t len, Header& H) {
 int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* bs, const size_t* len,
                 int32_t* const* xyz_out, const int64_t* cap, int64_t* n_out, int* status) {
   const int D = m->D, C = m->C, k0 = m->k0;
+  resolve_tuning(c);
   hipStream_t st = c->stream;
   std::vector<Header> H(nf);
   std::vector<int> live;
@@ -1259,6 +1384,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   HIPC(launch_fill_u32(err, 4, 0, st));
 
   Batch b;
+  b.ctx = c;
   {
     int8_t* f0 = B.F[0];
     const int64_t bytes = fr.tot[0] * C;
@@ -1449,6 +1575,11 @@ void lpcc_ctx_free(lpcc_ctx* c) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.z);
+  }
+  for (auto e : c->ev_free) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -1533,6 +1664,28 @@ int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* 
   c->ev_used = 0;
   c->time_units = 0;
   return LPCC_OK;
+}
+
+int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb) {
+  if (!c || !(rb == 0 || rb == 1 || rb == 2 || rb == 4)) return LPCC_E_INVAL;
+  c->tiling = rb;
+  return LPCC_OK;
+}
+
+int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n) {
+  if (!c || !n) return LPCC_E_INVAL;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LPCC_E_DEVICE;
+  resolve_tuning(c);
+  int k = 0;
+  for (auto& kv : c->tune) {
+    if (out && k < cap) {
+      for (int i = 0; i < 5; i++) out[6 * k + i] = kv.first[i];
+      out[6 * k + 5] = kv.second.best;
+    }
+    k++;
+  }
+  *n = k;
+  return k > cap && out ? LPCC_E_CAPACITY : LPCC_OK;
 }
 
 // Exponent table of the integer softmax as the library builds it (host only).

@@ -78,6 +78,8 @@ def lib():
         L.lpcc_timing_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64)]
         L.lpcc_softmax_table.argtypes = [vp]
+        L.lpcc_ctx_set_tiling.argtypes = [vp, i32]
+        L.lpcc_ctx_tuning.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
         L.lpcc_server_create.argtypes = [i32, vp, i32, i32, i32, sz, ctypes.POINTER(vp)]
         L.lpcc_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
         L.lpcc_server_poll.argtypes = [vp, ctypes.POINTER(Done), i32, ctypes.POINTER(i32), i32]
@@ -167,6 +169,25 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- tile shapes of the GEMM-type kernels: 0 autotunes, 1/2/4 fixes the
+    # number of 16-row blocks per wave
+    def set_tiling(self, rb: int):
+        _check(lib().lpcc_ctx_set_tiling(self.handle, int(rb)), self.handle)
+
+    def tuning(self):
+        """Autotuner table: dicts with kind ('gemm'/'up'), mode, cin, cout,
+        log2_rows and the chosen rb (0 while undecided)."""
+        n = ctypes.c_int32()
+        _check(lib().lpcc_ctx_tuning(self.handle, None, 0, ctypes.byref(n)), self.handle)
+        buf = (ctypes.c_int32 * (6 * max(n.value, 1)))()
+        _check(lib().lpcc_ctx_tuning(self.handle, buf, n.value, ctypes.byref(n)), self.handle)
+        out = []
+        for k in range(n.value):
+            v = buf[6 * k:6 * k + 6]
+            out.append({"kind": "up" if v[0] else "gemm", "mode": v[1], "cin": v[2], "cout": v[3],
+                        "log2_rows": v[4], "rb": v[5]})
+        return out
 
     # -- timing of one kernel family (HIP events on the context's stream)
     def timing_enable(self, family: str):

@@ -1,0 +1,70 @@
+"""Tile shapes of the gather-GEMM and up-convolution kernels: every fixed
+choice of 16-row blocks per wave (1, 2, 4) and the autotuned one give the
+oracle's CDF rows and bitstreams byte for byte."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_25260_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_25260_amd import lpcc
+    lpcc.lib()
+    return lpcc
+
+
+# (C, D, n_deep, points): every width the kernels are built for, several
+# 64 x rb tiles per level and ragged tails
+CASES = [(16, 9, 3, 3000), (32, 10, 4, 9000), (64, 10, 4, 7000)]
+
+
+@pytest.mark.parametrize("C,D,n_deep,npts", CASES)
+def test_fixed_tilings_match_oracle(L, C, D, n_deep, npts):
+    blob = synth.make_weights(11 + C, C, D, n_deep)
+    xyz = synth.random_cloud(npts, D, 500 + C)
+    want = O.encode(blob, xyz, 7)
+    d_deep, d_shallow = D - 1, D - n_deep - 2
+    p_deep, p_sh = O.level_probs(blob, xyz, d_deep), O.level_probs(blob, xyz, d_shallow)
+    m = L.Model(blob, 0)
+    dx = torch.from_numpy(xyz).cuda()
+    for rb in (1, 2, 4):
+        ctx = L.Context(0)
+        ctx.set_tiling(rb)
+        print("C", C, "rb", rb, flush=True)
+        assert L.encode_frame(ctx, m, dx, 7) == want, f"rb={rb}"
+        assert np.array_equal(L.level_probs(ctx, m, dx, d_deep), p_deep), f"rb={rb} deep"
+        assert np.array_equal(L.level_probs(ctx, m, dx, d_shallow), p_sh), f"rb={rb} shallow"
+        dec = L.decode_frame(ctx, m, want)
+        assert len(dec) == len(np.unique(xyz, axis=0))
+
+
+def test_autotuned_tiling_decides_and_matches(L):
+    C, D, n_deep = 32, 11, 4
+    blob = synth.make_weights(5, C, D, n_deep)
+    xyz = synth.random_cloud(20000, D, 77)
+    want = O.encode(blob, xyz, 8)
+    m = L.Model(blob, 0)
+    ctx = L.Context(0)
+    ctx.set_tiling(0)
+    dx = torch.from_numpy(xyz).cuda()
+    for it in range(3):  # the first call times every candidate, later ones use the choice
+        print("autotune call", it, flush=True)
+        assert L.encode_frame(ctx, m, dx, 8) == want
+        dec = L.decode_frame(ctx, m, want)
+        assert len(dec) == len(np.unique(xyz, axis=0))
+    table = ctx.tuning()
+    assert table, "no tuned classes"
+    assert all(t["rb"] in (1, 2, 4) for t in table), table
+
+
+def test_bad_tiling_rejected(L):
+    ctx = L.Context(0)
+    with pytest.raises(Exception):
+        ctx.set_tiling(3)
