@@ -2,7 +2,7 @@
 
 Every HIP source under ``csrc/`` is compiled for gfx950 only, then linked into
 one shared library next to this file.  Packed-FP32 instruction selection is
-disabled for all device code.
+disabled for all device code, and MFMA accumulators are kept in VGPRs.
 """
 from __future__ import annotations
 
@@ -17,8 +17,12 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "liblpcc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["octree.hip", "model.hip", "rc.hip", "runtime.hip", "server.hip"]
+# -amdgpu-mfma-vgpr-form: MFMA accumulators stay in VGPRs; without it the
+# register allocator shuttles the register-blocked accumulators between AGPRs
+# and VGPRs on every k-step of the gather-GEMM loops.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 

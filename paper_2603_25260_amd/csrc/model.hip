@@ -263,6 +263,13 @@ __global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ seg
     for (int nb = 0; nb < NB; nb++) acc[rb][nb] = v4i{0, 0, 0, 0};
   const GAS v4i* Wp = (const GAS v4i*)L.Wp;
   constexpr int LC = __builtin_ctz(CIN);
+  // [in | in2] layers (the ResBlock at k0 on [F | G]) are exactly those with
+  // cin = 2 cout, split at cout; the feature arrays stay below 2^31 bytes
+  // (checked on the host), so row offsets are 32-bit
+  constexpr int SPLIT = CIN == 2 * COUT ? COUT : CIN;
+  const GAS int8_t* in1 = gp(S.in);
+  const GAS int8_t* in2 = gp(S.in2);
+  const uint32_t st1 = (uint32_t)S.in_stride, st2 = (uint32_t)S.in2_stride;
 #pragma unroll 2
   for (int s = 0; s < KS; s++) {
     const int k0 = 64 * s + 16 * g;
@@ -273,8 +280,8 @@ __global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ seg
       const int sr = src_of(rb, tap);
       a[rb] = v4i{0, 0, 0, 0};
       if (sr >= 0)
-        a[rb] = c0 < S.split ? ld16(S.in + (int64_t)sr * S.in_stride + c0)
-                             : ld16(S.in2 + (int64_t)sr * S.in2_stride + (c0 - S.split));
+        a[rb] = c0 < SPLIT ? *(const GAS v4i*)(in1 + ((uint32_t)sr * st1 + (uint32_t)c0))
+                           : *(const GAS v4i*)(in2 + ((uint32_t)sr * st2 + (uint32_t)(c0 - SPLIT)));
     }
 #pragma unroll
     for (int nb = 0; nb < NB; nb++) {
