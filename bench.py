@@ -171,6 +171,30 @@ def main():
                             "ns_per_serial_symbol": round(dms * 1e6 / max(dl, 1) / (1 << cl), 1),
                             "cdf_row_gbs": round(dunits * 512 / (dms / 1e3) / 1e9, 1) if dms > 0 else None}
 
+    # ---- graph mode: the same plain loop with every launch batch captured
+    # into HIP graphs and replayed (executable graphs updated in place)
+    gctx = lpcc.Context(0, stream.cuda_stream)
+    gctx.set_graphs(True)
+
+    def gstep(i):
+        k = i % len(frames)
+        n = lpcc.encode_frame(gctx, model, dxyz[k], cl, out=dbs)
+        lpcc.decode_frame(gctx, model, dbs, length=n, out=dout)
+        return n
+
+    for i in range(2 * len(frames)):
+        n = gstep(i)
+        if i < len(frames):
+            assert bytes(dbs[:n].cpu().numpy()) == lens[i], "graph-mode stream differs"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        gstep(i)
+    torch.cuda.synchronize()
+    gw = time.perf_counter() - t0
+    res["graph_mode"] = {"value": round(pts / gw / 1e6, 3), "unit": "Mpts/s", "ms_per_step": round(gw / args.steps * 1e3, 3),
+                         **gctx.graph_stats()}
+
     # ---- bit-exactness of the timed streams against the oracle
     if not args.no_cpu:
         from oracle import oracle as O
@@ -217,10 +241,22 @@ def main():
                 lpcc.decode_frame(ctx, model, dbs, length=n, out=dout)
         torch.cuda.synchronize()
         tp = (time.perf_counter() - t0) / reps
+        # the batch again with its launch batches captured into graphs
+        lpcc.encode_batch(gctx, model, bd, cl, outs=bouts)
+        lg, _ = lpcc.encode_batch(gctx, model, bd, cl, outs=bouts)
+        lpcc.decode_batch(gctx, model, bouts, lengths=lg, outs=bdec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lg, _ = lpcc.encode_batch(gctx, model, bd, cl, outs=bouts)
+            lpcc.decode_batch(gctx, model, bouts, lengths=lg, outs=bdec)
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / reps
         res["batched"] = {"workload": "32 uneven frames (16/32/64 beams, 1024-2048 az), 14-level, C=32",
                           "points": bpts, "batched_mpts_s": round(bpts / tb / 1e6, 3),
+                          "batched_graph_mpts_s": round(bpts / tg / 1e6, 3),
                           "plain_mpts_s": round(bpts / tp / 1e6, 3), "speedup": round(tp / tb, 3),
-                          "same_lengths": plain_lens == ln}
+                          "same_lengths": plain_lens == ln and lg == ln}
         res["batched_128beam"] = _bench_128beam(lpcc, synth, torch, dev, ctx)
     if not args.no_serve:
         from paper_2603_25260_amd import serve

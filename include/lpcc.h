@@ -71,9 +71,13 @@ void lpcc_model_free(lpcc_model* m);
 int lpcc_model_info(const lpcc_model* m, int* C, int* D, int* n_deep, uint32_t* blob_id);
 
 /*
- * Context on `device`.  `hip_stream` (a hipStream_t, may be NULL for the null
- * stream) is where all work of the context is enqueued; the context does not
- * own it.  Device workspace grows on demand and is reused between calls.
+ * Context on `device`.  `hip_stream` (a hipStream_t) is where all work of the
+ * context is enqueued; the context does not own it.  With NULL the context
+ * creates a stream of its own (default priority, blocking: ordered with the
+ * null stream, so inputs written there are complete when its work starts) and
+ * destroys it in lpcc_ctx_free.  Every call returns after its work on the
+ * stream has finished.  Device workspace grows on demand and is reused
+ * between calls.
  */
 int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out);
 void lpcc_ctx_free(lpcc_ctx* c);
@@ -207,6 +211,20 @@ int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* 
  * cap is too small (the first cap rows are written).
  */
 int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb);
+
+/*
+ * Graph mode (off by default).  When on, each launch batch of a call (the
+ * level loop of a decode; the model, coder and packing stages of an encode)
+ * is captured on the context's stream into a HIP graph and launched as one
+ * graph.  The context keeps one executable graph per batch position and call
+ * kind and updates it in place (hipGraphExecUpdate) when the next call has
+ * the same launch sequence, else instantiates a new one.  Batches that time
+ * kernels (autotuning, lpcc_timing_enable) run directly.  Outputs are
+ * identical in both modes.  lpcc_ctx_graph_stats counts instantiations and
+ * in-place updates since the context was created.
+ */
+int lpcc_ctx_set_graphs(lpcc_ctx* c, int on);
+int lpcc_ctx_graph_stats(lpcc_ctx* c, int64_t* instantiated, int64_t* updated);
 int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n);
 
 /*

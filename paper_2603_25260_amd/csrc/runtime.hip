@@ -218,6 +218,7 @@ struct Arena {
 struct lpcc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;  // created when the caller passes none
   std::string err;
   char* dev[3] = {nullptr, nullptr, nullptr};  // arenas: octree, model, descriptors
   size_t cap[3] = {0, 0, 0};
@@ -244,6 +245,13 @@ struct lpcc_ctx {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> ev_free;
   int tiling = 0;
+  // graph mode: every launch batch of a call is captured into a HIP graph and
+  // replayed; the executable graph of each (call kind, batch) slot is kept and
+  // updated in place when the next call has the same launch sequence
+  int graphs = 0;
+  int call_kind = 0, batch_idx = 0;
+  std::map<int, hipGraphExec_t> gexec;
+  int64_t graph_inst = 0, graph_upd = 0;
 };
 
 namespace {
@@ -298,6 +306,7 @@ bool is_device_ptr(const void* p) {
 // over offsets into the uploaded block.
 struct Batch {
   lpcc_ctx* ctx = nullptr;
+  bool has_events = false;  // a launch records events of its own (tuning)
   std::vector<uint8_t> bytes;
   struct L {
     std::string family;
@@ -335,9 +344,54 @@ int run_batch(lpcc_ctx* c, Batch& b, size_t* desc_off) {
   // the pinned block mirrors the device block; regions of one call do not overlap
   memcpy(c->pinned + *desc_off, b.bytes.data(), b.bytes.size());
   uint8_t* dbase = (uint8_t*)c->dev[2] + *desc_off;
-  if (!b.bytes.empty())
-    HIPC(hipMemcpyAsync(dbase, c->pinned + *desc_off, b.bytes.size(), hipMemcpyHostToDevice, c->stream));
+  const uint8_t* hsrc = c->pinned + *desc_off;
   *desc_off += n;
+  const int slot = c->call_kind * 64 + c->batch_idx++;
+  if (c->graphs && c->time_family.empty() && !b.has_events && !b.launches.empty()) {
+    // capture the copy and the launches, then update the slot's executable
+    // graph in place (same launch sequence) or instantiate a new one
+    HIPC(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    if (!b.bytes.empty()) e = hipMemcpyAsync(dbase, hsrc, b.bytes.size(), hipMemcpyHostToDevice, c->stream);
+    for (size_t k = 0; k < b.launches.size() && e == hipSuccess; k++) e = b.launches[k].fn(dbase);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    b.bytes.clear();
+    b.launches.clear();
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      HIPC(e != hipSuccess ? e : e2);
+    }
+    bool updated = false;
+    auto it = c->gexec.find(slot);
+    if (it != c->gexec.end()) {
+      hipGraphExecUpdateResult r;
+      hipGraphNode_t en = nullptr;
+      if (hipGraphExecUpdate(it->second, g, &en, &r) == hipSuccess && r == hipGraphExecUpdateSuccess) {
+        updated = true;
+      } else {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(it->second);
+        c->gexec.erase(it);
+      }
+    }
+    if (!updated) {
+      hipGraphExec_t x = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        HIPC(ei);
+      }
+      c->gexec[slot] = x;
+      c->graph_inst++;
+    } else {
+      c->graph_upd++;
+    }
+    (void)hipGraphDestroy(g);
+    HIPC(hipGraphLaunch(c->gexec[slot], c->stream));
+    return LPCC_OK;
+  }
+  if (!b.bytes.empty()) HIPC(hipMemcpyAsync(dbase, hsrc, b.bytes.size(), hipMemcpyHostToDevice, c->stream));
   for (auto& L : b.launches) {
     const bool timed = !c->time_family.empty() && L.family == c->time_family;
     if (timed) {
@@ -623,6 +677,7 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
     ntiles.push_back((int)tiles.size());
   }
   const bool timed = rec != nullptr && cands.size() > 1;
+  if (timed) b.has_events = true;
   b.launch(f, units, [=](const uint8_t* base) {
     const GemmSeg* S = (const GemmSeg*)(base + so);
     for (size_t k = 0; k < plan.size(); k++) {
@@ -982,6 +1037,8 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
                 OutSpec os, int* status, int probe_level, int32_t* cdf_out, int64_t cdf_cap, int64_t* n_nodes) {
   const int D = m->D, C = m->C, k0 = m->k0;
   resolve_tuning(c);
+  c->call_kind = probe_level >= 0 ? 2 : 0;
+  c->batch_idx = 0;
   hipStream_t st = c->stream;
   size_t desc_off = 0;
   Levels lv;
@@ -1265,6 +1322,8 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
                 int32_t* const* xyz_out, const int64_t* cap, int64_t* n_out, int* status) {
   const int D = m->D, C = m->C, k0 = m->k0;
   resolve_tuning(c);
+  c->call_kind = 1;
+  c->batch_idx = 0;
   hipStream_t st = c->stream;
   std::vector<Header> H(nf);
   std::vector<int> live;
@@ -1561,6 +1620,13 @@ int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out) {
   lpcc_ctx* c = new lpcc_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (!c->stream) {
+    if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+      delete c;
+      return LPCC_E_DEVICE;
+    }
+    c->stream = c->own_stream;
+  }
   *out = c;
   return LPCC_OK;
 }
@@ -1580,6 +1646,8 @@ void lpcc_ctx_free(lpcc_ctx* c) {
     (void)hipEventDestroy(p.z);
   }
   for (auto e : c->ev_free) (void)hipEventDestroy(e);
+  for (auto& kv : c->gexec) (void)hipGraphExecDestroy(kv.second);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
 }
 
@@ -1663,6 +1731,19 @@ int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* 
   if (units) *units = c->time_units;
   c->ev_used = 0;
   c->time_units = 0;
+  return LPCC_OK;
+}
+
+int lpcc_ctx_set_graphs(lpcc_ctx* c, int on) {
+  if (!c) return LPCC_E_INVAL;
+  c->graphs = on ? 1 : 0;
+  return LPCC_OK;
+}
+
+int lpcc_ctx_graph_stats(lpcc_ctx* c, int64_t* instantiated, int64_t* updated) {
+  if (!c) return LPCC_E_INVAL;
+  if (instantiated) *instantiated = c->graph_inst;
+  if (updated) *updated = c->graph_upd;
   return LPCC_OK;
 }
 

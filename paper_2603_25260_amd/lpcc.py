@@ -79,6 +79,8 @@ def lib():
                                        ctypes.POINTER(i64)]
         L.lpcc_softmax_table.argtypes = [vp]
         L.lpcc_ctx_set_tiling.argtypes = [vp, i32]
+        L.lpcc_ctx_set_graphs.argtypes = [vp, i32]
+        L.lpcc_ctx_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.lpcc_ctx_tuning.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
         L.lpcc_server_create.argtypes = [i32, vp, i32, i32, i32, sz, ctypes.POINTER(vp)]
         L.lpcc_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
@@ -174,6 +176,15 @@ class Context:
     # number of 16-row blocks per wave
     def set_tiling(self, rb: int):
         _check(lib().lpcc_ctx_set_tiling(self.handle, int(rb)), self.handle)
+
+    # -- graph mode: launch batches captured into HIP graphs and replayed
+    def set_graphs(self, on: bool):
+        _check(lib().lpcc_ctx_set_graphs(self.handle, 1 if on else 0), self.handle)
+
+    def graph_stats(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lpcc_ctx_graph_stats(self.handle, ctypes.byref(a), ctypes.byref(b)), self.handle)
+        return {"instantiated": a.value, "updated": b.value}
 
     def tuning(self):
         """Autotuner table: dicts with kind ('gemm'/'up'), mode, cin, cout,
