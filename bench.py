@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparisons")
     ap.add_argument("--no-serve", action="store_true", help="skip the served (continuous batching) run")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-mode lines")
+    ap.add_argument("--only-128beam", action="store_true",
+                    help="run only the 128-beam batched comparison after the plain loop (profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
@@ -171,6 +174,11 @@ def main():
                             "ns_per_serial_symbol": round(dms * 1e6 / max(dl, 1) / (1 << cl), 1),
                             "cdf_row_gbs": round(dunits * 512 / (dms / 1e3) / 1e9, 1) if dms > 0 else None}
 
+    if args.only_128beam:
+        res["batched_128beam"] = _bench_128beam(lpcc, synth, torch, dev, ctx)
+        print(json.dumps(res))
+        return
+
     # ---- graph mode: the same plain loop with every launch batch captured
     # into HIP graphs and replayed (executable graphs updated in place)
     gctx = lpcc.Context(0, stream.cuda_stream)
@@ -182,18 +190,19 @@ def main():
         lpcc.decode_frame(gctx, model, dbs, length=n, out=dout)
         return n
 
-    for i in range(2 * len(frames)):
-        n = gstep(i)
-        if i < len(frames):
-            assert bytes(dbs[:n].cpu().numpy()) == lens[i], "graph-mode stream differs"
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        gstep(i)
-    torch.cuda.synchronize()
-    gw = time.perf_counter() - t0
-    res["graph_mode"] = {"value": round(pts / gw / 1e6, 3), "unit": "Mpts/s", "ms_per_step": round(gw / args.steps * 1e3, 3),
-                         **gctx.graph_stats()}
+    if not args.no_graph:
+        for i in range(2 * len(frames)):
+            n = gstep(i)
+            if i < len(frames):
+                assert bytes(dbs[:n].cpu().numpy()) == lens[i], "graph-mode stream differs"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            gstep(i)
+        torch.cuda.synchronize()
+        gw = time.perf_counter() - t0
+        res["graph_mode"] = {"value": round(pts / gw / 1e6, 3), "unit": "Mpts/s",
+                             "ms_per_step": round(gw / args.steps * 1e3, 3), **gctx.graph_stats()}
 
     # ---- bit-exactness of the timed streams against the oracle
     if not args.no_cpu:
@@ -242,6 +251,7 @@ def main():
         torch.cuda.synchronize()
         tp = (time.perf_counter() - t0) / reps
         # the batch again with its launch batches captured into graphs
+        gctx.set_graphs(not args.no_graph)
         lpcc.encode_batch(gctx, model, bd, cl, outs=bouts)
         lg, _ = lpcc.encode_batch(gctx, model, bd, cl, outs=bouts)
         lpcc.decode_batch(gctx, model, bouts, lengths=lg, outs=bdec)
@@ -315,10 +325,11 @@ def _bench_128beam(lpcc, synth, torch, dev, ctx):
 
 
 # HBM bytes per k_predict launch (read + write, scaled FETCH_SIZE / WRITE_SIZE
-# counters averaged over the launches of this workload) and the source they
-# were taken on; a changed kernel source reports traffic = null
-PROFILED_MODEL_HIP = "d4245a68180d1d72"
-PREDICT_BYTES_PER_LAUNCH = (60 * (12968.4 + 1364.8) + 840 * (1149.0 + 11817.2)) / 900 * 1024
+# counters of profiles/64beam_D14_C32_plain_counters.md averaged over the 840
+# decode-mode and 60 encode-mode launches of that run) and the kernel source
+# they were taken on; a changed kernel source reports traffic = null
+PROFILED_MODEL_HIP = "a7605df00fa49228"
+PREDICT_BYTES_PER_LAUNCH = (840 * (1042.3 + 11230.6) + 60 * (12870.3 + 1364.8)) / 900 * 1024
 
 
 def _source_hash():
