@@ -396,12 +396,15 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
       ps[wave][16 * rb + r] = row < S.rows ? gp(S.cstart)[row] : 0;
     }
   }
-  // the output loop below gives every lane the fixed column lane % C
-  static_assert(64 % C == 0, "C must divide the wave width");
-  const int ocol = lane % C;
-  int bia[8];
+  // output: 4 consecutive columns per lane, C/4 lanes per child row
+  static_assert(C % 4 == 0 && 64 % (C / 4) == 0, "C");
+  constexpr int LPR = C / 4, RPP = 64 / LPR;
+  const int jl = lane / LPR, c4 = (lane % LPR) * 4;
+  int bia[8][4];
 #pragma unroll
-  for (int o = 0; o < 8; o++) bia[o] = gp(L.bias)[o * C + ocol];
+  for (int o = 0; o < 8; o++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) bia[o][q] = gp(L.bias)[o * C + c4 + q];
 
   v4i a[RB][KS];
 #pragma unroll
@@ -464,10 +467,10 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // only the occupied (row, slot) outputs: k rows x C columns over the wave
+      // only the occupied (row, slot) outputs: k rows of C columns, RPP rows
+      // per pass, 4 columns (one 32-bit store) per lane
       const int k = __popc(m);
-      for (int v = lane; v < k * C; v += 64) {
-        const int j = v / C, col = v - j * C;
+      for (int j = jl; j < k; j += RPP) {
         // row of the j-th set bit of m
         int pos = 0;
 #pragma unroll
@@ -476,8 +479,13 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
         const uint32_t pcode = pc[wave][16 * rb + pos];
         const int crow = ps[wave][16 * rb + pos] + __popc(pcode & ((1u << o) - 1u));
         if (crow >= S.child_rows) continue;  // only for a corrupt stream
-        const int y = requant_l(st[wave][pos][col] + bia[o], L);
-        gp(S.out)[(int64_t)crow * S.out_stride + col] = (int8_t)y;
+        uint32_t packed = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int y = requant_l(st[wave][pos][c4 + q] + bia[o][q], L);
+          packed |= ((uint32_t)y & 0xFFu) << (8 * q);
+        }
+        *(GAS uint32_t*)(gp(S.out) + (int64_t)crow * S.out_stride + c4) = packed;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();

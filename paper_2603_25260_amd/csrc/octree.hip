@@ -382,6 +382,7 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
                                                        uint64_t mask, uint32_t* err) {
   __shared__ uint32_t wtot[4];
   __shared__ uint32_t run;
+  __shared__ uint64_t kids[8 * 256];  // child keys of the current round, in child order
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cb = blockIdx.x;
   const Chunk ch = chunks[cb];
@@ -411,26 +412,30 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
     uint32_t before = run;
     for (int w = 0; w < wave; w++) before += wtot[w];
     const uint32_t first = before + inc - c;
+    const uint32_t r0 = run;  // first child of this round
     if (valid) {
       cstart[i] = (int32_t)first;
       const uint64_t pk = pkeys[i];
-      uint32_t r = first;
+      uint32_t r = first - r0;
       for (int o = 0; o < 8; o++)
-        if ((code >> o) & 1u) {
-          if ((int64_t)r < expected) {
-            const uint64_t k = (pk << 3) | (uint64_t)o;
-            ckeys[r] = k;
-            if (tkeys != nullptr) hash_put(k, (int32_t)r, tkeys, tvals, mask);
-          }
-          r++;
-        }
+        if ((code >> o) & 1u) kids[r++] = (pk << 3) | (uint64_t)o;
       if (i == n - 1) {
         cstart[n] = (int32_t)(first + c);
         if ((int64_t)(first + c) != expected) atomicOr(err, ERR_COUNT);
       }
     }
     __syncthreads();
-    if (threadIdx.x == 0) run += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    // one thread per child: coalesced key stores and independent insertions
+    const uint32_t nk = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    for (uint32_t j = threadIdx.x; j < nk; j += 256) {
+      const uint32_t r = r0 + j;
+      if ((int64_t)r >= expected) break;
+      const uint64_t k = kids[j];
+      ckeys[r] = k;
+      if (tkeys != nullptr) hash_put(k, (int32_t)r, tkeys, tvals, mask);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) run = r0 + nk;
     __syncthreads();
   }
 }
