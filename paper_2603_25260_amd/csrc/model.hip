@@ -19,6 +19,27 @@ namespace lpcc {
 
 __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const GAS v4i*)p; }
 
+// N int8 values (N a multiple of 4, 4-byte aligned) as 32-bit words
+template <int N>
+__device__ __forceinline__ void ld_bytes(const int8_t* p, int8_t (&v)[N]) {
+#pragma unroll
+  for (int w = 0; w < N / 4; w++) {
+    const uint32_t x = ((const GAS uint32_t*)p)[w];
+#pragma unroll
+    for (int b = 0; b < 4; b++) v[4 * w + b] = (int8_t)(x >> (8 * b));
+  }
+}
+template <int N>
+__device__ __forceinline__ void st_bytes(int8_t* p, const int8_t (&v)[N]) {
+#pragma unroll
+  for (int w = 0; w < N / 4; w++) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int b = 0; b < 4; b++) x |= ((uint32_t)(uint8_t)v[4 * w + b]) << (8 * b);
+    ((GAS uint32_t*)p)[w] = x;
+  }
+}
+
 // Epilogue: one wave's 16 x COUT int32 tile staged in LDS, then every lane
 // handles a contiguous run of COUT/4 columns of one row.
 template <int COUT>
@@ -111,8 +132,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
 #pragma unroll
   for (int q = 0; q < PER; q++) res[q] = 0;
   if (S.resid != nullptr && ov) {
-#pragma unroll
-    for (int q = 0; q < PER; q++) res[q] = gp(S.resid)[(int64_t)orow * S.resid_stride + ec + q];
+    ld_bytes<PER>(S.resid + (int64_t)orow * S.resid_stride + ec, res);
   }
 
   v4i acc[NB];
@@ -171,9 +191,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
       }
       outv[q] = (int8_t)y;
     }
-    GAS int8_t* dst = gp(S.out) + (int64_t)orow * S.out_stride + ec;
-#pragma unroll
-    for (int q = 0; q < PER; q++) dst[q] = outv[q];
+    st_bytes<PER>(S.out + (int64_t)orow * S.out_stride + ec, outv);
   }
 }
 
@@ -216,8 +234,7 @@ __global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ seg
 #pragma unroll
     for (int q = 0; q < PER; q++) res[rb][q] = 0;
     if (S.resid != nullptr && orow < S.rows) {
-#pragma unroll
-      for (int q = 0; q < PER; q++) res[rb][q] = gp(S.resid)[(int64_t)orow * S.resid_stride + ec + q];
+      ld_bytes<PER>(S.resid + (int64_t)orow * S.resid_stride + ec, res[rb]);
     }
   }
 
@@ -326,9 +343,7 @@ __global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ seg
         }
         outv[q] = (int8_t)y;
       }
-      GAS int8_t* dst = gp(S.out) + (int64_t)orow * S.out_stride + ec;
-#pragma unroll
-      for (int q = 0; q < PER; q++) dst[q] = outv[q];
+      st_bytes<PER>(S.out + (int64_t)orow * S.out_stride + ec, outv);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -632,17 +647,25 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   if (C < 64) {  // zero the K padding (columns C..63 of the 16 rows)
     for (int k = lane; k < 16 * (64 - C); k += 64) hs[wave][k / (64 - C)][C + k % (64 - C)] = 0;
   }
-  __syncthreads();
+  // fc2 operands issued before the barrier (independent of fc1)
+  const GAS v4i* W2 = (const GAS v4i*)L2.Wp;
+  v4i w2[16];
+  int b2[16];
+#pragma unroll
+  for (int b = 0; b < 16; b++) {
+    w2[b] = W2[b * 64 + lane];
+    b2[b] = gp(L2.bias)[16 * b + r];
+  }
+  __syncthreads();  // hs of this wave, and the exponent table written by all waves
   v4i h = *(const v4i*)&hs[wave][r][16 * g];
 
   // fc2: 16 column blocks of 16 logits
-  const GAS v4i* W2 = (const GAS v4i*)L2.Wp;
   int lg[4][16];
 #pragma unroll
   for (int b = 0; b < 16; b++) {
-    v4i acc = mfma16(h, W2[b * 64 + lane], v4i{0, 0, 0, 0});
+    v4i acc = mfma16(h, w2[b], v4i{0, 0, 0, 0});
     const int col = 16 * b + r;
-    const int bias = gp(L2.bias)[col];
+    const int bias = b2[b];
 #pragma unroll
     for (int i = 0; i < 4; i++)
       lg[i][b] = col < kNSym ? requant_l(acc[i] + bias, L2) : -1000;
