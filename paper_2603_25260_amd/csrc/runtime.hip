@@ -252,6 +252,11 @@ struct lpcc_ctx {
   int call_kind = 0, batch_idx = 0;
   std::map<int, hipGraphExec_t> gexec;
   int64_t graph_inst = 0, graph_upd = 0;
+  // second stream of the decoder (convolutions and neighbour tables of the
+  // next depth run beside the current depth's predictor and coder)
+  hipStream_t side = nullptr;
+  std::vector<hipEvent_t> sync_ev;
+  size_t sync_used = 0;
 };
 
 namespace {
@@ -708,8 +713,9 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
 }
 
 // Shallow depth d (1 <= d <= k0): S = ResBlock(F_{d-1}); F_d = Prune(Up([S | bits X_{d-1}]))
-void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B, int d,
-                  hipStream_t st) {
+// The ResBlock part of shallow depth d (needs F_{d-1} and the neighbour
+// table of depth d-1, not the codes of depth d-1)
+void plan_shallow_convs(Batch& b, const lpcc_model* m, const Frames& fr, ModelBufs& B, int d, hipStream_t st) {
   const int C = m->C;
   const int j = d - 1;
   const int rows = (int)fr.tot[j];
@@ -729,6 +735,14 @@ void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames&
   s.resid = B.F[j];
   s.resid_stride = C;
   plan_gemm(b, m, "conv", G_CONV, C, C, {s}, st);
+}
+
+// Upsampling + pruning of shallow depth d (needs the codes of depth d-1)
+void plan_shallow_up(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B, int d,
+                     hipStream_t st) {
+  const int C = m->C;
+  const int j = d - 1;
+  const int rows = (int)fr.tot[j];
   GemmSeg u = seg0();
   u.in = B.S;
   u.in_stride = C;
@@ -740,6 +754,28 @@ void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames&
   u.rows = rows;
   u.child_rows = (int)fr.tot[d];
   plan_gemm(b, m, "up", 0, C, C, {u}, st);
+}
+
+void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B, int d,
+                  hipStream_t st) {
+  plan_shallow_convs(b, m, fr, B, d, st);
+  plan_shallow_up(b, m, lv, fr, B, d, st);
+}
+
+// Cross-stream ordering inside a launch batch
+hipEvent_t sync_event(lpcc_ctx* c) {
+  if (c->sync_used == c->sync_ev.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    c->sync_ev.push_back(e);
+  }
+  return c->sync_ev[c->sync_used++];
+}
+void plan_record(Batch& b, hipEvent_t e, hipStream_t s) {
+  b.launch("sync", 0, [=](const uint8_t*) { return hipEventRecord(e, s); });
+}
+void plan_wait(Batch& b, hipStream_t s, hipEvent_t e) {
+  b.launch("sync", 0, [=](const uint8_t*) { return hipStreamWaitEvent(s, e, 0); });
 }
 
 // Deep depths `ds` (all > k0), stage by stage; every launch covers all of them.
@@ -1451,9 +1487,50 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   }
   plan_hash_clear(b, B, st);
   if (B.kmap[0]) plan_kmaps(b, lv, fr, B, {0}, st);
+  // Depth d's chain is predictor -> coder -> expansion -> upsampling of
+  // depth d+1.  The ResBlock of depth d+1 needs only F_d and the neighbour
+  // table of depth d, and the neighbour table of depth d+1 only the
+  // expansion, so both run on a second stream beside the chain.
+  c->sync_used = 0;
+  bool two = c->time_family.empty() && !c->graphs;
+  if (two && !c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    c->side = nullptr;
+  }
+  two = two && c->side;
+  const hipStream_t sd = two ? c->side : st;
+  bool ok_ev = true;
+  // record an event on `s` now (null when one stream is used)
+  auto mark = [&](hipStream_t s) -> hipEvent_t {
+    if (!two) return nullptr;
+    hipEvent_t e = sync_event(c);
+    if (!e) {
+      ok_ev = false;
+      return nullptr;
+    }
+    plan_record(b, e, s);
+    return e;
+  };
+  auto wait = [&](hipStream_t s, hipEvent_t e) {
+    if (two && e) plan_wait(b, s, e);
+  };
+  auto join = [&](hipStream_t from, hipStream_t to) {
+    wait(to, mark(from));
+    return true;
+  };
+  hipEvent_t kmap_k0 = nullptr;
   for (int d = 0; d < D; d++) {
-    if (d >= 1 && d <= k0) plan_shallow(b, m, lv, fr, B, d, st);
-    if (d > k0) plan_deep(b, m, lv, fr, B, {d}, st);
+    const int t = d + 1;  // the shallow depth whose features this iteration prepares
+    if (d > k0) {
+      if (d == k0 + 1) wait(st, kmap_k0);  // the neighbour table of k0
+      plan_deep(b, m, lv, fr, B, {d}, st);
+    }
+    hipEvent_t resblock = nullptr;
+    if (t <= k0) {
+      join(st, sd);  // F_d
+      plan_shallow_convs(b, m, fr, B, t, sd);
+      resblock = mark(sd);
+    }
     PredSeg p;
     memset(&p, 0, sizeof(p));
     p.F = features_of(m, B, d);
@@ -1491,7 +1568,20 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
                                     st);
       });
     }
-    if (d + 1 <= k0 && B.kmap[d + 1]) plan_kmap_only(b, lv, fr, B, d + 1, st);
+    if (t <= k0 && B.kmap[t]) {
+      join(st, sd);  // the expansion filled the hash table of depth t
+      plan_kmap_only(b, lv, fr, B, t, sd);
+      if (t == k0) kmap_k0 = mark(sd);
+    }
+    if (t <= k0) {
+      wait(st, resblock);  // the ResBlock output (not the neighbour table)
+      plan_shallow_up(b, m, lv, fr, B, t, st);
+    }
+  }
+  join(sd, st);
+  if (!ok_ev) {
+    c->err = "event creation failed";
+    return LPCC_E_DEVICE;
   }
   s = run_batch(c, b, &desc_off);
   if (s) return s;
@@ -1647,6 +1737,8 @@ void lpcc_ctx_free(lpcc_ctx* c) {
   }
   for (auto e : c->ev_free) (void)hipEventDestroy(e);
   for (auto& kv : c->gexec) (void)hipGraphExecDestroy(kv.second);
+  for (auto e : c->sync_ev) (void)hipEventDestroy(e);
+  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
 }
