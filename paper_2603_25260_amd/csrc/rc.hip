@@ -1,27 +1,44 @@
 // Range coder on gfx950: G. N. N. Martin's byte-oriented range coder (1979)
 // with a cache byte and carry propagation; 32-bit range, 16-bit totals.  The
 // stream of every (frame, depth) is cut into chunks of 2^c nodes that are
-// coded independently: encoding runs one lane per chunk (all depths at once),
+// coded independently: encoding runs one wave per chunk (all depths at once),
 // decoding one wave per chunk with a wave-wide symbol search over the CDF.
 #include "lpcc_internal.h"
 
 namespace lpcc {
 
 // ---------------------------------------------------------------------------
-// Encoder: lane per chunk.  Node i of the chunk carries start | freq << 16.
-// Output bytes are gathered into 32-bit words before they are stored.
+// Encoder: one wave per chunk.  The coder state is wave-uniform (scalar
+// registers); the node values start | freq << 16 are loaded 64 at a time
+// (one per lane, the next 64 in flight) and taken one by one with readlane.
+// Output bytes are packed into 32-bit words; word w of the chunk is kept in
+// lane w % 64 of a vector register and every 64 words are stored at once.
 // ---------------------------------------------------------------------------
-struct ByteSink {
-  uint32_t* out;
-  uint32_t pos;
-  uint32_t word;
+struct WaveSink {
+  GAS uint32_t* out;
+  uint32_t pos;   // bytes emitted
+  uint32_t word;  // the word being filled
+  uint32_t ob;    // words of the current group of 64, word w in lane w % 64
+  int lane;
   __device__ __forceinline__ void put(uint32_t b) {
     word |= (b & 0xFFu) << (8 * (pos & 3u));
     if ((pos & 3u) == 3u) {
-      out[pos >> 2] = word;
+      const uint32_t wi = pos >> 2;
+      ob = lane == (int)(wi & 63u) ? word : ob;
       word = 0;
+      if ((wi & 63u) == 63u) out[(wi & ~63u) + (uint32_t)lane] = ob;
     }
     pos++;
+  }
+  // the last partial word and the group not stored yet: put() stores a group
+  // when its word 63 completes, so words from (complete words & ~63) on are
+  // still in ob
+  __device__ __forceinline__ void finish() {
+    const uint32_t cw = pos >> 2;  // complete words
+    if (pos & 3u) ob = lane == (int)(cw & 63u) ? word : ob;
+    const uint32_t g0 = cw & ~63u;
+    const uint32_t left = ((pos + 3u) >> 2) - g0;  // 0 .. 64
+    if ((uint32_t)lane < left) out[g0 + (uint32_t)lane] = ob;
   }
 };
 
@@ -30,7 +47,7 @@ struct RcEnc {
   uint32_t range;
   uint32_t cache;
   uint32_t pending;
-  __device__ __forceinline__ void shift_low(ByteSink& o) {
+  __device__ __forceinline__ void shift_low(WaveSink& o) {
     if (low < 0xFF000000ull || low >= 0x100000000ull) {
       const uint32_t carry = (uint32_t)(low >> 32);
       o.put(cache + carry);
@@ -43,7 +60,7 @@ struct RcEnc {
   }
   // freq >= 1 always holds for the model's tables; a zero is clamped so that
   // the renormalisation loop always ends
-  __device__ __forceinline__ void encode(uint32_t sf, ByteSink& o) {
+  __device__ __forceinline__ void encode(uint32_t sf, WaveSink& o) {
     const uint32_t start = sf & 0xFFFFu, freq = (sf >> 16) ? (sf >> 16) : 1u;
     const uint32_t r = range >> 16;
     low += (uint64_t)r * start;
@@ -55,54 +72,31 @@ struct RcEnc {
   }
 };
 
-constexpr int kEncBlock = 32;  // symbols staged per lane and block
-
 __global__ __launch_bounds__(64) void k_rc_encode(const Chunk* __restrict__ chunks, int nch,
                                                   const uint32_t* __restrict__ sf, uint8_t* __restrict__ scratch,
                                                   uint32_t* __restrict__ lens) {
-  // lane-private rows, padded to 33 words so that lanes reading the same
-  // column hit different banks
-  __shared__ uint32_t stg[64][kEncBlock + 1];
   const int lane = threadIdx.x;
-  const int c = blockIdx.x * blockDim.x + lane;
-  const bool live = c < nch;
-  Chunk ch;
-  ch.node0 = 0;
-  ch.count = 0;
-  ch.scratch = 0;
-  if (live) ch = chunks[c];
-  ByteSink o{(uint32_t*)(scratch + ch.scratch), 0u, 0u};
+  const Chunk ch = chunks[blockIdx.x];
+  WaveSink o{(GAS uint32_t*)(scratch + ch.scratch), 0u, 0u, 0u, lane};
   RcEnc e{0ull, 0xFFFFFFFFu, 0u, 1u};
-  const uint32_t* p = sf + ch.node0;
+  const GAS uint32_t* p = gp(sf) + ch.node0;
   const int n = ch.count;
-  // every lane takes part in the staging rounds of the longest chunk
-  int nmax = n;
-#pragma unroll
-  for (int o2 = 32; o2 > 0; o2 >>= 1) nmax = max(nmax, __shfl_xor(nmax, o2));
-  for (int base = 0; base < nmax; base += kEncBlock) {
-    const int cnt = min(kEncBlock, max(n - base, 0));
-    uint32_t t[kEncBlock];
-#pragma unroll
-    for (int k = 0; k < kEncBlock; k++) t[k] = cnt > 0 ? p[base + min(k, cnt - 1)] : 0u;
-#pragma unroll
-    for (int k = 0; k < kEncBlock; k++) stg[lane][k] = t[k];
-    uint32_t nxt = stg[lane][0];
-    for (int k = 0; k < cnt; k++) {
-      const uint32_t v = nxt;
-      nxt = stg[lane][min(k + 1, kEncBlock - 1)];
-      e.encode(v, o);
-    }
+  uint32_t v = lane < n ? p[lane] : 0u;
+  for (int base = 0; base < n; base += 64) {
+    const int cnt = min(64, n - base);
+    const uint32_t vn = base + 64 + lane < n ? p[base + 64 + lane] : 0u;  // next 64 in flight
+    for (int k = 0; k < cnt; k++) e.encode((uint32_t)__builtin_amdgcn_readlane((int)v, k), o);
+    v = vn;
   }
-  if (!live) return;
   for (int k = 0; k < 5; k++) e.shift_low(o);
-  if (o.pos & 3u) o.out[o.pos >> 2] = o.word;
-  lens[c] = o.pos;
+  o.finish();
+  if (lane == 0) lens[blockIdx.x] = o.pos;
 }
 
 hipError_t launch_rc_encode(const Chunk* chunks, int nchunks, const uint32_t* sf, uint8_t* scratch, uint32_t* lens,
                             hipStream_t s) {
   if (nchunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rc_encode, dim3((nchunks + 63) / 64), dim3(64), 0, s, chunks, nchunks, sf, scratch, lens);
+  hipLaunchKernelGGL(k_rc_encode, dim3(nchunks), dim3(64), 0, s, chunks, nchunks, sf, scratch, lens);
   return hipGetLastError();
 }
 
