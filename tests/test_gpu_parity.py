@@ -89,6 +89,19 @@ def test_encode_bytes_and_round_trip_small(L, ctx, C, D, nd, n, seed, zp):
         assert np.array_equal(dec, sorted_unique(xyz, D))
 
 
+def test_long_chunks_decode_from_lds(L, ctx):
+    """Chunks of 2^12 and 2^14 nodes: payloads beyond the register window are
+    read from LDS by the decoder."""
+    blob, m = model(L, 8, 32, 10, 3)
+    xyz = synth.random_cloud(15000, 10, 8)
+    for c in (12, 14):
+        _note("long chunks", c)
+        want = O.encode(blob, xyz, c)
+        got = L.encode_frame(ctx, m, xyz, c)
+        assert got == want
+        assert np.array_equal(L.decode_frame(ctx, m, got), sorted_unique(xyz, D=10))
+
+
 def test_config1_all_depths_and_stream(L, ctx):
     cfg = synth.CONFIGS["cfg1"]
     blob, m = model(L, cfg.weight_seed, cfg.C, cfg.scan.D, cfg.n_deep)

@@ -20,14 +20,16 @@ def L():
     return lpcc
 
 
-# (C, D, n_deep, points): every width the kernels are built for, several
-# 64 x rb tiles per level and ragged tails
-CASES = [(16, 9, 3, 3000), (32, 10, 4, 9000), (64, 10, 4, 7000)]
+# (C, D, n_deep, points, zero points): every width the kernels are built
+# for, several 64 x rb tiles per level and ragged tails; nonzero input zero
+# points exercise the per-tap corrections (present neighbours only)
+CASES = [(16, 9, 3, 3000, False), (32, 10, 4, 9000, False), (64, 10, 4, 7000, False),
+         (32, 9, 3, 5000, True), (64, 9, 3, 4000, True)]
 
 
-@pytest.mark.parametrize("C,D,n_deep,npts", CASES)
-def test_fixed_tilings_match_oracle(L, C, D, n_deep, npts):
-    blob = synth.make_weights(11 + C, C, D, n_deep)
+@pytest.mark.parametrize("C,D,n_deep,npts,zp", CASES)
+def test_fixed_tilings_match_oracle(L, C, D, n_deep, npts, zp):
+    blob = synth.make_weights(11 + C, C, D, n_deep, zero_points=zp)
     xyz = synth.random_cloud(npts, D, 500 + C)
     want = O.encode(blob, xyz, 7)
     d_deep, d_shallow = D - 1, D - n_deep - 2
@@ -37,7 +39,7 @@ def test_fixed_tilings_match_oracle(L, C, D, n_deep, npts):
     for rb in (1, 2, 4):
         ctx = L.Context(0)
         ctx.set_tiling(rb)
-        print("C", C, "rb", rb, flush=True)
+        print("C", C, "zp", zp, "rb", rb, flush=True)
         assert L.encode_frame(ctx, m, dx, 7) == want, f"rb={rb}"
         assert np.array_equal(L.level_probs(ctx, m, dx, d_deep), p_deep), f"rb={rb} deep"
         assert np.array_equal(L.level_probs(ctx, m, dx, d_shallow), p_sh), f"rb={rb} shallow"
