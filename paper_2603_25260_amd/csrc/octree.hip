@@ -91,27 +91,38 @@ hipError_t launch_level_hist(const uint64_t* keys, int64_t n, int D, int tile, u
 }
 
 // In place: hist[t][d] <- #elements of tiles < t with d* <= d (exclusive over
-// tiles, cumulative over depth).  totals[d] = N_d.  One block.
-__global__ void k_level_scan(uint32_t* __restrict__ hist, int nb, int D, uint32_t* __restrict__ totals) {
-  __shared__ uint32_t part[kLevelThreads][kMaxD + 1];
-  int tid = threadIdx.x;
-  int per = (nb + kLevelThreads - 1) / kLevelThreads;
-  int t0 = tid * per, t1 = min(nb, t0 + per);
+// tiles, cumulative over depth).  totals[d] = N_d.  One block: every thread
+// sums a run of tiles, a block-wide exclusive scan (wave shuffles, then the
+// four wave totals) gives each run its offsets, the runs are rewritten.
+__global__ __launch_bounds__(kLevelThreads) void k_level_scan(uint32_t* __restrict__ hist, int nb, int D,
+                                                             uint32_t* __restrict__ totals) {
+  __shared__ uint32_t wsum[kLevelThreads / 64][kMaxD + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (nb + kLevelThreads - 1) / kLevelThreads;
+  const int t0 = tid * per, t1 = min(nb, t0 + per);
   uint32_t run[kMaxD + 1];
   for (int d = 0; d <= D; d++) run[d] = 0;
   for (int t = t0; t < t1; t++) {
     uint32_t c = 0;
     for (int d = 0; d <= D; d++) { c += hist[(int64_t)t * (D + 1) + d]; run[d] += c; }
   }
-  for (int d = 0; d <= D; d++) part[tid][d] = run[d];
-  __syncthreads();
-  if (tid <= D) {  // serial exclusive scan over threads, one depth per thread
-    uint32_t acc = 0;
-    for (int k = 0; k < (int)blockDim.x; k++) { uint32_t v = part[k][tid]; part[k][tid] = acc; acc += v; }
-    totals[tid] = acc;
+  for (int d = 0; d <= D; d++) {
+    uint32_t inc = run[d];
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t v = __shfl_up(inc, off);
+      if (lane >= off) inc += v;
+    }
+    if (lane == 63) wsum[wave][d] = inc;
+    run[d] = inc - run[d];  // exclusive within the wave
   }
   __syncthreads();
-  for (int d = 0; d <= D; d++) run[d] = part[tid][d];
+  for (int d = 0; d <= D; d++)
+    for (int w = 0; w < wave; w++) run[d] += wsum[w][d];
+  if (tid <= D) {
+    uint32_t tot = 0;
+    for (int w = 0; w < kLevelThreads / 64; w++) tot += wsum[w][tid];
+    totals[tid] = tot;
+  }
   for (int t = t0; t < t1; t++) {
     uint32_t c = 0, inc[kMaxD + 1];
     for (int d = 0; d <= D; d++) { c += hist[(int64_t)t * (D + 1) + d]; inc[d] = c; }

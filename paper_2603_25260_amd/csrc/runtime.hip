@@ -1342,16 +1342,64 @@ int parse_header(const uint8_t* h, size_t avail, size_t len, Header& H, bool nee
   return LPCC_OK;
 }
 
-int read_header(lpcc_ctx* c, const uint8_t* bs, size_t len, Header& H) {
-  if (!bs) return LPCC_E_INVAL;
-  if (!is_device_ptr(bs)) return parse_header(bs, len, len, H, true);
-  std::vector<uint8_t> tmp(std::min<size_t>(len, 16 + 4 * kMaxD));
-  HIPC(hipMemcpy(tmp.data(), bs, tmp.size(), hipMemcpyDeviceToHost));
-  int s = parse_header(tmp.data(), tmp.size(), len, H, false);
+// Headers of all frames.  Host streams are parsed in place; device streams
+// are copied to pinned memory: a prefix that holds the whole header up to
+// 4096 chunk lengths for every frame in one round trip, then the rest of any
+// longer header in a second one.
+constexpr size_t kHdrPrefix = 16 + 4 * kMaxD + 2 * 4096;
+
+int read_headers(lpcc_ctx* c, int nf, const uint8_t* const* bs, const size_t* len, std::vector<Header>& H,
+                 std::vector<int>& st) {
+  std::vector<size_t> off(nf, 0), got(nf, 0);
+  std::vector<bool> dev(nf, false);
+  size_t need = 0;
+  for (int f = 0; f < nf; f++) {
+    st[f] = LPCC_OK;
+    if (!bs[f]) {
+      st[f] = LPCC_E_INVAL;
+      continue;
+    }
+    dev[f] = is_device_ptr(bs[f]);
+    if (!dev[f]) {
+      st[f] = parse_header(bs[f], len[f], len[f], H[f], true);
+      continue;
+    }
+    off[f] = need;
+    got[f] = std::min(len[f], kHdrPrefix);
+    need += align_up(got[f], 64);
+  }
+  if (need == 0) return LPCC_OK;
+  int s = reserve_pinned(c, need);
   if (s) return s;
-  tmp.resize(H.hdr);
-  HIPC(hipMemcpy(tmp.data(), bs, H.hdr, hipMemcpyDeviceToHost));
-  return parse_header(tmp.data(), tmp.size(), len, H, true);
+  for (int f = 0; f < nf; f++)
+    if (dev[f] && got[f]) HIPC(hipMemcpyAsync(c->pinned + off[f], bs[f], got[f], hipMemcpyDeviceToHost, c->stream));
+  HIPC(hipStreamSynchronize(c->stream));
+  std::vector<int> more;
+  size_t need2 = 0;
+  for (int f = 0; f < nf; f++) {
+    if (!dev[f]) continue;
+    st[f] = parse_header(c->pinned + off[f], got[f], len[f], H[f], true);
+    if (st[f] == LPCC_E_CAPACITY) {  // longer than the prefix: fetch the whole header
+      st[f] = parse_header(c->pinned + off[f], got[f], len[f], H[f], false);
+      if (st[f] == LPCC_OK) {
+        more.push_back(f);
+        need2 += align_up(H[f].hdr, 64);
+      }
+    }
+  }
+  if (more.empty()) return LPCC_OK;
+  // the first round's bytes are parsed; the buffer is reused
+  s = reserve_pinned(c, need2);
+  if (s) return s;
+  size_t o = 0;
+  for (int f : more) {
+    off[f] = o;
+    HIPC(hipMemcpyAsync(c->pinned + o, bs[f], H[f].hdr, hipMemcpyDeviceToHost, c->stream));
+    o += align_up(H[f].hdr, 64);
+  }
+  HIPC(hipStreamSynchronize(c->stream));
+  for (int f : more) st[f] = parse_header(c->pinned + off[f], H[f].hdr, len[f], H[f], true);
+  return LPCC_OK;
 }
 
 int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* bs, const size_t* len,
@@ -1362,11 +1410,14 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   c->batch_idx = 0;
   hipStream_t st = c->stream;
   std::vector<Header> H(nf);
-  std::vector<int> live;
+  std::vector<int> live, hst(nf, LPCC_OK);
+  {
+    const int s = read_headers(c, nf, bs, len, H, hst);
+    if (s) return s;
+  }
   for (int f = 0; f < nf; f++) {
     n_out[f] = 0;
-    int s = read_header(c, bs[f], len[f], H[f]);
-    if (s == LPCC_E_DEVICE || s == LPCC_E_NOMEM) return s;
+    int s = hst[f];
     if (s == LPCC_OK && (H[f].D != D || H[f].n_deep != m->n_deep || H[f].blob != m->blob_id)) s = LPCC_E_MODEL;
     if (s == LPCC_OK) {
       n_out[f] = H[f].N[D];
