@@ -779,14 +779,17 @@ void plan_wait(Batch& b, hipStream_t s, hipEvent_t e) {
 }
 
 // Deep depths `ds` (all > k0), stage by stage; every launch covers all of them.
+// part 1: the re-densification (embedding and stride-2 steps; codes only),
+// part 2: ResBlock at k0 and the upsampling chain (needs F_k0), 0: both.
 void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B,
-               const std::vector<int>& dset, hipStream_t st) {
+               const std::vector<int>& dset, hipStream_t st, int part = 0) {
   if (dset.empty()) return;
   const int C = m->C, k0 = m->k0;
   auto Gout = [&](int d, int j) -> std::pair<int8_t*, int64_t> {  // destination of depth-j G of target d
     if (j == k0) return {B.Gk[d], C};
     return {B.G[d][j], C};
   };
+  if (part != 2) {
   // occupancy embedding at depth d-1
   {
     std::vector<GemmSeg> v;
@@ -825,6 +828,8 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
     }
     plan_gemm(b, m, "down", G_DOWN, C, C, v, st);
   }
+  }
+  if (part == 1) return;
   // ResBlock at k0: conv1 (2C -> C), skip (2C -> C), conv2 (+ skip)
   std::vector<GemmSeg> c1, sk, c2;
   for (int d : dset) {
@@ -1175,13 +1180,43 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     plan_hash_clear(b, B, st);
     plan_kmaps(b, lv, fr, B, js, st);
   }
-  for (int d = 1; d <= std::min(last, k0); d++) plan_shallow(b, m, lv, fr, B, d, st);
+  // Two streams: the re-densification of the deep depths needs only the
+  // codes and runs beside the shallow chain; the predictor of the shallow
+  // depths runs beside the deep ResBlock and upsampling.
+  c->sync_used = 0;
+  bool two = c->time_family.empty() && !c->graphs;
+  if (two && !c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    c->side = nullptr;
+  }
+  two = two && c->side;
+  const hipStream_t sd = two ? c->side : st;
+  bool ok_ev = true;
+  auto mark = [&](hipStream_t ss) -> hipEvent_t {
+    if (!two) return nullptr;
+    hipEvent_t e = sync_event(c);
+    if (!e) {
+      ok_ev = false;
+      return nullptr;
+    }
+    plan_record(b, e, ss);
+    return e;
+  };
+  auto wait = [&](hipStream_t ss, hipEvent_t e) {
+    if (two && e) plan_wait(b, ss, e);
+  };
   std::vector<int> dset;
   for (int d = k0 + 1; d <= last; d++)
     if (wanted[d]) dset.push_back(d);
-  plan_deep(b, m, lv, fr, B, dset, st);
-  // predictor
-  std::vector<PredSeg> ps;
+  wait(sd, mark(st));  // the side stream starts after the fills
+  plan_deep(b, m, lv, fr, B, dset, sd, 1);
+  hipEvent_t g_done = mark(sd);
+  for (int d = 1; d <= std::min(last, k0); d++) plan_shallow(b, m, lv, fr, B, d, st);
+  hipEvent_t f_done = mark(st);
+  wait(st, g_done);
+  plan_deep(b, m, lv, fr, B, dset, st, 2);
+  // predictor: shallow depths on the side stream, deep depths here
+  std::vector<PredSeg> ps, pd;
   for (int d = 0; d <= last; d++) {
     if (!wanted[d] || fr.tot[d] == 0) continue;
     PredSeg p;
@@ -1193,9 +1228,18 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     p.rows = (int)fr.tot[d];
     if (probe) p.cdf32 = cdf_dev ? cdf_out : cdf_stage;
     else p.sf = sf + dbase[d];
-    ps.push_back(p);
+    (d <= k0 && two ? ps : pd).push_back(p);
   }
-  plan_predict(b, m, ps, probe ? 2 : 0, st);
+  if (!ps.empty()) {
+    wait(sd, f_done);
+    plan_predict(b, m, ps, probe ? 2 : 0, sd);
+  }
+  plan_predict(b, m, pd, probe ? 2 : 0, st);
+  wait(st, mark(sd));
+  if (!ok_ev) {
+    c->err = "event creation failed";
+    return LPCC_E_DEVICE;
+  }
   if (!probe && !chunks.empty()) {
     const size_t co = b.add(chunks);
     const int nch = (int)chunks.size();
