@@ -220,6 +220,8 @@ hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int 
                      int rb, hipStream_t s);
 hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, const GemmArg& one,
                       hipStream_t s);
+// single-segment predictor launches up to this many rows take 4 rows per wave
+constexpr int kPredSmall = 8192;
 hipError_t launch_predict(int C, int mode, const PredSeg* segs_dev, const Tile* tiles_dev, int ntiles,
                           const int32_t* lut, const PredArg& one, hipStream_t s);
 

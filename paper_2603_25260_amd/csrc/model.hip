@@ -599,9 +599,15 @@ __device__ __forceinline__ int red16_sum(int v) {
 
 enum { P_ENCODE = 0, P_CDF16 = 1, P_CDF32 = 2 };
 
-template <int C, int MODE>
+// NI = nodes per group of 16 lanes: 4 (a wave handles 16 nodes) or 1 for
+// small launches (4 nodes per wave at MFMA rows 0, 4, 8, 12: a quarter of the
+// per-lane softmax work, so short launches finish sooner).
+template <int C, int MODE, int NI>
 __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ segs, const Tile* __restrict__ tiles,
                                                  const int32_t* __restrict__ lut_g, const PredArg A) {
+  static_assert(NI == 4 || NI == 1, "NI");
+  // node (within the wave) of output group g, row i, and the MFMA row of a node
+  auto node_of = [](int g_, int i_) { return NI == 4 ? 4 * g_ + i_ : g_; };
   __shared__ int32_t lut[256];
   __shared__ int8_t hs[4][16][64];
   __shared__ __attribute__((aligned(16))) uint16_t fs[MODE == P_ENCODE ? 1 : 4][16][256];
@@ -614,7 +620,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
     S = A.seg;
     L1 = A.fc1;
     L2 = A.fc2;
-    tile_row0 = (int)blockIdx.x * 64;
+    tile_row0 = (int)blockIdx.x * 16 * NI;
   } else {
     const Tile tl = tiles[blockIdx.x];
     S = segs[tl.seg];
@@ -624,9 +630,10 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
-  const int row0 = tile_row0 + wave * 16;
-  const int row = row0 + r;
-  const bool rv = row < S.rows;
+  const int row0 = tile_row0 + wave * 4 * NI;
+  // A operand: lane row r is MFMA row r; with NI = 1 only rows 0, 4, 8, 12 hold nodes
+  const int row = NI == 4 ? row0 + r : row0 + (r >> 2);
+  const bool rv = row < S.rows && (NI == 4 || (r & 3) == 0);
 
   // fc1: K = C (padded to 64)
   constexpr int NB1 = C / 16;
@@ -660,22 +667,22 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   v4i h = *(const v4i*)&hs[wave][r][16 * g];
 
   // fc2: 16 column blocks of 16 logits
-  int lg[4][16];
+  int lg[NI][16];
 #pragma unroll
   for (int b = 0; b < 16; b++) {
     v4i acc = mfma16(h, w2[b], v4i{0, 0, 0, 0});
     const int col = 16 * b + r;
     const int bias = b2[b];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < NI; i++)
       lg[i][b] = col < kNSym ? requant_l(acc[i] + bias, L2) : -1000;
   }
 
   // per row: max, lowest argmax, E_i = LUT[M - l_i] (replacing the logits), S
-  int arg[4];
-  uint32_t Sr[4];
+  int arg[NI];
+  uint32_t Sr[NI];
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
+  for (int i = 0; i < NI; i++) {
     int M = -1000;
 #pragma unroll
     for (int b = 0; b < 16; b++) M = max(M, lg[i][b]);
@@ -696,16 +703,20 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   }
   // one reciprocal per lane (lane r computes row r % 4 of its group), shared
   // within the group of 16 lanes
-  const int ri = r & 3;
-  const uint32_t Ssel = ri == 0 ? Sr[0] : (ri == 1 ? Sr[1] : (ri == 2 ? Sr[2] : Sr[3]));
-  const uint32_t invsel = recip32(Ssel);
-  uint32_t inv[4];
+  uint32_t inv[NI];
+  if (NI == 4) {
+    const int ri = r & 3;
+    const uint32_t Ssel = ri == 0 ? Sr[0] : (ri == 1 ? Sr[1 % NI] : (ri == 2 ? Sr[2 % NI] : Sr[3 % NI]));
+    const uint32_t invsel = recip32(Ssel);
 #pragma unroll
-  for (int i = 0; i < 4; i++) inv[i] = (uint32_t)__shfl((int)invsel, (lane & 48) | i);
+    for (int i = 0; i < NI; i++) inv[i] = (uint32_t)__shfl((int)invsel, (lane & 48) | i);
+  } else {
+    inv[0] = recip32(Sr[0]);
+  }
 
 #pragma unroll
-  for (int i = 0; i < 4; i++) {
-    const int nrow = row0 + 4 * g + i;
+  for (int i = 0; i < NI; i++) {
+    const int nrow = row0 + node_of(g, i);
     const uint32_t S_ = Sr[i];
     int f[16];
     int fsum = 0;
@@ -732,9 +743,9 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
       fr = red16_sum(fr);
       if (r == 0 && nrow < S.rows) gp(S.sf)[nrow] = (uint32_t)st_ | ((uint32_t)fr << 16);
     } else {
-      // frequencies of row 4g+i into LDS for the row-wise prefix below
+      // frequencies of the node into LDS for the row-wise prefix below
 #pragma unroll
-      for (int b = 0; b < 16; b++) fs[wave][4 * g + i][16 * b + r] = (uint16_t)f[b];
+      for (int b = 0; b < 16; b++) fs[wave][node_of(g, i)][16 * b + r] = (uint16_t)f[b];
     }
   }
   if (MODE != P_ENCODE) {
@@ -745,8 +756,8 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
     // entries 16r..16r+15 of row 4p+q: serial prefix in registers, exclusive
     // scan of the lane totals across the 16 lanes of the row
 #pragma unroll
-    for (int p = 0; p < 4; p++) {
-      const int prow = 4 * p + g;
+    for (int p = 0; p < NI; p++) {
+      const int prow = NI == 4 ? 4 * p + g : g;
       const uint4* src = (const uint4*)&fs[wave][prow][16 * r];
       const uint4 u0 = src[0], u1 = src[1];
       const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
@@ -797,10 +808,16 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
 hipError_t launch_predict(int C, int mode, const PredSeg* segs, const Tile* tiles, int ntiles, const int32_t* lut,
                           const PredArg& A, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-#define LPCC_P(CC, MM)                                                                               \
-  if (C == CC && mode == MM) {                                                                       \
-    hipLaunchKernelGGL((k_predict<CC, MM>), dim3(ntiles), dim3(256), 0, s, segs, tiles, lut, A);     \
-    return hipGetLastError();                                                                        \
+  // single-segment launches of at most kPredSmall rows use 4 nodes per wave
+  const bool small = A.one && A.seg.rows <= kPredSmall;
+  const int grid = small ? (A.seg.rows + 15) / 16 : ntiles;
+#define LPCC_P(CC, MM)                                                                                   \
+  if (C == CC && mode == MM) {                                                                           \
+    if (small)                                                                                           \
+      hipLaunchKernelGGL((k_predict<CC, MM, 1>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);      \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_predict<CC, MM, 4>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);      \
+    return hipGetLastError();                                                                            \
   }
   LPCC_P(16, 0) LPCC_P(16, 1) LPCC_P(16, 2)
   LPCC_P(32, 0) LPCC_P(32, 1) LPCC_P(32, 2)
