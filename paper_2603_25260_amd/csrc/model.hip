@@ -382,6 +382,11 @@ hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs, const T
 // Upsampling + pruning: per parent p, A = [Z[p] (C) | bits(X[p]) (8)],
 // out block o (columns oC..oC+C-1) is child slot o; occupied slots only,
 // child row = cstart[p] + rank of o among the set bits.
+//
+// The product is formed transposed (weights as the MFMA row operand,
+// parents as columns), so that every lane ends with four consecutive output
+// channels of one parent: it requantises them and writes one 32-bit word of
+// the child row directly, with no staging of the accumulators.
 // ---------------------------------------------------------------------------
 template <int C, int RB>
 __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
@@ -390,10 +395,7 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
   constexpr int NBS = C / 16;          // column blocks per child slot
   constexpr int NBT = 8 * NBS;         // column blocks of the layer
   constexpr int WR = 16 * RB;          // parent rows per wave
-  // per wave: the accumulator tile of one slot, and the parents' codes / first children
-  __shared__ int32_t st[4][16][C + 1];
-  __shared__ uint32_t pc[4][WR];
-  __shared__ int32_t ps[4][WR];
+  static_assert(C % 16 == 0, "C");
 
   GemmSeg S;
   LayerDev L;
@@ -401,26 +403,17 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const int wrow0 = tile_row0 + wave * WR;
+  // lane (r, g) serves parent row wrow0 + 16 rb + r
   uint32_t code[RB];
+  int first[RB];
 #pragma unroll
   for (int rb = 0; rb < RB; rb++) {
     const int row = wrow0 + 16 * rb + r;
     code[rb] = row < S.rows ? gp(S.code)[row] : 0u;
-    if (g == 0) {
-      pc[wave][16 * rb + r] = code[rb];
-      ps[wave][16 * rb + r] = row < S.rows ? gp(S.cstart)[row] : 0;
-    }
+    first[rb] = row < S.rows ? gp(S.cstart)[row] : 0;
   }
-  // output: 4 consecutive columns per lane, C/4 lanes per child row
-  static_assert(C % 4 == 0 && 64 % (C / 4) == 0, "C");
-  constexpr int LPR = C / 4, RPP = 64 / LPR;
-  const int jl = lane / LPR, c4 = (lane % LPR) * 4;
-  int bia[8][4];
-#pragma unroll
-  for (int o = 0; o < 8; o++)
-#pragma unroll
-    for (int q = 0; q < 4; q++) bia[o][q] = gp(L.bias)[o * C + c4 + q];
 
+  // column operand: k-slice 16g..16g+15 of the parent's input row
   v4i a[RB][KS];
 #pragma unroll
   for (int rb = 0; rb < RB; rb++) {
@@ -443,16 +436,17 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
       }
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const GAS v4i* Wp = (const GAS v4i*)L.Wp;
-  // weights of slot o+1 are in flight while slot o is computed
-  v4i wb[2][KS][NBS];
+  const GAS v4i* Bp = (const GAS v4i*)L.bias;
+  // weights and biases of slot o+1 are in flight while slot o is computed;
+  // lane (r, g) holds the bias of channels 16 nb + 4g .. +3
+  v4i wb[2][KS][NBS], bb[2][NBS];
 #pragma unroll
   for (int s = 0; s < KS; s++)
 #pragma unroll
     for (int nb = 0; nb < NBS; nb++) wb[0][s][nb] = Wp[((int64_t)s * NBT + nb) * 64 + lane];
+#pragma unroll
+  for (int nb = 0; nb < NBS; nb++) bb[0][nb] = Bp[(16 * nb + 4 * g) / 4];
 
 #pragma unroll
   for (int o = 0; o < 8; o++) {
@@ -462,49 +456,34 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
 #pragma unroll
         for (int nb = 0; nb < NBS; nb++)
           wb[(o + 1) & 1][s][nb] = Wp[((int64_t)s * NBT + (o + 1) * NBS + nb) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < NBS; nb++) bb[(o + 1) & 1][nb] = Bp[((o + 1) * C + 16 * nb + 4 * g) / 4];
     }
 #pragma unroll
     for (int rb = 0; rb < RB; rb++) {
-      // rows of this block whose parent has child slot o (wave-uniform)
-      const uint32_t m = (uint32_t)(__ballot((code[rb] >> o) & 1u) & 0xFFFFull);
-      if (m == 0u) continue;
+      const bool has = (code[rb] >> o) & 1u;
+      if (__ballot(has) == 0ull) continue;  // no parent of the block has child o
       v4i acc[NBS];
 #pragma unroll
       for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS; s++)
 #pragma unroll
-        for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(a[rb][s], wb[o & 1][s][nb], acc[nb]);
+        for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(wb[o & 1][s][nb], a[rb][s], acc[nb]);
+      if (!has) continue;
+      const int crow = first[rb] + __popc(code[rb] & ((1u << o) - 1u));
+      if (crow >= S.child_rows) continue;  // only for a corrupt stream
+      GAS uint32_t* dst = (GAS uint32_t*)(gp(S.out) + (int64_t)crow * S.out_stride + 4 * g);
 #pragma unroll
-      for (int nb = 0; nb < NBS; nb++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) st[wave][4 * g + i][16 * nb + r] = acc[nb][i];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // only the occupied (row, slot) outputs: k rows of C columns, RPP rows
-      // per pass, 4 columns (one 32-bit store) per lane
-      const int k = __popc(m);
-      for (int j = jl; j < k; j += RPP) {
-        // row of the j-th set bit of m
-        int pos = 0;
-#pragma unroll
-        for (int w = 8; w >= 1; w >>= 1)
-          if (__popc(m & ((1u << (pos + w)) - 1u)) <= j) pos += w;
-        const uint32_t pcode = pc[wave][16 * rb + pos];
-        const int crow = ps[wave][16 * rb + pos] + __popc(pcode & ((1u << o) - 1u));
-        if (crow >= S.child_rows) continue;  // only for a corrupt stream
+      for (int nb = 0; nb < NBS; nb++) {
         uint32_t packed = 0;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-          const int y = requant_l(st[wave][pos][c4 + q] + bia[o][q], L);
-          packed |= ((uint32_t)y & 0xFFu) << (8 * q);
+        for (int i = 0; i < 4; i++) {
+          const int y = requant_l(acc[nb][i] + bb[o & 1][nb][i], L);
+          packed |= ((uint32_t)y & 0xFFu) << (8 * i);
         }
-        *(GAS uint32_t*)(gp(S.out) + (int64_t)crow * S.out_stride + c4) = packed;
+        dst[4 * nb] = packed;
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }

@@ -210,6 +210,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
 
   uint32_t kids = 0;  // children announced by the codes this lane stored
   const bool last_lane = lane == 63;
+  const uint32_t lane4p1 = 4u * (uint32_t)lane + 1u;
   bool bad = false;
 
   // one block of up to kDecBlock symbols from the rows in t (fully unrolled:
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
       if (k < cnt) {
         const uint2 row = t[k];
         const uint32_t nx = (uint32_t)__builtin_amdgcn_mov_dpp((int)row.x, 0x130, 0xF, 0xF, false);  // lane+1
-        if (nb < 2) refill();
+        if (__builtin_expect(nb < 2u, 0)) refill();
         const uint32_t r = range >> 16;
         const uint32_t b0 = row.x & 0xFFFFu, b1 = row.x >> 16, b2 = row.y & 0xFFFFu;
         const uint32_t b3 = last_lane ? 65536u : (row.y >> 16);
@@ -233,7 +234,8 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
         const bool m3 = __umul24(r, b3) <= code;
         const uint32_t lo = m3 ? b3 : (m2 ? b2 : (m1 ? b1 : b0));
         const uint32_t hi = m3 ? b4 : (m2 ? b3 : (m1 ? b2 : b1));
-        const uint32_t sub = (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
+        // code (symbol + 1) of this lane's candidate: 4 lane + 1 + entries passed
+        const uint32_t cand = lane4p1 + (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
         const int L = (int)__popcll(__ballot(m0)) - 1;
         const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)(lo | ((hi - lo) << 16)), L);
         code -= r * (P & 0xFFFFu);
@@ -244,8 +246,8 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
         bb <<= sh;
         nb -= sh >> 3;
         range <<= sh;
-        const int sym = 4 * L + __builtin_amdgcn_readlane((int)sub, L);
-        cv = lane == k ? (uint32_t)(sym + 1) : cv;
+        const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cand, L);
+        cv = lane == k ? c1 : cv;
       }
     }
     bad = range == 0u;
