@@ -234,6 +234,20 @@ int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n);
  */
 int lpcc_softmax_table(int32_t* out);
 
+/*
+ * The form in which the kernels evaluate one layer's requantisation (Eq. 14):
+ * q(a) = ((a m + 2^(r-1)) >> r) + z_out, m = m_pos for a >= 0 else m_neg,
+ * clamped to [-128, 127].  The kernels clamp the int32 accumulator to
+ * [a_lo, a_hi] first: a_hi is the smallest a >= 0 with q(a) >= 127 (INT32_MAX
+ * if none), a_lo the largest a < 0 with q(a) <= -128 (INT32_MIN if none), so
+ * no output changes and the shifted product stays below 2^31.  With r = 0 a
+ * multiplier above 256 is replaced by 256 (the same function).
+ * out[0..3] = {m_pos, m_neg, a_lo, a_hi} as used; host memory, needs no
+ * device.  LPCC_E_INVAL for parameters a weight blob may not hold (negative
+ * multipliers, r outside [0, 62], z_out outside int8).
+ */
+int lpcc_requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z_out, int32_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,32 +27,27 @@ struct LayerDev {
   const int8_t* Wr;     // row-major W[taps][cin][cout] (VALU paths)
   const int32_t* bias;  // [Npad]; dense layers carry -z_in * colsum folded in
   const int32_t* zc;    // [taps][Npad] = -z_in * sum_c W[t][c][o] for sparse layers, or null
-  int32_t m_pos, m_neg;
+  int32_t m_pos, m_neg;  // multipliers (with r = 0 at most 256: the same function)
   int32_t r, z_out;
   int32_t taps, cin, cout;
   int32_t ksteps;       // Kpad / 64
   int32_t npad;
+  int32_t a_lo, a_hi;   // accumulator range outside which the output saturates
   int32_t pad_;
   int64_t rnd;          // 2^(r-1) for r > 0, else 0 (half-up rounding term)
 };
 
 // Requantisation of an int32 accumulator (Eq. 14): sign-selected multiplier,
 // 64-bit product, round half up, arithmetic shift, zero point, clamp to int8.
-__device__ __forceinline__ int requant(int acc, int m_pos, int m_neg, int r, int z_out) {
-  long long m = acc >= 0 ? m_pos : m_neg;
-  long long p = (long long)acc * m;
-  if (r > 0) p = (p + (1ll << (r - 1))) >> r;
-  p += z_out;
-  return p < -128 ? -128 : (p > 127 ? 127 : (int)p);
-}
-
-// Same, with the layer's rounding term precomputed: one 64-bit multiply-add,
-// one arithmetic shift, zero point and clamp.
+// The output is monotone in the accumulator and saturates outside
+// [a_lo, a_hi] (derived on the host from m, r and z_out), so the accumulator
+// is clamped to that range first; inside it the shifted product is far below
+// 2^31, and the zero point and the final clamp are 32-bit operations.
 __device__ __forceinline__ int requant_l(int acc, const LayerDev& L) {
-  const long long m = acc >= 0 ? L.m_pos : L.m_neg;
-  const long long p = ((long long)acc * m + L.rnd) >> L.r;
-  const long long q = p + L.z_out;
-  return q < -128 ? -128 : (q > 127 ? 127 : (int)q);
+  const int a = min(max(acc, L.a_lo), L.a_hi);
+  const long long m = a >= 0 ? L.m_pos : L.m_neg;
+  const int p = (int)(((long long)a * m + L.rnd) >> L.r);
+  return min(max(p + L.z_out, -128), 127);
 }
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -84,6 +79,8 @@ __device__ __forceinline__ LayerDev load_layer(const LayerDev* p) {
   L.cout = q->cout;
   L.ksteps = q->ksteps;
   L.npad = q->npad;
+  L.a_lo = q->a_lo;
+  L.a_hi = q->a_hi;
   L.pad_ = q->pad_;
   L.rnd = q->rnd;
   return L;

@@ -488,6 +488,137 @@ __global__ __launch_bounds__(256) void k_up(const GemmSeg* __restrict__ segs, co
   }
 }
 
+// Staged variant for C = 64: the accumulators of a slot go through LDS and
+// only the occupied (parent, slot) outputs are requantised, RPP child rows
+// per pass.  At the sparse depths most slots hold few children, and this
+// compaction saves more requantisation work than the staging costs; at
+// C <= 32 the direct form above is faster.
+template <int C, int RB>
+__global__ __launch_bounds__(256) void k_up_staged(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                            const GemmArg A) {
+  constexpr int KS = (C + 8 + 63) / 64;
+  constexpr int NBS = C / 16;          // column blocks per child slot
+  constexpr int NBT = 8 * NBS;         // column blocks of the layer
+  constexpr int WR = 16 * RB;          // parent rows per wave
+  // per wave: the accumulator tile of one slot, and the parents' codes / first children
+  __shared__ int32_t st[4][16][C + 1];
+  __shared__ uint32_t pc[4][WR];
+  __shared__ int32_t ps[4][WR];
+
+  GemmSeg S;
+  LayerDev L;
+  const int tile_row0 = pick_seg(segs, tiles, A, S, L, 4 * WR);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int wrow0 = tile_row0 + wave * WR;
+  uint32_t code[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+    const int row = wrow0 + 16 * rb + r;
+    code[rb] = row < S.rows ? gp(S.code)[row] : 0u;
+    if (g == 0) {
+      pc[wave][16 * rb + r] = code[rb];
+      ps[wave][16 * rb + r] = row < S.rows ? gp(S.cstart)[row] : 0;
+    }
+  }
+  // output: 4 consecutive columns per lane, C/4 lanes per child row
+  static_assert(C % 4 == 0 && 64 % (C / 4) == 0, "C");
+  constexpr int LPR = C / 4, RPP = 64 / LPR;
+  const int jl = lane / LPR, c4 = (lane % LPR) * 4;
+  int bia[8][4];
+#pragma unroll
+  for (int o = 0; o < 8; o++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) bia[o][q] = gp(L.bias)[o * C + c4 + q];
+
+  v4i a[RB][KS];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+    const int row = wrow0 + 16 * rb + r;
+    const bool rv = row < S.rows;
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+      const int k0 = 64 * s + 16 * g;
+      a[rb][s] = v4i{0, 0, 0, 0};
+      if (rv && k0 < C) {
+        a[rb][s] = ld16(S.in + (int64_t)row * S.in_stride + k0);
+      } else if (rv && k0 == C) {  // occupancy bits as int8 {0,127}, then zeros
+        uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          if ((code[rb] >> b) & 1u) w0 |= 127u << (8 * b);
+          if ((code[rb] >> (b + 4)) & 1u) w1 |= 127u << (8 * b);
+        }
+        a[rb][s] = v4i{(int)w0, (int)w1, 0, 0};
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const GAS v4i* Wp = (const GAS v4i*)L.Wp;
+  // weights of slot o+1 are in flight while slot o is computed
+  v4i wb[2][KS][NBS];
+#pragma unroll
+  for (int s = 0; s < KS; s++)
+#pragma unroll
+    for (int nb = 0; nb < NBS; nb++) wb[0][s][nb] = Wp[((int64_t)s * NBT + nb) * 64 + lane];
+
+#pragma unroll
+  for (int o = 0; o < 8; o++) {
+    if (o + 1 < 8) {
+#pragma unroll
+      for (int s = 0; s < KS; s++)
+#pragma unroll
+        for (int nb = 0; nb < NBS; nb++)
+          wb[(o + 1) & 1][s][nb] = Wp[((int64_t)s * NBT + (o + 1) * NBS + nb) * 64 + lane];
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++) {
+      // rows of this block whose parent has child slot o (wave-uniform)
+      const uint32_t m = (uint32_t)(__ballot((code[rb] >> o) & 1u) & 0xFFFFull);
+      if (m == 0u) continue;
+      v4i acc[NBS];
+#pragma unroll
+      for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; s++)
+#pragma unroll
+        for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(a[rb][s], wb[o & 1][s][nb], acc[nb]);
+#pragma unroll
+      for (int nb = 0; nb < NBS; nb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) st[wave][4 * g + i][16 * nb + r] = acc[nb][i];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // only the occupied (row, slot) outputs: k rows of C columns, RPP rows
+      // per pass, 4 columns (one 32-bit store) per lane
+      const int k = __popc(m);
+      for (int j = jl; j < k; j += RPP) {
+        // row of the j-th set bit of m
+        int pos = 0;
+#pragma unroll
+        for (int w = 8; w >= 1; w >>= 1)
+          if (__popc(m & ((1u << (pos + w)) - 1u)) <= j) pos += w;
+        const uint32_t pcode = pc[wave][16 * rb + pos];
+        const int crow = ps[wave][16 * rb + pos] + __popc(pcode & ((1u << o) - 1u));
+        if (crow >= S.child_rows) continue;  // only for a corrupt stream
+        uint32_t packed = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int y = requant_l(st[wave][pos][c4 + q] + bia[o][q], L);
+          packed |= ((uint32_t)y & 0xFFu) << (8 * q);
+        }
+        *(GAS uint32_t*)(gp(S.out) + (int64_t)crow * S.out_stride + c4) = packed;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+}
+
 hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, int rb,
                      hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
@@ -498,8 +629,14 @@ hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, 
     else hipLaunchKernelGGL((k_up<CC, 1>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);         \
     return hipGetLastError();                                                                      \
   }
-  LPCC_U(16) LPCC_U(32) LPCC_U(64)
+  LPCC_U(16) LPCC_U(32)
 #undef LPCC_U
+  if (C == 64) {
+    if (rb == 4) hipLaunchKernelGGL((k_up_staged<64, 4>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+    else if (rb == 2) hipLaunchKernelGGL((k_up_staged<64, 2>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+    else hipLaunchKernelGGL((k_up_staged<64, 1>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 

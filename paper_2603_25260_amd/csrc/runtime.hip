@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -145,6 +146,53 @@ int parse_blob(const uint8_t* b, size_t len, lpcc_model* m) {
 
 // Device image of one layer: packed B operand, bias (zero point folded in for
 // dense layers), per-tap zero-point corrections for sparse layers.
+// Requantisation q(a) = ((a m + 2^(r-1)) >> r) + z_out with m = m_pos for
+// a >= 0, m_neg below (m >= 0, so q is non-decreasing on each side of 0),
+// then clamped to int8.  The kernels clamp the accumulator to [a_lo, a_hi]
+// first: a_hi is the smallest a >= 0 with q(a) >= 127 (int32 max if none),
+// a_lo the largest a < 0 with q(a) <= -128 (int32 min if none), so every
+// output is unchanged.  Inside the range |q| < 2^30 + 2^8 when r >= 1; with
+// r = 0 a multiplier above 256 already saturates every nonzero accumulator,
+// so it is lowered to 256, which keeps the function and the bound.
+struct RqBounds {
+  int32_t m_pos, m_neg, a_lo, a_hi;
+};
+
+int64_t requant_q(int64_t a, int64_t m, int r, int z) {
+  const int64_t rnd = r > 0 ? (1ll << (r - 1)) : 0;
+  return ((a * m + rnd) >> r) + z;
+}
+
+RqBounds requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z) {
+  RqBounds B;
+  B.m_pos = r == 0 ? std::min<int32_t>(m_pos, 256) : m_pos;
+  B.m_neg = r == 0 ? std::min<int32_t>(m_neg, 256) : m_neg;
+  int64_t lo = 0, hi = INT32_MAX;
+  if (requant_q(hi, B.m_pos, r, z) < 127) {
+    B.a_hi = INT32_MAX;
+  } else {
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (requant_q(mid, B.m_pos, r, z) >= 127) hi = mid;
+      else lo = mid + 1;
+    }
+    B.a_hi = (int32_t)lo;
+  }
+  lo = INT32_MIN;
+  hi = -1;
+  if (requant_q(lo, B.m_neg, r, z) > -128) {
+    B.a_lo = INT32_MIN;
+  } else {
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (requant_q(mid, B.m_neg, r, z) <= -128) lo = mid;
+      else hi = mid - 1;
+    }
+    B.a_lo = (int32_t)lo;
+  }
+  return B;
+}
+
 struct LayerImage {
   std::vector<int8_t> packed;
   std::vector<int32_t> bias, zc;
@@ -1759,8 +1807,11 @@ int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out) 
     D.Wr = (const int8_t*)put(L.W.data(), L.W.size());
     D.bias = (const int32_t*)put(im[i].bias.data(), im[i].bias.size() * 4);
     D.zc = im[i].zc.empty() ? nullptr : (const int32_t*)put(im[i].zc.data(), im[i].zc.size() * 4);
-    D.m_pos = L.m_pos;
-    D.m_neg = L.m_neg;
+    const RqBounds rq = requant_bounds(L.m_pos, L.m_neg, L.r, L.z_out);
+    D.m_pos = rq.m_pos;
+    D.m_neg = rq.m_neg;
+    D.a_lo = rq.a_lo;
+    D.a_hi = rq.a_hi;
     D.r = L.r;
     D.z_out = L.z_out;
     D.taps = L.taps;
@@ -1960,6 +2011,17 @@ int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n) {
 int lpcc_softmax_table(int32_t* out) {
   if (!out) return LPCC_E_INVAL;
   softmax_table(out);
+  return LPCC_OK;
+}
+
+// Accumulator bounds of one requantisation as the kernels use them (host only).
+int lpcc_requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z_out, int32_t* out) {
+  if (!out || m_pos < 0 || m_neg < 0 || r < 0 || r > 62 || z_out < -128 || z_out > 127) return LPCC_E_INVAL;
+  const RqBounds B = requant_bounds(m_pos, m_neg, r, z_out);
+  out[0] = B.m_pos;
+  out[1] = B.m_neg;
+  out[2] = B.a_lo;
+  out[3] = B.a_hi;
   return LPCC_OK;
 }
 

@@ -78,6 +78,7 @@ def lib():
         L.lpcc_timing_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64)]
         L.lpcc_softmax_table.argtypes = [vp]
+        L.lpcc_requant_bounds.argtypes = [i32, i32, i32, i32, vp]
         L.lpcc_ctx_set_tiling.argtypes = [vp, i32]
         L.lpcc_ctx_set_graphs.argtypes = [vp, i32]
         L.lpcc_ctx_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -119,6 +120,14 @@ def softmax_table() -> np.ndarray:
     out = np.zeros(256, np.int32)
     _check(lib().lpcc_softmax_table(out.ctypes.data))
     return out
+
+
+def requant_bounds(m_pos: int, m_neg: int, r: int, z_out: int):
+    """(m_pos, m_neg, a_lo, a_hi) of a requantisation as the kernels use it
+    (host computation)."""
+    out = np.zeros(4, np.int32)
+    _check(lib().lpcc_requant_bounds(m_pos, m_neg, r, z_out, out.ctypes.data))
+    return tuple(int(v) for v in out)
 
 
 def _check(st, ctx=None):
