@@ -348,11 +348,12 @@ def _bench_128beam(lpcc, synth, torch, dev, ctx):
 
 
 # HBM bytes per k_predict launch (read + write, scaled FETCH_SIZE / WRITE_SIZE
-# counters of profiles/64beam_D14_C32_plain_counters.md averaged over the 840
-# decode-mode and 60 encode-mode launches of that run) and the kernel source
-# they were taken on; a changed kernel source reports traffic = null
-PROFILED_MODEL_HIP = "a7605df00fa49228"
-PREDICT_BYTES_PER_LAUNCH = (840 * (1042.3 + 11230.6) + 60 * (12870.3 + 1364.8)) / 900 * 1024
+# counters of profiles/64beam_D14_C32_plain_counters.md averaged over the 340
+# decode-mode launches of 16 nodes per wave, 612 of 4 nodes per wave and 96
+# encode-mode launches of that run) and the kernel source they were taken on;
+# a changed kernel source reports traffic = null
+PROFILED_MODEL_HIP = "8e152115dca53bf8"
+PREDICT_BYTES_PER_LAUNCH = (340 * (2405.6 + 30761.3) + 612 * (213.2 + 376.0) + 96 * (9191.4 + 966.6)) / 1048 * 1024
 
 
 def _source_hash():
