@@ -148,19 +148,27 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmSeg* __restrict__ segs, 
     src[s] = (rv && tap < TAPS) ? src_row<MODE>(S, row, tap) : -1;
   }
   const GAS v4i* Wp = (const GAS v4i*)L.Wp;
-#pragma unroll
-  for (int s = 0; s < KS; s++) {
+  // software pipeline: the loads of step s + PD - 1 are issued before the
+  // MFMAs of step s; absent neighbours read row 0 and are zeroed afterwards
+  constexpr int PD = 3;
+  v4i abuf[PD], bbuf[PD][NB];
+  auto load_step = [&](int s, v4i& a, v4i (&b)[NB]) {
     const int k0 = 64 * s + 16 * g;
     const int c0 = k0 % CIN;
-    v4i a = v4i{0, 0, 0, 0};
-    if (src[s] >= 0)
-      a = c0 < S.split ? ld16(S.in + (int64_t)src[s] * S.in_stride + c0)
-                       : ld16(S.in2 + (int64_t)src[s] * S.in2_stride + (c0 - S.split));
+    const int64_t ur = src[s] >= 0 ? src[s] : 0;
+    const v4i v = c0 < S.split ? ld16(S.in + ur * S.in_stride + c0) : ld16(S.in2 + ur * S.in2_stride + (c0 - S.split));
+    a = src[s] >= 0 ? v : v4i{0, 0, 0, 0};
 #pragma unroll
-    for (int nb = 0; nb < NB; nb++) {
-      v4i b = Wp[((int64_t)s * NB + nb) * 64 + lane];
-      acc[nb] = mfma16(a, b, acc[nb]);
-    }
+    for (int nb = 0; nb < NB; nb++) b[nb] = Wp[((int64_t)s * NB + nb) * 64 + lane];
+  };
+#pragma unroll
+  for (int p = 0; p < PD - 1; p++)
+    if (p < KS) load_step(p, abuf[p], bbuf[p]);
+#pragma unroll
+  for (int s = 0; s < KS; s++) {
+    if (s + PD - 1 < KS) load_step(s + PD - 1, abuf[(s + PD - 1) % PD], bbuf[(s + PD - 1) % PD]);
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) acc[nb] = mfma16(abuf[s % PD], bbuf[s % PD][nb], acc[nb]);
   }
 
   // stage the tile, then requantise row-contiguous runs
@@ -287,25 +295,37 @@ __global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ seg
   const GAS int8_t* in1 = gp(S.in);
   const GAS int8_t* in2 = gp(S.in2);
   const uint32_t st1 = (uint32_t)S.in_stride, st2 = (uint32_t)S.in2_stride;
-#pragma unroll 2
-  for (int s = 0; s < KS; s++) {
+  // Software pipeline over the k-steps: the gathers and weight fragments of
+  // step s + PD - 1 are issued before the MFMAs of step s, so PD - 1 steps of
+  // loads are in flight behind the math instead of one load latency per
+  // step.  Absent neighbours read row 0 (every launch has one) and are
+  // zeroed after the load, which keeps the gathers free of branches.
+  constexpr int PD = 3;
+  v4i abuf[PD][RB], bbuf[PD][NB];
+  auto load_step = [&](int s, v4i (&a)[RB], v4i (&b)[NB]) {
     const int k0 = 64 * s + 16 * g;
     const int tap = k0 >> LC, c0 = k0 & (CIN - 1);
-    v4i a[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; rb++) {
       const int sr = src_of(rb, tap);
-      a[rb] = v4i{0, 0, 0, 0};
-      if (sr >= 0)
-        a[rb] = c0 < SPLIT ? *(const GAS v4i*)(in1 + ((uint32_t)sr * st1 + (uint32_t)c0))
-                           : *(const GAS v4i*)(in2 + ((uint32_t)sr * st2 + (uint32_t)(c0 - SPLIT)));
+      const uint32_t ur = sr >= 0 ? (uint32_t)sr : 0u;
+      const v4i v = c0 < SPLIT ? *(const GAS v4i*)(in1 + (ur * st1 + (uint32_t)c0))
+                               : *(const GAS v4i*)(in2 + (ur * st2 + (uint32_t)(c0 - SPLIT)));
+      a[rb] = sr >= 0 ? v : v4i{0, 0, 0, 0};
     }
 #pragma unroll
-    for (int nb = 0; nb < NB; nb++) {
-      const v4i b = Wp[((int64_t)s * NB + nb) * 64 + lane];
+    for (int nb = 0; nb < NB; nb++) b[nb] = Wp[((int64_t)s * NB + nb) * 64 + lane];
+  };
 #pragma unroll
-      for (int rb = 0; rb < RB; rb++) acc[rb][nb] = mfma16(a[rb], b, acc[rb][nb]);
-    }
+  for (int p = 0; p < PD - 1; p++)
+    if (p < KS) load_step(p, abuf[p], bbuf[p]);
+#pragma unroll
+  for (int s = 0; s < KS; s++) {
+    if (s + PD - 1 < KS) load_step(s + PD - 1, abuf[(s + PD - 1) % PD], bbuf[(s + PD - 1) % PD]);
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+      for (int rb = 0; rb < RB; rb++) acc[rb][nb] = mfma16(abuf[s % PD][rb], bbuf[s % PD][nb], acc[rb][nb]);
   }
 
   // epilogue, one row block at a time through the wave's LDS stage
