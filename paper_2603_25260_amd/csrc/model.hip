@@ -670,14 +670,29 @@ __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, c
   GemmSeg S;
   LayerDev L;
   const int tile_row0 = pick_seg(segs, tiles, A, S, L);
-  const int cs = __builtin_ctz((unsigned)C);  // C is a power of two
-  for (int e = threadIdx.x; e < 64 * C; e += blockDim.x) {
-    const int row = tile_row0 + (e >> cs), o = e & (C - 1);
-    if (row >= S.rows) continue;
-    const uint32_t code = gp(S.code)[row];
-    int acc = gp(L.bias)[o];
-    for (int b = 0; b < 8; b++)
-      if ((code >> b) & 1u) acc += 127 * (int)gp(L.Wr)[b * C + o];
+  const int cs = __builtin_ctz((unsigned)C);  // C is a power of two dividing 256
+  // a thread keeps one output channel o for every row it writes, so its
+  // weights and bias are loaded once; the codes of all its rows (at most 16)
+  // are loaded together before any is used
+  const int o = threadIdx.x & (C - 1);
+  const int rstep = 256 >> cs, nrow = 64 >> (8 - cs);  // rows per pass, rows per thread
+  int w[8];
+#pragma unroll
+  for (int b = 0; b < 8; b++) w[b] = 127 * (int)gp(L.Wr)[b * C + o];
+  const int bias = gp(L.bias)[o];
+  uint32_t code[16];
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int row = tile_row0 + (threadIdx.x >> cs) + k * rstep;
+    code[k] = (k < nrow && row < S.rows) ? gp(S.code)[row] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < 16; k++) {
+    const int row = tile_row0 + (threadIdx.x >> cs) + k * rstep;
+    if (k >= nrow || row >= S.rows) continue;
+    int acc = bias;
+#pragma unroll
+    for (int b = 0; b < 8; b++) acc += ((code[k] >> b) & 1u) ? w[b] : 0;
     gp(S.out)[(int64_t)row * S.out_stride + o] = (int8_t)requant_l(acc, L);
   }
 }
