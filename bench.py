@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--only-128beam", action="store_true",
                     help="run only the 128-beam batched comparison after the plain loop (profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-schedules", action="store_true",
+                    help="skip the re-densification threshold variants (t = L-3, L-4, L-5)")
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration under a profiler)")
@@ -291,6 +293,8 @@ def main():
                           "plain_mpts_s": round(bpts / tp / 1e6, 3), "speedup": round(tp / tb, 3),
                           "same_lengths": plain_lens == ln and lg == ln}
         res["batched_128beam"] = _bench_128beam(lpcc, synth, torch, dev, ctx)
+    if not args.no_schedules:
+        res["schedules_t"] = _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout)
     if not args.no_serve:
         from paper_2603_25260_amd import serve
         rep_ = serve.run(duration_s=args.serve_seconds, n_sensors=24, rate_hz=10.0, seed=5000, slots=4,
@@ -345,6 +349,35 @@ def _bench_128beam(lpcc, synth, torch, dev, ctx):
             "points": pts, "batched_mpts_s": round(pts / tb / 1e6, 3), "plain_mpts_s": round(pts / tp / 1e6, 3),
             "speedup": round(tp / tb, 3), "batched_ms_per_frame": round(tb / 8 * 1e3, 3),
             "bit_exact_first_frame": exact}
+
+
+def _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout):
+    """Plain encode+decode of the same 64-beam frames under the threshold
+    variants of the paper's ablation: t = L - n_deep with n_deep = 3, 4
+    (the default) and 5 re-densified depths, each its own seeded model."""
+    cfg = synth.CONFIGS["cfg2"]
+    out = []
+    for nd in (3, 4, 5):
+        m = lpcc.Model(synth.make_weights(cfg.weight_seed, cfg.C, cfg.scan.D, nd), 0)
+        lens = []
+        for k in range(len(frames)):  # warm-up (and the first call's tile tuning)
+            n = lpcc.encode_frame(ctx, m, dxyz[k], cl, out=dbs)
+            lpcc.decode_frame(ctx, m, dbs, length=n, out=dout)
+            lens.append(n)
+        reps = 2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for k in range(len(frames)):
+                n = lpcc.encode_frame(ctx, m, dxyz[k], cl, out=dbs)
+                lpcc.decode_frame(ctx, m, dbs, length=n, out=dout)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        pts = sum(len(f) for f in frames)
+        out.append({"n_deep": nd, "t": f"L-{nd}", "k0": cfg.scan.D - nd - 1,
+                    "mpts_s": round(pts / wall / 1e6, 3), "ms_per_frame": round(wall / len(frames) * 1e3, 3),
+                    "bytes_per_point": round(sum(lens) / pts, 3)})
+    return out
 
 
 # HBM bytes per k_predict launch (read + write, scaled FETCH_SIZE / WRITE_SIZE

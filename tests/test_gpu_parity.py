@@ -130,6 +130,21 @@ def test_config2_full_frame_bytes(L, ctx):
     assert np.array_equal(dec, sorted_unique(xyz, cfg.scan.D))
 
 
+@pytest.mark.parametrize("nd", [3, 5])
+def test_threshold_variants_64beam_scene(L, ctx, nd):
+    """The re-densification threshold of the paper's ablation (t = L - 3 and
+    L - 5 beside the default L - 4) on a 64-beam scene, 14-level octree,
+    C = 32: every fifth point of the first frame, bytes equal the oracle's."""
+    cfg = synth.CONFIGS["cfg2"]
+    blob, m = model(L, cfg.weight_seed, cfg.C, cfg.scan.D, nd)
+    xyz = np.ascontiguousarray(synth.make_scan(cfg.scan, cfg.seeds[0])[::5])
+    _note(f"cfg2 n_deep={nd}", len(xyz))
+    want = O.encode(blob, xyz, 8)
+    got = L.encode_frame(ctx, m, xyz, 8)
+    assert got == want
+    assert np.array_equal(L.decode_frame(ctx, m, got), sorted_unique(xyz, cfg.scan.D))
+
+
 def test_device_resident_buffers(L, ctx):
     cfg = synth.CONFIGS["cfg1"]
     blob, m = model(L, cfg.weight_seed, cfg.C, cfg.scan.D, cfg.n_deep)
