@@ -430,10 +430,33 @@ static void logits_to_cdf(const int8_t *l, int32_t *cdf)
     for (int i = 0; i < NSYM; i++) cdf[i + 1] = cdf[i] + (int32_t)f[i];
 }
 
+/* Base geometry (Sec. S3.1, last paragraph of the network details: the     */
+/* levels that are not modelled are coded directly from the frequencies of  */
+/* their symbols).  For a depth d < B the counts n_s of its occupancy codes */
+/* give the frequencies by the same rule as the softmax above, with the     */
+/* counts in place of the exponentials:                                     */
+/*   N = sum n_s, f_s = 1 + floor(n_s * 65281 / N), the remainder goes to   */
+/*   the lowest index holding max n.  Every f_s >= 1, total exactly 2^16.   */
+static void counts_to_cdf(const uint32_t *n, int32_t *cdf)
+{
+    int64_t N = 0;
+    int arg = 0;
+    for (int i = 0; i < NSYM; i++) {
+        N += n[i];
+        if (n[i] > n[arg]) arg = i;
+    }
+    int64_t f[NSYM], tot = 0;
+    for (int i = 0; i < NSYM; i++) { f[i] = 1 + ((int64_t)n[i] * 65281) / (N > 0 ? N : 1); tot += f[i]; }
+    f[arg] += 65536 - tot;
+    cdf[0] = 0;
+    for (int i = 0; i < NSYM; i++) cdf[i + 1] = cdf[i] + (int32_t)f[i];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Model: features F_d for coded depth d (Sec. 3.1-3.2, Eq. 4-11).          */
-/*   d = 0        : F_0 = 0 (the root has no coarser context)               */
-/*   1 <= d <= k0 : S = ResBlock(F_{d-1}) on V_{d-1};                       */
+/*   d = B        : F_B = 0 (the first modelled depth has no coarser        */
+/*                  context; B = 0 models every depth from the root)        */
+/*   B < d <= k0  : S = ResBlock(F_{d-1}) on V_{d-1};                       */
 /*                  F_d = Prune(Up([S | bits(X_{d-1})]), X_{d-1})           */
 /*   d > k0       : G = Down(X_{d-1}) at depth k0;                          */
 /*                  H = ResBlock([F_k0 | G]) on V_k0;                       */
@@ -470,7 +493,7 @@ done:
 
 /* F_d into *F (malloc'ed N_d x C).  Needs V_0..V_d, X_0..X_{d-1},          */
 /* F_{d-1} (shallow) and F_k0 (deep): only already-coded data (Sec. 3.1).   */
-static int features(const model_t *M, const octree_t *T, int d, const int8_t *F_prev,
+static int features(const model_t *M, const octree_t *T, int d, int B, const int8_t *F_prev,
                     const int8_t *F_k0, int8_t **F)
 {
     int C = M->C, k0 = M->k0;
@@ -478,7 +501,7 @@ static int features(const model_t *M, const octree_t *T, int d, const int8_t *F_
     *F = NULL;
     int8_t *out = (int8_t *)calloc((size_t)(Nd > 0 ? Nd : 1) * C, 1);
     if (!out) return ORC_E_NOMEM;
-    if (d == 0) { *F = out; return ORC_OK; }
+    if (d == B) { *F = out; return ORC_OK; }
     const layer_t *L = &M->L[M->first[d]];
     int st = ORC_OK;
     if (d <= k0) {
@@ -632,9 +655,12 @@ static int rc_decode(rc_dec_t *dd, const int32_t *cdf)
 
 /* ------------------------------------------------------------------------ */
 /* Bitstream (little-endian):                                               */
-/*   u32 'LPC1', u8 version=1, u8 D, u8 n_deep, u8 c, u32 blob_id,          */
-/*   u32 N_D, u32 N_d (d = 0..D-1), u16 chunk length for each chunk         */
-/*   (depth ascending, chunk ascending), then the chunk payloads.           */
+/*   u32 'LPC1', u8 version (1, or 2 with base geometry), u8 D, u8 n_deep,  */
+/*   u8 c, u32 blob_id, u32 N_D, u32 N_d (d = 0..D-1);                      */
+/*   version 2 only: u8 B, then for d = 0..B-1 u8 m and m pairs             */
+/*   (u8 code, u32 count), codes ascending, counts >= 1 summing to N_d;     */
+/*   u16 chunk length for each chunk (depth ascending, chunk ascending),    */
+/*   then the chunk payloads.                                               */
 /* Chunk k of depth d codes nodes [k 2^c, min((k+1) 2^c, N_d)).             */
 /* ------------------------------------------------------------------------ */
 static void wr32(uint8_t *p, uint32_t v) { p[0] = v & 0xFF; p[1] = (v >> 8) & 0xFF; p[2] = (v >> 16) & 0xFF; p[3] = v >> 24; }
@@ -704,6 +730,12 @@ int orc_conv3(const int8_t *x, const int32_t *nbr, int64_t rows, int cin, int co
     return conv3(&L, x, nbr, rows, y);
 }
 
+int orc_counts_to_cdf(const uint32_t *counts, int32_t *cdf)
+{
+    counts_to_cdf(counts, cdf);
+    return ORC_OK;
+}
+
 int orc_logits_to_cdf(const int8_t *logits, int64_t n, int32_t *cdf)
 {
     for (int64_t i = 0; i < n; i++) logits_to_cdf(logits + i * NSYM, cdf + i * 256);
@@ -758,7 +790,7 @@ static int run_depth(const model_t *M, const octree_t *T, int level, int what, v
     for (int d = 0; d <= level && st == ORC_OK; d++) {
         /* deep depths read only F_k0; shallow ones need the chain */
         if (d > M->k0 && d < level) continue;
-        st = features(M, T, d, Fprev, Fk0, &F);
+        st = features(M, T, d, 0, Fprev, Fk0, &F);
         if (st != ORC_OK) break;
         if (d == M->k0) {
             free(Fk0);
@@ -816,20 +848,32 @@ int orc_level_probs(const void *blob, size_t blob_len, const int32_t *xyz, int64
     return orc_level_output(blob, blob_len, xyz, n, level, 0, cdf_out, cap, n_nodes);
 }
 
-int orc_encode(const void *blob, size_t blob_len, const int32_t *xyz, int64_t n, int c, uint8_t *out,
-               size_t cap, size_t *out_len)
+/* Encode with the depths d < B coded from their own symbol counts and the  */
+/* model applied from depth B on (B = 0: every depth modelled, version 1).  */
+int orc_encode_base(const void *blob, size_t blob_len, const int32_t *xyz, int64_t n, int c, int B,
+                    uint8_t *out, size_t cap, size_t *out_len)
 {
     model_t M;
     int st = model_parse((const uint8_t *)blob, blob_len, &M);
     if (st != ORC_OK) return st;
-    if (n < 0 || c < 4 || c > 14) { model_free(&M); return ORC_E_INVAL; }
+    if (n < 0 || c < 4 || c > 14 || B < 0 || B > M.k0) { model_free(&M); return ORC_E_INVAL; }
     int D = M.D;
     octree_t T;
     st = octree_build(xyz, n, D, &T);
     if (st != ORC_OK) { octree_free(&T); model_free(&M); return st; }
     int64_t nch = 0;
     for (int d = 0; d < D; d++) nch += nchunks(T.N[d], c);
-    size_t hdr = 16 + 4 * (size_t)D + 2 * (size_t)nch;
+    /* symbol counts of the base depths */
+    uint32_t (*cnt)[NSYM] = (uint32_t (*)[NSYM])calloc((size_t)(B > 0 ? B : 1), sizeof(uint32_t[NSYM]));
+    size_t tables = 0;
+    if (!cnt) st = ORC_E_NOMEM;
+    for (int d = 0; d < B && st == ORC_OK; d++) {
+        for (int64_t i = 0; i < T.N[d]; i++) cnt[d][T.code[d][i] - 1]++;
+        tables += 1;
+        for (int s2 = 0; s2 < NSYM; s2++) tables += cnt[d][s2] ? 5 : 0;
+    }
+    size_t pre = 16 + 4 * (size_t)D + (B > 0 ? 1 + tables : 0);
+    size_t hdr = pre + 2 * (size_t)nch;
     /* the payload is built in a scratch buffer; worst case 2 bytes/symbol + 5/chunk */
     size_t worst = 0;
     for (int d = 0; d < D; d++) worst += 2 * (size_t)T.N[d];
@@ -844,17 +888,21 @@ int orc_encode(const void *blob, size_t blob_len, const int32_t *xyz, int64_t n,
     for (int d = 0; d < D && st == ORC_OK; d++) {
         int64_t N = T.N[d];
         int8_t *F = NULL, *lg = NULL;
-        st = features(&M, &T, d, Fprev, Fk0, &F);
-        if (st != ORC_OK) break;
-        lg = (int8_t *)malloc((size_t)(N > 0 ? N : 1) * NSYM);
-        if (!lg) { free(F); st = ORC_E_NOMEM; break; }
-        st = predict_logits(&M, d, F, N, lg);
+        if (d < B) {
+            counts_to_cdf(cnt[d], cdf);
+        } else {
+            st = features(&M, &T, d, B, Fprev, Fk0, &F);
+            if (st != ORC_OK) break;
+            lg = (int8_t *)malloc((size_t)(N > 0 ? N : 1) * NSYM);
+            if (!lg) { free(F); st = ORC_E_NOMEM; break; }
+            st = predict_logits(&M, d, F, N, lg);
+        }
         for (int64_t k = 0; k < nchunks(N, c) && st == ORC_OK; k++) {
             int64_t a = k << c, b = a + ((int64_t)1 << c) < N ? a + ((int64_t)1 << c) : N;
             rc_enc_t e;
             rc_enc_init(&e, pay + plen, worst - plen);
             for (int64_t i = a; i < b; i++) {
-                logits_to_cdf(lg + i * NSYM, cdf);
+                if (d >= B) logits_to_cdf(lg + i * NSYM, cdf);
                 int s = T.code[d][i] - 1;
                 rc_encode(&e, (uint32_t)cdf[s], (uint32_t)(cdf[s + 1] - cdf[s]));
             }
@@ -864,7 +912,7 @@ int orc_encode(const void *blob, size_t blob_len, const int32_t *xyz, int64_t n,
             plen += e.len;
         }
         free(lg);
-        if (d <= M.k0) { free(Fprev); Fprev = F; if (d == M.k0) { free(Fk0); Fk0 = (int8_t *)malloc((size_t)(N > 0 ? N : 1) * M.C); if (Fk0) memcpy(Fk0, F, (size_t)N * M.C); else st = ORC_E_NOMEM; } }
+        if (d >= B && d <= M.k0) { free(Fprev); Fprev = F; if (d == M.k0) { free(Fk0); Fk0 = (int8_t *)malloc((size_t)(N > 0 ? N : 1) * M.C); if (Fk0) memcpy(Fk0, F, (size_t)N * M.C); else st = ORC_E_NOMEM; } }
         else free(F);
     }
     if (st == ORC_OK) {
@@ -873,26 +921,44 @@ int orc_encode(const void *blob, size_t blob_len, const int32_t *xyz, int64_t n,
     }
     if (st == ORC_OK) {
         out[0] = 'L'; out[1] = 'P'; out[2] = 'C'; out[3] = '1';
-        out[4] = 1; out[5] = (uint8_t)D; out[6] = (uint8_t)M.n_deep; out[7] = (uint8_t)c;
+        out[4] = B > 0 ? 2 : 1; out[5] = (uint8_t)D; out[6] = (uint8_t)M.n_deep; out[7] = (uint8_t)c;
         wr32(out + 8, M.blob_id);
         wr32(out + 12, (uint32_t)T.N[D]);
         for (int d = 0; d < D; d++) wr32(out + 16 + 4 * d, (uint32_t)T.N[d]);
+        if (B > 0) {
+            size_t o = 16 + 4 * (size_t)D;
+            out[o++] = (uint8_t)B;
+            for (int d = 0; d < B; d++) {
+                int m = 0;
+                for (int s2 = 0; s2 < NSYM; s2++) m += cnt[d][s2] ? 1 : 0;
+                out[o++] = (uint8_t)m;
+                for (int s2 = 0; s2 < NSYM; s2++)
+                    if (cnt[d][s2]) { out[o] = (uint8_t)(s2 + 1); wr32(out + o + 1, cnt[d][s2]); o += 5; }
+            }
+        }
         for (int64_t k = 0; k < nch; k++) {
-            out[16 + 4 * D + 2 * k] = lens[k] & 0xFF;
-            out[16 + 4 * D + 2 * k + 1] = lens[k] >> 8;
+            out[pre + 2 * k] = lens[k] & 0xFF;
+            out[pre + 2 * k + 1] = lens[k] >> 8;
         }
         memcpy(out + hdr, pay, plen);
     }
-    free(Fprev); free(Fk0); free(pay); free(lens); free(cdf);
+    free(Fprev); free(Fk0); free(pay); free(lens); free(cdf); free(cnt);
     octree_free(&T);
     model_free(&M);
     return st;
 }
 
+int orc_encode(const void *blob, size_t blob_len, const int32_t *xyz, int64_t n, int c, uint8_t *out,
+               size_t cap, size_t *out_len)
+{
+    return orc_encode_base(blob, blob_len, xyz, n, c, 0, out, cap, out_len);
+}
+
 int orc_peek_header(const uint8_t *bs, size_t len, int *D, int64_t *n_points)
 {
     if (!bs || len < 16) return ORC_E_CORRUPT;
-    if (bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' || bs[4] != 1) return ORC_E_CORRUPT;
+    if (bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' || (bs[4] != 1 && bs[4] != 2))
+        return ORC_E_CORRUPT;
     *D = bs[5];
     *n_points = rd32(bs + 12);
     return ORC_OK;
@@ -907,7 +973,8 @@ int orc_decode(const void *blob, size_t blob_len, const uint8_t *bs, size_t len,
     int st = model_parse((const uint8_t *)blob, blob_len, &M);
     if (st != ORC_OK) return st;
     int D = M.D;
-    if (!bs || len < 16 || bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' || bs[4] != 1) {
+    if (!bs || len < 16 || bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' ||
+        (bs[4] != 1 && bs[4] != 2)) {
         model_free(&M); return ORC_E_CORRUPT;
     }
     if (bs[5] != D || bs[6] != M.n_deep || rd32(bs + 8) != M.blob_id) { model_free(&M); return ORC_E_MODEL; }
@@ -926,14 +993,41 @@ int orc_decode(const void *blob, size_t blob_len, const uint8_t *bs, size_t len,
         if (Nh[d + 1] < Nh[d] || Nh[d + 1] > 8 * Nh[d]) { model_free(&M); return ORC_E_CORRUPT; }
     int64_t nch = 0;
     for (int d = 0; d < D; d++) nch += nchunks(Nh[d], c);
-    size_t hdr = 16 + 4 * (size_t)D + 2 * (size_t)nch;
-    if (len < hdr) { model_free(&M); return ORC_E_CORRUPT; }
+    /* version 2: base depth and the symbol counts of every base depth */
+    int B = 0;
+    size_t pre = 16 + 4 * (size_t)D;
+    uint32_t (*cnt)[NSYM] = NULL;
+    if (bs[4] == 2) {
+        if (len < pre + 1) { model_free(&M); return ORC_E_CORRUPT; }
+        B = bs[pre++];
+        if (B < 1 || B > M.k0) { model_free(&M); return ORC_E_CORRUPT; }
+        cnt = (uint32_t (*)[NSYM])calloc((size_t)B, sizeof(uint32_t[NSYM]));
+        if (!cnt) { model_free(&M); return ORC_E_NOMEM; }
+        for (int d = 0; d < B && st == ORC_OK; d++) {
+            if (len < pre + 1) { st = ORC_E_CORRUPT; break; }
+            int m = bs[pre++], last = 0;
+            int64_t sum = 0;
+            if (len < pre + 5 * (size_t)m) { st = ORC_E_CORRUPT; break; }
+            for (int k = 0; k < m; k++, pre += 5) {
+                int code = bs[pre];
+                uint32_t v = rd32(bs + pre + 1);
+                if (code <= last || v == 0) { st = ORC_E_CORRUPT; break; }
+                cnt[d][code - 1] = v;
+                sum += v;
+                last = code;
+            }
+            if (st == ORC_OK && sum != Nh[d]) st = ORC_E_CORRUPT;
+        }
+        if (st != ORC_OK) { free(cnt); model_free(&M); return st; }
+    }
+    size_t hdr = pre + 2 * (size_t)nch;
+    if (len < hdr) { free(cnt); model_free(&M); return ORC_E_CORRUPT; }
     size_t total = 0;
-    for (int64_t k = 0; k < nch; k++) total += (size_t)bs[16 + 4 * D + 2 * k] | ((size_t)bs[16 + 4 * D + 2 * k + 1] << 8);
-    if (hdr + total != len) { model_free(&M); return ORC_E_CORRUPT; }
+    for (int64_t k = 0; k < nch; k++) total += (size_t)bs[pre + 2 * k] | ((size_t)bs[pre + 2 * k + 1] << 8);
+    if (hdr + total != len) { free(cnt); model_free(&M); return ORC_E_CORRUPT; }
     *n_out = NDh;
-    if (NDh > cap) { model_free(&M); return ORC_E_CAPACITY; }
-    if (NDh == 0) { model_free(&M); return ORC_OK; }
+    if (NDh > cap) { free(cnt); model_free(&M); return ORC_E_CAPACITY; }
+    if (NDh == 0) { free(cnt); model_free(&M); return ORC_OK; }
 
     T.N[0] = 1;
     T.key[0] = (uint64_t *)calloc(1, sizeof(uint64_t));
@@ -945,19 +1039,24 @@ int orc_decode(const void *blob, size_t blob_len, const uint8_t *bs, size_t len,
     for (int d = 0; d < D && st == ORC_OK; d++) {
         int64_t N = T.N[d];
         int8_t *F = NULL, *lg = NULL;
-        st = features(&M, &T, d, Fprev, Fk0, &F);
-        if (st != ORC_OK) break;
-        lg = (int8_t *)malloc((size_t)(N > 0 ? N : 1) * NSYM);
         T.code[d] = (uint8_t *)malloc((size_t)(N > 0 ? N : 1));
-        if (!lg || !T.code[d]) { free(F); free(lg); st = ORC_E_NOMEM; break; }
-        st = predict_logits(&M, d, F, N, lg);
+        if (!T.code[d]) { st = ORC_E_NOMEM; break; }
+        if (d < B) {
+            counts_to_cdf(cnt[d], cdf);
+        } else {
+            st = features(&M, &T, d, B, Fprev, Fk0, &F);
+            if (st != ORC_OK) break;
+            lg = (int8_t *)malloc((size_t)(N > 0 ? N : 1) * NSYM);
+            if (!lg) { free(F); st = ORC_E_NOMEM; break; }
+            st = predict_logits(&M, d, F, N, lg);
+        }
         for (int64_t k = 0; k < nchunks(N, c) && st == ORC_OK; k++, ci++) {
-            size_t cl = (size_t)bs[16 + 4 * D + 2 * ci] | ((size_t)bs[16 + 4 * D + 2 * ci + 1] << 8);
+            size_t cl = (size_t)bs[pre + 2 * ci] | ((size_t)bs[pre + 2 * ci + 1] << 8);
             rc_dec_t dd;
             rc_dec_init(&dd, bs + pos, cl);
             int64_t a = k << c, b = a + ((int64_t)1 << c) < N ? a + ((int64_t)1 << c) : N;
             for (int64_t i = a; i < b; i++) {
-                logits_to_cdf(lg + i * NSYM, cdf);
+                if (d >= B) logits_to_cdf(lg + i * NSYM, cdf);
                 int s = rc_decode(&dd, cdf);
                 if (s < 0) { st = ORC_E_CORRUPT; break; }
                 T.code[d][i] = (uint8_t)(s + 1);
@@ -978,7 +1077,9 @@ int orc_decode(const void *blob, size_t blob_len, const uint8_t *bs, size_t len,
             for (int o = 0; o < 8; o++)
                 if ((T.code[d][p] >> o) & 1u) T.key[d + 1][r++] = (T.key[d][p] << 3) | (uint64_t)o;
         T.N[d + 1] = Nc;
-        if (d <= M.k0) {
+        if (d < B) {
+            /* base depth: no features */
+        } else if (d <= M.k0) {
             free(Fprev); Fprev = F;
             if (d == M.k0) {
                 free(Fk0);
@@ -996,7 +1097,7 @@ int orc_decode(const void *blob, size_t blob_len, const uint8_t *bs, size_t len,
             xyz_out[3 * i] = (int32_t)x; xyz_out[3 * i + 1] = (int32_t)y; xyz_out[3 * i + 2] = (int32_t)z;
         }
     }
-    free(Fprev); free(Fk0); free(cdf);
+    free(Fprev); free(Fk0); free(cdf); free(cnt);
     octree_free(&T);
     model_free(&M);
     return st;

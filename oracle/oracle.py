@@ -186,19 +186,30 @@ def level_features(blob: bytes, xyz, level: int) -> np.ndarray:
     return _level_output(blob, xyz, level, 2)
 
 
-def encode(blob: bytes, xyz, chunk_log2: int = 10) -> bytes:
+def encode(blob: bytes, xyz, chunk_log2: int = 10, base: int = 0) -> bytes:
+    """Bitstream of one frame; the depths below ``base`` are coded from their
+    own symbol counts (base = 0: every depth through the model)."""
     xyz = _xyz(xyz)
     b = np.frombuffer(blob, np.uint8)
     L = lib()
     n = ctypes.c_size_t(0)
-    st = L.orc_encode(_p(b), ctypes.c_size_t(len(blob)), _p(xyz), ctypes.c_int64(len(xyz)),
-                      ctypes.c_int(chunk_log2), None, ctypes.c_size_t(0), ctypes.byref(n))
+    st = L.orc_encode_base(_p(b), ctypes.c_size_t(len(blob)), _p(xyz), ctypes.c_int64(len(xyz)),
+                           ctypes.c_int(chunk_log2), ctypes.c_int(base), None, ctypes.c_size_t(0), ctypes.byref(n))
     if st not in (OK, E_CAPACITY):
         raise OracleError(st)
     out = np.zeros(max(1, n.value), np.uint8)
-    _chk(L.orc_encode(_p(b), ctypes.c_size_t(len(blob)), _p(xyz), ctypes.c_int64(len(xyz)),
-                      ctypes.c_int(chunk_log2), _p(out), ctypes.c_size_t(n.value), ctypes.byref(n)))
+    _chk(L.orc_encode_base(_p(b), ctypes.c_size_t(len(blob)), _p(xyz), ctypes.c_int64(len(xyz)),
+                           ctypes.c_int(chunk_log2), ctypes.c_int(base), _p(out), ctypes.c_size_t(n.value),
+                           ctypes.byref(n)))
     return out[:n.value].tobytes()
+
+
+def counts_to_cdf(counts) -> np.ndarray:
+    """CDF (int32 [256]) of a base depth from the counts of its 255 codes."""
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint32).reshape(255))
+    out = np.zeros(256, np.int32)
+    _chk(lib().orc_counts_to_cdf(_p(c), _p(out)))
+    return out
 
 
 def peek_header(bs: bytes):
