@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--only-128beam", action="store_true",
                     help="run only the 128-beam batched comparison after the plain loop (profiling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-base", action="store_true", help="skip the base-geometry lines")
     ap.add_argument("--no-schedules", action="store_true",
                     help="skip the re-densification threshold variants (t = L-3, L-4, L-5)")
     ap.add_argument("--frames", type=int, default=8)
@@ -295,6 +296,8 @@ def main():
         res["batched_128beam"] = _bench_128beam(lpcc, synth, torch, dev, ctx)
     if not args.no_schedules:
         res["schedules_t"] = _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout)
+    if not args.no_base:
+        res["base_geometry"] = _bench_base(lpcc, torch, model, frames, dxyz, cl, dbs, dout, D - cfg.n_deep - 1)
     if not args.no_serve:
         from paper_2603_25260_amd import serve
         rep_ = serve.run(duration_s=args.serve_seconds, n_sensors=24, rate_hz=10.0, seed=5000, slots=4,
@@ -377,6 +380,35 @@ def _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout):
         out.append({"n_deep": nd, "t": f"L-{nd}", "k0": cfg.scan.D - nd - 1,
                     "mpts_s": round(pts / wall / 1e6, 3), "ms_per_frame": round(wall / len(frames) * 1e3, 3),
                     "bytes_per_point": round(sum(lens) / pts, 3)})
+    return out
+
+
+def _bench_base(lpcc, torch, model, frames, dxyz, cl, dbs, dout, k0):
+    """Plain encode+decode of the same 64-beam frames with the depths below B
+    coded from their own code counts (the model from depth B on), for a few
+    B up to the dense fusion depth k0; B = 0 is the headline path."""
+    out = []
+    for B in (0, 3, 6, k0):
+        bctx = lpcc.Context(0, torch.cuda.current_stream().cuda_stream)
+        bctx.set_base_depth(B)
+        lens = []
+        for k in range(len(frames)):  # warm-up and tile tuning
+            n = lpcc.encode_frame(bctx, model, dxyz[k], cl, out=dbs)
+            lpcc.decode_frame(bctx, model, dbs, length=n, out=dout)
+            lens.append(n)
+        reps = 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for k in range(len(frames)):
+                n = lpcc.encode_frame(bctx, model, dxyz[k], cl, out=dbs)
+                lpcc.decode_frame(bctx, model, dbs, length=n, out=dout)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        pts = sum(len(f) for f in frames)
+        out.append({"B": B, "mpts_s": round(pts / wall / 1e6, 3), "ms_per_frame": round(wall / len(frames) * 1e3, 3),
+                    "bytes_per_point": round(sum(lens) / pts, 4)})
+        bctx.close()
     return out
 
 

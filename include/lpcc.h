@@ -228,6 +228,24 @@ int lpcc_ctx_graph_stats(lpcc_ctx* c, int64_t* instantiated, int64_t* updated);
 int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n);
 
 /*
+ * Base geometry (the paper codes the geometry of the levels it does not
+ * model directly from the frequencies of their symbols, Sec. S3.1).  With
+ * base depth B > 0 the streams this context encodes code the occupancy codes
+ * of depths 0..B-1 with a static table per depth built from the counts of
+ * that depth's codes (the integer-softmax rule with counts in place of the
+ * exponentials: f_s = 1 + floor(n_s 65281 / N), the rest of 2^16 to the most
+ * frequent code), and the model runs from depth B on, with zero features at
+ * depth B.  Such streams are version 2: after the depth counts they carry
+ * u8 B and, per base depth, u8 m and m pairs (u8 code, u32 count) of the
+ * codes present, ascending.  B = 0 (the default) models every depth and
+ * writes version 1 streams.  Decoding reads B from each stream.
+ * LPCC_E_INVAL for B outside [0, 21); an encode call whose model has its
+ * dense fusion depth k0 = D - n_deep - 1 below B fails with LPCC_E_INVAL.
+ * lpcc_level_probs always evaluates the model from depth 0.
+ */
+int lpcc_ctx_set_base_depth(lpcc_ctx* c, int base);
+
+/*
  * The integer exponent table of the softmax (Eq. 15) as the library builds
  * it: out[i] = round(2^15 e^{-i/16}), i = 0..255, computed on the host with
  * an integer recurrence.  Host memory; needs no device.

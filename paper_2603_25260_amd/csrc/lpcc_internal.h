@@ -238,4 +238,26 @@ hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t
                                 uint32_t* err, hipStream_t s);
 hipError_t launch_keys_to_xyz(const uint64_t* keys, int64_t n, int D, int32_t* xyz, hipStream_t s);
 
+// Base geometry: the depths d < nb are coded from the counts of their own
+// codes.  Nodes of those depths are addressed as one range: node i of depth
+// d is entry start[d] + i; its frame is key >> 3d (the frame tag).
+struct BaseLevels {
+  const uint64_t* key[kMaxD];
+  const uint8_t* code[kMaxD];
+  int64_t start[kMaxD + 1];
+  const uint32_t* count;  // device node count per depth, or null: entries of
+                          // depth d at or beyond count[d] are skipped
+  int32_t nb;             // number of base depths
+  int32_t nf;             // frames
+};
+// hist[(f nb + d) 256 + code] += 1 over every base node (hist cleared first)
+hipError_t launch_base_hist(const BaseLevels& bl, uint32_t* hist, hipStream_t s);
+// encoder: sf[start[d] + i] = {start | freq << 16} of node i's code under the
+// table cdf[(f nb + d) 256 ..] (int32 CDF, cdf[0] = 0, cdf[255] = 65536)
+hipError_t launch_base_sf(const BaseLevels& bl, const int32_t* cdf, uint32_t* sf, hipStream_t s);
+// decoder: the CDF row (u16 [256]) of every node of base depth d, copied from
+// rows16[(f nb + d) 256 ..]
+hipError_t launch_base_rows(const uint64_t* keys, int64_t n, int d, int nb, int nf, const uint16_t* rows16,
+                            uint16_t* cdf16, hipStream_t s);
+
 }  // namespace lpcc

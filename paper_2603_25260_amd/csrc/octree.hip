@@ -466,6 +466,73 @@ hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Base geometry (the levels that are not modelled are coded from the
+// frequencies of their own symbols).  One thread per base node.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int base_depth_of(const BaseLevels& bl, int64_t i) {
+  int d = 0;
+  while (d + 1 < bl.nb && i >= bl.start[d + 1]) d++;
+  return d;
+}
+
+__global__ void k_base_hist(const BaseLevels bl, uint32_t* __restrict__ hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= bl.start[bl.nb]) return;
+  const int d = base_depth_of(bl, i);
+  const int64_t k = i - bl.start[d];
+  if (bl.count != nullptr && k >= (int64_t)gp(bl.count)[d]) return;
+  const int f = (int)(gp(bl.key[d])[k] >> (3 * d));
+  if (f >= bl.nf) return;
+  atomicAdd(&hist[((int64_t)f * bl.nb + d) * 256 + gp(bl.code[d])[k]], 1u);
+}
+
+hipError_t launch_base_hist(const BaseLevels& bl, uint32_t* hist, hipStream_t s) {
+  const int64_t n = bl.start[bl.nb];
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_base_hist, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bl, hist);
+  return hipGetLastError();
+}
+
+__global__ void k_base_sf(const BaseLevels bl, const int32_t* __restrict__ cdf, uint32_t* __restrict__ sf) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= bl.start[bl.nb]) return;
+  const int d = base_depth_of(bl, i);
+  const int64_t k = i - bl.start[d];
+  const int f = min((int)(gp(bl.key[d])[k] >> (3 * d)), bl.nf - 1);
+  const GAS int32_t* row = gp(cdf) + ((int64_t)f * bl.nb + d) * 256;
+  const int sym = max((int)gp(bl.code[d])[k] - 1, 0);
+  const uint32_t lo = (uint32_t)row[sym], hi = (uint32_t)row[sym + 1];
+  gp(sf)[i] = lo | ((hi - lo) << 16);
+}
+
+hipError_t launch_base_sf(const BaseLevels& bl, const int32_t* cdf, uint32_t* sf, hipStream_t s) {
+  const int64_t n = bl.start[bl.nb];
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_base_sf, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, bl, cdf, sf);
+  return hipGetLastError();
+}
+
+// 64 lanes per node, 8 bytes each
+__global__ void k_base_rows(const uint64_t* __restrict__ keys, int64_t n, int d, int nb, int nf,
+                            const uint16_t* __restrict__ rows16, uint16_t* __restrict__ cdf16) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t >> 6;
+  const int l = (int)(t & 63);
+  if (i >= n) return;
+  const int f = min((int)(gp(keys)[i] >> (3 * d)), nf - 1);
+  const GAS uint64_t* src = (const GAS uint64_t*)(rows16 + ((int64_t)f * nb + d) * 256);
+  ((GAS uint64_t*)(cdf16 + i * 256))[l] = src[l];
+}
+
+hipError_t launch_base_rows(const uint64_t* keys, int64_t n, int d, int nb, int nf, const uint16_t* rows16,
+                            uint16_t* cdf16, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_base_rows, dim3((unsigned)((n * 64 + 255) / 256)), dim3(256), 0, s, keys, n, d, nb, nf,
+                     rows16, cdf16);
+  return hipGetLastError();
+}
+
 __global__ void k_keys_to_xyz(const uint64_t* __restrict__ keys, int64_t n, int D, int32_t* __restrict__ xyz) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;

@@ -193,6 +193,28 @@ RqBounds requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z) {
   return B;
 }
 
+// Frequencies of a base depth from the counts n_s of its 255 codes (the
+// integer-softmax rule with the counts in place of the exponentials):
+// f_s = 1 + floor(n_s 65281 / N), N = sum n_s, and what the f_s leave of
+// 2^16 goes to the lowest code of maximum count.  cdf[0] = 0, cdf[255] = 2^16.
+void base_cdf(const uint32_t* n, int32_t* cdf) {
+  int64_t N = 0;
+  int arg = 0;
+  for (int i = 0; i < 255; i++) {
+    N += n[i];
+    if (n[i] > n[arg]) arg = i;
+  }
+  if (N == 0) N = 1;
+  int64_t f[255], tot = 0;
+  for (int i = 0; i < 255; i++) {
+    f[i] = 1 + (int64_t)n[i] * 65281 / N;
+    tot += f[i];
+  }
+  f[arg] += 65536 - tot;
+  cdf[0] = 0;
+  for (int i = 0; i < 255; i++) cdf[i + 1] = cdf[i] + (int32_t)f[i];
+}
+
 struct LayerImage {
   std::vector<int8_t> packed;
   std::vector<int32_t> bias, zc;
@@ -305,6 +327,9 @@ struct lpcc_ctx {
   hipStream_t side = nullptr;
   std::vector<hipEvent_t> sync_ev;
   size_t sync_used = 0;
+  // base depth B of the streams this context encodes: depths below B are
+  // coded from the counts of their own codes, the model runs from depth B
+  int base = 0;
 };
 
 namespace {
@@ -577,11 +602,11 @@ bool need_kmap(const lpcc_model* m, int j) { return j <= m->k0 - 1 || (j == m->k
 // Carve the model buffers for depths in [0, last] (`wanted` selects the
 // predicted depths; shallow features are always built up to min(last, k0)).
 void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, const std::vector<bool>& wanted,
-                 ModelBufs& B) {
+                 ModelBufs& B, int base = 0) {
   const int C = m->C, k0 = m->k0;
   const int shallow_last = std::min(last, k0);
   int64_t tmax = 0;
-  for (int d = 0; d <= shallow_last; d++) {
+  for (int d = base; d <= shallow_last; d++) {
     B.F[d] = A.take<int8_t>((size_t)fr.tot[d] * C);
     tmax = std::max(tmax, fr.tot[d]);
   }
@@ -589,7 +614,7 @@ void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, cons
   B.S = A.take<int8_t>((size_t)tmax * C);
   // all hash-table key arrays first and contiguous, so that one fill clears them
   const int kmax = std::min(last, k0);
-  auto hashed = [&](int j) { return need_kmap(m, j) && !(j >= last && !(j == k0 && last > k0)); };
+  auto hashed = [&](int j) { return j >= base && need_kmap(m, j) && !(j >= last && !(j == k0 && last > k0)); };
   B.hash_lo = nullptr;
   B.hash_words = 0;
   for (int j = 0; j <= kmax; j++) {
@@ -982,7 +1007,8 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
 // Octree of all frames: Morton keys, radix sort, level arrays.  Fills
 // `fr` (after a synchronisation) and the level pointers.
 int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n,
-                 Levels& lv, Frames& fr, std::vector<int>& fstatus, size_t* desc_off) {
+                 Levels& lv, Frames& fr, std::vector<int>& fstatus, size_t* desc_off, int base = 0,
+                 std::vector<uint32_t>* base_hist = nullptr) {
   const int D = m->D;
   hipStream_t st = c->stream;
   int64_t ntot = 0;
@@ -1018,8 +1044,9 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
   int32_t* xyz_stage = nullptr;
   uint64_t *kin = nullptr, *kout = nullptr;
   void* tmp = nullptr;
-  uint32_t *err = nullptr, *hist = nullptr, *totals = nullptr, *foff = nullptr;
+  uint32_t *err = nullptr, *hist = nullptr, *totals = nullptr, *foff = nullptr, *bhist = nullptr;
   char *zero_lo = nullptr, *zero_hi = nullptr;
+  const size_t nbh = (size_t)nf * base * 256;  // code counts of the base depths
   auto carve = [&](Arena& A) {
     if (need_stage) xyz_stage = A.take<int32_t>((size_t)ntot * 3);
     kin = A.take<uint64_t>(ntot);
@@ -1031,6 +1058,7 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
     err = A.take<uint32_t>(nf);
     zero_lo = (char*)err;
     totals = A.take<uint32_t>(D + 1);
+    if (nbh) bhist = A.take<uint32_t>(nbh);
     for (int d = 0; d <= D; d++) lv.code[d] = A.take<uint8_t>(align_up(ub[d], 4) + 4);
     zero_hi = (char*)(lv.code[D] + align_up(ub[D], 4) + 4);
     for (int d = 0; d <= D; d++) {
@@ -1074,16 +1102,39 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
     lo.frame_off = foff;
     HIPC(launch_level_write(kout, ntot, D, tile, hist, lo, st));
     HIPC(launch_sentinels(lo, totals, D, st));
+    if (nbh) {
+      // code counts per (frame, base depth); the node counts are still on
+      // the device, so the range covers the upper bounds and the kernel
+      // skips entries beyond the real count of their depth
+      BaseLevels bl;
+      memset(&bl, 0, sizeof(bl));
+      bl.nb = base;
+      bl.nf = nf;
+      bl.count = totals;
+      for (int d = 0; d < base; d++) {
+        bl.key[d] = lv.key[d];
+        bl.code[d] = lv.code[d];
+        bl.start[d + 1] = bl.start[d] + ub[d];
+      }
+      HIPC(launch_fill_u32(bhist, (int64_t)nbh, 0, st));
+      HIPC(launch_base_hist(bl, bhist, st));
+    }
   }
-  // read back counts, frame offsets and errors
-  const size_t rb = (size_t)(D + 1 + nf * (D + 1) + nf) * 4;
+  // read back counts, frame offsets, errors (and the base depths' code counts)
+  const size_t rb = (size_t)(D + 1 + nf * (D + 1) + nf) * 4 + nbh * 4;
   s = reserve_pinned(c, *desc_off + rb + 256);
   if (s) return s;
   uint32_t* h = (uint32_t*)(c->pinned + c->pinned_cap - align_up(rb, 256));
   HIPC(hipMemcpyAsync(h, totals, (D + 1) * 4, hipMemcpyDeviceToHost, st));
   HIPC(hipMemcpyAsync(h + D + 1, foff, (size_t)nf * (D + 1) * 4, hipMemcpyDeviceToHost, st));
   HIPC(hipMemcpyAsync(h + (D + 1) * (nf + 1), err, (size_t)nf * 4, hipMemcpyDeviceToHost, st));
+  if (nbh && ntot > 0)
+    HIPC(hipMemcpyAsync(h + (D + 1) * (nf + 1) + nf, bhist, nbh * 4, hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
+  if (base_hist) {
+    base_hist->assign(nbh, 0u);
+    if (nbh && ntot > 0) memcpy(base_hist->data(), h + (D + 1) * (nf + 1) + nf, nbh * 4);
+  }
   fr.nf = nf;
   fr.tot.assign(D + 1, 0);
   for (int d = 0; d <= D; d++) fr.tot[d] = h[d];
@@ -1133,7 +1184,15 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   Levels lv;
   Frames fr;
   std::vector<int> fst;
-  int s = build_octree(c, m, nf, xyz, n, lv, fr, fst, &desc_off);
+  // base depth: depths below it are coded from their own code counts
+  const int nb = probe_level >= 0 ? 0 : c->base;
+  if (nb > k0) {
+    c->err = "base depth above the dense fusion depth of the model";
+    for (int g = 0; g < nf; g++) status[g] = LPCC_E_INVAL;
+    return LPCC_E_INVAL;
+  }
+  std::vector<uint32_t> bhist;
+  int s = build_octree(c, m, nf, xyz, n, lv, fr, fst, &desc_off, nb, &bhist);
   if (s) return s;
   for (int f = 0; f < nf; f++)
     if (fst[f] != LPCC_OK) {
@@ -1144,6 +1203,14 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   const int last = probe ? probe_level : D - 1;
   std::vector<bool> wanted(D, !probe);
   if (probe) wanted[probe_level] = true;
+  for (int d = 0; d < nb; d++) wanted[d] = false;
+  // static tables of the base depths: int32 CDF per (frame, depth)
+  std::vector<int32_t> bcdf((size_t)nf * nb * 256, 0);
+  for (int f = 0; f < nf; f++)
+    for (int d = 0; d < nb; d++) {
+      const size_t t = ((size_t)f * nb + d) * 256;
+      base_cdf(bhist.data() + t + 1, bcdf.data() + t);  // counts of codes 1..255
+    }
   if (probe) {
     *n_nodes = fr.tot[probe_level];
     if (fr.tot[probe_level] > cdf_cap) {
@@ -1184,8 +1251,18 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   // bound + the frame's chunk scratch bound
   std::vector<size_t> stage_off(nf, 0);
   size_t stage_bytes = 0;
+  // header bytes of the base tables per frame: B, then per depth m and m pairs
+  std::vector<size_t> tbytes(nf, 0);
+  for (int f = 0; f < nf && nb > 0; f++) {
+    tbytes[f] = 1;
+    for (int d = 0; d < nb; d++) {
+      tbytes[f] += 1;
+      for (int k = 1; k < 256; k++) tbytes[f] += bhist[((size_t)f * nb + d) * 256 + k] ? 5 : 0;
+    }
+  }
   if (!probe) {
     std::vector<size_t> fbytes(nf, 16 + 4 * (size_t)D);
+    for (int f = 0; f < nf; f++) fbytes[f] += tbytes[f];
     for (size_t k = 0; k < chunks.size(); k++) fbytes[chunk_frame[k]] += 2 + align_up(2 * (size_t)chunks[k].count + 16, 16);
     for (int f = 0; f < nf; f++) {
       stage_off[f] = stage_bytes;
@@ -1194,7 +1271,7 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   }
   uint8_t* stage = nullptr;
   auto carve = [&](Arena& A) {
-    carve_model(A, m, fr, last, wanted, B);
+    carve_model(A, m, fr, last, wanted, B, nb);
     if (!probe) {
       sf = A.take<uint32_t>(dbase[D]);
       scratch = A.take<uint8_t>(scratch_bytes);
@@ -1215,18 +1292,35 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
 
   Batch b;
   b.ctx = c;
-  // F_0 = 0
+  // F_B = 0: the first modelled depth has no coarser context
   {
-    int8_t* f0 = B.F[0];
-    const int64_t bytes = fr.tot[0] * C;
+    int8_t* f0 = B.F[nb];
+    const int64_t bytes = fr.tot[nb] * C;
     b.launch("fill", 0, [=](const uint8_t*) { return launch_fill_u32((uint32_t*)f0, (bytes + 3) / 4, 0, st); });
   }
   {
     std::vector<int> js;
-    for (int j = 0; j <= std::min(last, k0); j++)
+    for (int j = nb; j <= std::min(last, k0); j++)
       if (B.kmap[j]) js.push_back(j);
     plan_hash_clear(b, B, st);
     plan_kmaps(b, lv, fr, B, js, st);
+  }
+  // start/freq of every base node from its frame's table
+  if (nb > 0 && dbase[nb] > 0) {
+    BaseLevels bl;
+    memset(&bl, 0, sizeof(bl));
+    bl.nb = nb;
+    bl.nf = nf;
+    for (int d = 0; d < nb; d++) {
+      bl.key[d] = lv.key[d];
+      bl.code[d] = lv.code[d];
+      bl.start[d + 1] = dbase[d + 1];
+    }
+    const size_t to = b.add(bcdf);
+    uint32_t* sf0 = sf;
+    b.launch("base", dbase[nb], [=](const uint8_t* base) {
+      return launch_base_sf(bl, (const int32_t*)(base + to), sf0, st);
+    });
   }
   // Two streams: the re-densification of the deep depths needs only the
   // codes and runs beside the shallow chain; the predictor of the shallow
@@ -1259,7 +1353,7 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   wait(sd, mark(st));  // the side stream starts after the fills
   plan_deep(b, m, lv, fr, B, dset, sd, 1);
   hipEvent_t g_done = mark(sd);
-  for (int d = 1; d <= std::min(last, k0); d++) plan_shallow(b, m, lv, fr, B, d, st);
+  for (int d = nb + 1; d <= std::min(last, k0); d++) plan_shallow(b, m, lv, fr, B, d, st);
   hipEvent_t f_done = mark(st);
   wait(st, g_done);
   plan_deep(b, m, lv, fr, B, dset, st, 2);
@@ -1323,17 +1417,34 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
       size_t nchf = 0;
       for (int d = 0; d < D; d++) nchf += (size_t)nchunks_of(fr.N[f][d], cl);
       std::vector<uint8_t>& H = hdr[f];
-      H.assign(16 + 4 * (size_t)D + 2 * nchf, 0);
+      const size_t pre = 16 + 4 * (size_t)D + tbytes[f];
+      H.assign(pre + 2 * nchf, 0);
       H[0] = 'L'; H[1] = 'P'; H[2] = 'C'; H[3] = '1';
-      H[4] = 1; H[5] = (uint8_t)D; H[6] = (uint8_t)m->n_deep; H[7] = (uint8_t)cl;
+      H[4] = nb > 0 ? 2 : 1; H[5] = (uint8_t)D; H[6] = (uint8_t)m->n_deep; H[7] = (uint8_t)cl;
       auto w32 = [&](size_t o, uint32_t v) { for (int k = 0; k < 4; k++) H[o + k] = (uint8_t)(v >> (8 * k)); };
       w32(8, m->blob_id);
       w32(12, (uint32_t)fr.N[f][D]);
       for (int d = 0; d < D; d++) w32(16 + 4 * d, (uint32_t)fr.N[f][d]);
+      if (nb > 0) {  // B, then per base depth the (code, count) pairs of its present codes
+        size_t o = 16 + 4 * (size_t)D;
+        H[o++] = (uint8_t)nb;
+        for (int d = 0; d < nb; d++) {
+          const uint32_t* cnt = bhist.data() + ((size_t)f * nb + d) * 256;
+          int mcodes = 0;
+          for (int k = 1; k < 256; k++) mcodes += cnt[k] ? 1 : 0;
+          H[o++] = (uint8_t)mcodes;
+          for (int k = 1; k < 256; k++)
+            if (cnt[k]) {
+              H[o] = (uint8_t)k;
+              w32(o + 1, cnt[k]);
+              o += 5;
+            }
+        }
+      }
       size_t pay = 0;
       for (size_t k = 0; k < nchf; k++) {
-        H[16 + 4 * D + 2 * k] = (uint8_t)(hl[ci + k] & 0xFF);
-        H[16 + 4 * D + 2 * k + 1] = (uint8_t)(hl[ci + k] >> 8);
+        H[pre + 2 * k] = (uint8_t)(hl[ci + k] & 0xFF);
+        H[pre + 2 * k + 1] = (uint8_t)(hl[ci + k] >> 8);
         pay += hl[ci + k];
       }
       total[f] = H.size() + pay;
@@ -1394,15 +1505,21 @@ namespace {
 
 struct Header {
   int D = 0, n_deep = 0, cl = 0;
+  int B = 0;                  // base depth (version 2), 0 in version 1
   uint32_t blob = 0;
   std::vector<int64_t> N;     // [D+1]
+  std::vector<uint32_t> cnt;  // [B][255] counts of codes 1..255 per base depth
   std::vector<uint32_t> len;  // chunk lengths
+  size_t pre = 0;             // offset of the chunk lengths
   size_t hdr = 0, total = 0;
+  size_t bound = 0;           // header bytes that certainly suffice (when hdr is not known yet)
 };
 
+// Parse a stream header from the `avail` bytes at h (the stream has `len`).
+// LPCC_E_CAPACITY: more bytes are needed (H.bound, or H.hdr once known).
 int parse_header(const uint8_t* h, size_t avail, size_t len, Header& H, bool need_lengths) {
   if (len < 16 || avail < 16) return LPCC_E_CORRUPT;
-  if (h[0] != 'L' || h[1] != 'P' || h[2] != 'C' || h[3] != '1' || h[4] != 1) return LPCC_E_CORRUPT;
+  if (h[0] != 'L' || h[1] != 'P' || h[2] != 'C' || h[3] != '1' || (h[4] != 1 && h[4] != 2)) return LPCC_E_CORRUPT;
   H.D = h[5];
   H.n_deep = h[6];
   H.cl = h[7];
@@ -1410,6 +1527,8 @@ int parse_header(const uint8_t* h, size_t avail, size_t len, Header& H, bool nee
   if (H.D < 1 || H.D > kMaxD || H.cl < 4 || H.cl > 14) return LPCC_E_CORRUPT;
   const size_t fixed = 16 + 4 * (size_t)H.D;
   if (len < fixed) return LPCC_E_CORRUPT;
+  H.hdr = 0;
+  H.bound = len;
   if (avail < fixed) return LPCC_E_CAPACITY;  // caller fetches more
   H.N.assign(H.D + 1, 0);
   H.N[H.D] = rd32(h + 12);
@@ -1419,14 +1538,45 @@ int parse_header(const uint8_t* h, size_t avail, size_t len, Header& H, bool nee
     if (H.N[d + 1] < H.N[d] || H.N[d + 1] > 8 * H.N[d]) return LPCC_E_CORRUPT;
   int64_t nch = 0;
   for (int d = 0; d < H.D; d++) nch += nchunks_of(H.N[d], H.cl);
-  H.hdr = fixed + 2 * (size_t)nch;
+  size_t pre = fixed;
+  H.B = 0;
+  H.cnt.clear();
+  H.bound = fixed + 1 + (size_t)(H.D - 1) * (1 + 5 * 255) + 2 * (size_t)nch;
+  if (h[4] == 2) {
+    if (len < pre + 1) return LPCC_E_CORRUPT;
+    if (avail < pre + 1) return LPCC_E_CAPACITY;
+    H.B = h[pre++];
+    if (H.B < 1 || H.B > H.D - 1) return LPCC_E_CORRUPT;
+    H.bound = pre + (size_t)H.B * (1 + 5 * 255) + 2 * (size_t)nch;
+    H.cnt.assign((size_t)H.B * 255, 0);
+    for (int d = 0; d < H.B; d++) {
+      if (len < pre + 1) return LPCC_E_CORRUPT;
+      if (avail < pre + 1) return LPCC_E_CAPACITY;
+      const int mc = h[pre++];
+      if (len < pre + 5 * (size_t)mc) return LPCC_E_CORRUPT;
+      if (avail < pre + 5 * (size_t)mc) return LPCC_E_CAPACITY;
+      int last = 0;
+      int64_t sum = 0;
+      for (int k = 0; k < mc; k++, pre += 5) {
+        const int code = h[pre];
+        const uint32_t v = rd32(h + pre + 1);
+        if (code <= last || v == 0) return LPCC_E_CORRUPT;
+        H.cnt[(size_t)d * 255 + code - 1] = v;
+        sum += v;
+        last = code;
+      }
+      if (sum != H.N[d]) return LPCC_E_CORRUPT;
+    }
+  }
+  H.pre = pre;
+  H.hdr = pre + 2 * (size_t)nch;
   if (len < H.hdr) return LPCC_E_CORRUPT;
   if (!need_lengths) return LPCC_OK;
   if (avail < H.hdr) return LPCC_E_CAPACITY;
   H.len.resize(nch);
   size_t tot = 0;
   for (int64_t k = 0; k < nch; k++) {
-    H.len[k] = (uint32_t)h[fixed + 2 * k] | ((uint32_t)h[fixed + 2 * k + 1] << 8);
+    H.len[k] = (uint32_t)h[pre + 2 * k] | ((uint32_t)h[pre + 2 * k + 1] << 8);
     tot += H.len[k];
   }
   H.total = H.hdr + tot;
@@ -1467,15 +1617,19 @@ int read_headers(lpcc_ctx* c, int nf, const uint8_t* const* bs, const size_t* le
     if (dev[f] && got[f]) HIPC(hipMemcpyAsync(c->pinned + off[f], bs[f], got[f], hipMemcpyDeviceToHost, c->stream));
   HIPC(hipStreamSynchronize(c->stream));
   std::vector<int> more;
+  std::vector<size_t> want(nf, 0);
   size_t need2 = 0;
   for (int f = 0; f < nf; f++) {
     if (!dev[f]) continue;
     st[f] = parse_header(c->pinned + off[f], got[f], len[f], H[f], true);
     if (st[f] == LPCC_E_CAPACITY) {  // longer than the prefix: fetch the whole header
       st[f] = parse_header(c->pinned + off[f], got[f], len[f], H[f], false);
-      if (st[f] == LPCC_OK) {
+      if (st[f] == LPCC_OK || st[f] == LPCC_E_CAPACITY) {
+        // the header's length, or (base tables beyond the prefix) a bound
+        want[f] = std::min(len[f], st[f] == LPCC_OK ? H[f].hdr : H[f].bound);
+        st[f] = LPCC_OK;
         more.push_back(f);
-        need2 += align_up(H[f].hdr, 64);
+        need2 += align_up(want[f], 64);
       }
     }
   }
@@ -1486,11 +1640,14 @@ int read_headers(lpcc_ctx* c, int nf, const uint8_t* const* bs, const size_t* le
   size_t o = 0;
   for (int f : more) {
     off[f] = o;
-    HIPC(hipMemcpyAsync(c->pinned + o, bs[f], H[f].hdr, hipMemcpyDeviceToHost, c->stream));
-    o += align_up(H[f].hdr, 64);
+    HIPC(hipMemcpyAsync(c->pinned + o, bs[f], want[f], hipMemcpyDeviceToHost, c->stream));
+    o += align_up(want[f], 64);
   }
   HIPC(hipStreamSynchronize(c->stream));
-  for (int f : more) st[f] = parse_header(c->pinned + off[f], H[f].hdr, len[f], H[f], true);
+  for (int f : more) {
+    st[f] = parse_header(c->pinned + off[f], want[f], len[f], H[f], true);
+    if (st[f] == LPCC_E_CAPACITY) st[f] = LPCC_E_CORRUPT;  // the bound held the whole header
+  }
   return LPCC_OK;
 }
 
@@ -1518,7 +1675,27 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     status[f] = s;
     if (s == LPCC_OK && H[f].N[D] > 0) live.push_back(f);
   }
-  // frames in the batch must share one chunk size; decode others separately
+  // the frames of one call share the base depth; a call whose frames differ
+  // decodes them one at a time
+  const int nb = live.empty() ? 0 : H[live[0]].B;
+  for (int f : live)
+    if (H[f].B != nb) {
+      for (int g : live) {
+        int st1 = LPCC_OK;
+        int64_t n1 = 0;
+        decode_impl(c, m, 1, &bs[g], &len[g], &xyz_out[g], &cap[g], &n1, &st1);
+        status[g] = st1;
+        n_out[g] = n1;
+      }
+      int ret = LPCC_OK;
+      for (int g = 0; g < nf; g++)
+        if (status[g] != LPCC_OK && ret == LPCC_OK) ret = status[g];
+      return ret;
+    }
+  if (nb > k0) {  // a base depth the model cannot continue from
+    for (int f : live) status[f] = LPCC_E_CORRUPT;
+    return LPCC_E_CORRUPT;
+  }
   Frames fr;
   fr.nf = nf;
   fr.tot.assign(D + 1, 0);
@@ -1572,6 +1749,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   for (int d = 0; d < D; d++) maxch = std::max(maxch, dchunks[d].size());
   for (int d = 0; d <= D; d++) maxN = std::max(maxN, fr.tot[d]);
   std::vector<bool> wanted(D, true);
+  for (int d = 0; d < nb; d++) wanted[d] = false;
   std::vector<bool> xdev(nf, false);
   bool any_host_out = false;
   for (int f : live) {
@@ -1589,7 +1767,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     err = A.take<uint32_t>(4);
     csum = A.take<uint32_t>(maxch + 1);
     if (any_host_out) xyz_stage = A.take<int32_t>((size_t)fr.tot[D] * 3);
-    carve_model(A, m, fr, D - 1, wanted, B);
+    carve_model(A, m, fr, D - 1, wanted, B, nb);
   };
   Arena meas;
   carve(meas);
@@ -1624,12 +1802,26 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   Batch b;
   b.ctx = c;
   {
-    int8_t* f0 = B.F[0];
-    const int64_t bytes = fr.tot[0] * C;
+    // F_B = 0: the first modelled depth has no coarser context
+    int8_t* f0 = B.F[nb];
+    const int64_t bytes = fr.tot[nb] * C;
     b.launch("fill", 0, [=](const uint8_t*) { return launch_fill_u32((uint32_t*)f0, (bytes + 3) / 4, 0, st); });
   }
+  size_t brow_off = 0;  // descriptor offset of the base rows [live frame][depth][256]
+  if (nb > 0) {
+    // 16-bit CDF rows of the base depths (entry 255 is not a boundary: 0)
+    std::vector<uint16_t> rows(live.size() * nb * 256, 0);
+    for (size_t i = 0; i < live.size(); i++)
+      for (int d = 0; d < nb; d++) {
+        int32_t cdf[256];
+        base_cdf(H[live[i]].cnt.data() + (size_t)d * 255, cdf);
+        uint16_t* r = rows.data() + (i * nb + d) * 256;
+        for (int k = 0; k < 255; k++) r[k] = (uint16_t)cdf[k];
+      }
+    brow_off = b.add(rows);
+  }
   plan_hash_clear(b, B, st);
-  if (B.kmap[0]) plan_kmaps(b, lv, fr, B, {0}, st);
+  if (nb == 0 && B.kmap[0]) plan_kmaps(b, lv, fr, B, {0}, st);
   // Depth d's chain is predictor -> coder -> expansion -> upsampling of
   // depth d+1.  The ResBlock of depth d+1 needs only F_d and the neighbour
   // table of depth d, and the neighbour table of depth d+1 only the
@@ -1669,19 +1861,31 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       plan_deep(b, m, lv, fr, B, {d}, st);
     }
     hipEvent_t resblock = nullptr;
-    if (t <= k0) {
+    const bool modelled = d >= nb;  // base depths carry no features
+    if (t <= k0 && modelled) {
       join(st, sd);  // F_d
       plan_shallow_convs(b, m, fr, B, t, sd);
       resblock = mark(sd);
     }
-    PredSeg p;
-    memset(&p, 0, sizeof(p));
-    p.F = features_of(m, B, d);
-    p.fc1 = dlayer(m, d, m->first[d + 1] - m->first[d] - 2);
-    p.fc2 = dlayer(m, d, m->first[d + 1] - m->first[d] - 1);
-    p.rows = (int)fr.tot[d];
-    p.cdf16 = cdf16;
-    plan_predict(b, m, {p}, 1, st);
+    if (modelled) {
+      PredSeg p;
+      memset(&p, 0, sizeof(p));
+      p.F = features_of(m, B, d);
+      p.fc1 = dlayer(m, d, m->first[d + 1] - m->first[d] - 2);
+      p.fc2 = dlayer(m, d, m->first[d + 1] - m->first[d] - 1);
+      p.rows = (int)fr.tot[d];
+      p.cdf16 = cdf16;
+      plan_predict(b, m, {p}, 1, st);
+    } else {
+      // the CDF row of every node of this base depth is its frame's table
+      const uint64_t* keys = lv.key[d];
+      const int64_t nd_ = fr.tot[d];
+      const int dd = d, nb_ = nb, nl = (int)live.size();
+      const size_t ro = brow_off;
+      b.launch("base", nd_, [=](const uint8_t* base) {
+        return launch_base_rows(keys, nd_, dd, nb_, nl, (const uint16_t*)(base + ro), cdf16, st);
+      });
+    }
     const size_t co = b.add(dchunks[d]);
     const int nch = (int)dchunks[d].size();
     {
@@ -1702,7 +1906,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       int32_t* cst = lv.cstart[d];
       uint32_t* e1 = err + 1;
       uint32_t* cs = csum;
-      const bool hashed = d + 1 <= k0 && B.kmap[d + 1];
+      const bool hashed = d + 1 <= k0 && d + 1 >= nb && B.kmap[d + 1];
       uint64_t* tk = hashed ? B.hkeys[d + 1] : nullptr;
       int32_t* tv = hashed ? B.hvals[d + 1] : nullptr;
       const uint64_t hm = hashed ? B.hmask[d + 1] : 0;
@@ -1711,12 +1915,12 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
                                     st);
       });
     }
-    if (t <= k0 && B.kmap[t]) {
+    if (t <= k0 && t >= nb && B.kmap[t]) {
       join(st, sd);  // the expansion filled the hash table of depth t
       plan_kmap_only(b, lv, fr, B, t, sd);
       if (t == k0) kmap_k0 = mark(sd);
     }
-    if (t <= k0) {
+    if (t <= k0 && modelled) {
       wait(st, resblock);  // the ResBlock output (not the neighbour table)
       plan_shallow_up(b, m, lv, fr, B, t, st);
     }
@@ -1893,7 +2097,8 @@ const char* lpcc_last_error(const lpcc_ctx* c) { return c ? c->err.c_str() : "nu
 
 int lpcc_peek_header(const uint8_t* bs, size_t len, int* D, int64_t* n_points) {
   if (!bs) return LPCC_E_INVAL;
-  if (len < 16 || bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' || bs[4] != 1) return LPCC_E_CORRUPT;
+  if (len < 16 || bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' || (bs[4] != 1 && bs[4] != 2))
+    return LPCC_E_CORRUPT;
   if (bs[5] < 1 || bs[5] > kMaxD) return LPCC_E_CORRUPT;
   if (D) *D = bs[5];
   if (n_points) *n_points = rd32(bs + 12);
@@ -1988,6 +2193,12 @@ int lpcc_ctx_graph_stats(lpcc_ctx* c, int64_t* instantiated, int64_t* updated) {
 int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb) {
   if (!c || !(rb == 0 || rb == 1 || rb == 2 || rb == 4)) return LPCC_E_INVAL;
   c->tiling = rb;
+  return LPCC_OK;
+}
+
+int lpcc_ctx_set_base_depth(lpcc_ctx* c, int base) {
+  if (!c || base < 0 || base >= kMaxD) return LPCC_E_INVAL;
+  c->base = base;
   return LPCC_OK;
 }
 

@@ -80,6 +80,7 @@ def lib():
         L.lpcc_softmax_table.argtypes = [vp]
         L.lpcc_requant_bounds.argtypes = [i32, i32, i32, i32, vp]
         L.lpcc_ctx_set_tiling.argtypes = [vp, i32]
+        L.lpcc_ctx_set_base_depth.argtypes = [vp, i32]
         L.lpcc_ctx_set_graphs.argtypes = [vp, i32]
         L.lpcc_ctx_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.lpcc_ctx_tuning.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
@@ -185,6 +186,10 @@ class Context:
     # number of 16-row blocks per wave
     def set_tiling(self, rb: int):
         _check(lib().lpcc_ctx_set_tiling(self.handle, int(rb)), self.handle)
+
+    # -- base geometry: depths below B coded from their own code counts
+    def set_base_depth(self, base: int):
+        _check(lib().lpcc_ctx_set_base_depth(self.handle, int(base)), self.handle)
 
     # -- graph mode: launch batches captured into HIP graphs and replayed
     def set_graphs(self, on: bool):
