@@ -197,6 +197,7 @@ hipError_t launch_level_write(const uint64_t* keys, int64_t n, int D, int tile, 
 hipError_t launch_sentinels(const LevelOut& lo, const uint32_t* totals, int D, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_iota_u64(uint64_t* p, int64_t n, hipStream_t s);  // p[i] = i
 
 hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
                               uint64_t mask, hipStream_t s);

@@ -1786,17 +1786,8 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     HIPC(hipMemcpyAsync(payload + payoff[f], bs[f] + H[f].hdr, pl,
                         is_device_ptr(bs[f]) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
   }
-  {
-    // V_0: one root per live frame; its key is the frame's position tag
-    std::vector<uint64_t> roots;
-    for (size_t i = 0; i < live.size(); i++) roots.push_back((uint64_t)i);
-    s = reserve_pinned(c, roots.size() * 8 + 256);
-    if (s) return s;
-    memcpy(c->pinned, roots.data(), roots.size() * 8);
-    HIPC(hipMemcpyAsync(lv.key[0], c->pinned, roots.size() * 8, hipMemcpyHostToDevice, st));
-    HIPC(hipStreamSynchronize(st));
-    desc_off = align_up(roots.size() * 8, 256);
-  }
+  // V_0: one root per live frame; its key is the frame's position tag
+  HIPC(launch_iota_u64(lv.key[0], (int64_t)live.size(), st));
   HIPC(launch_fill_u32(err, 4, 0, st));
 
   Batch b;
@@ -1932,8 +1923,18 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   }
   s = run_batch(c, b, &desc_off);
   if (s) return s;
-  // coordinates
-  uint32_t herr[4];
+  // coordinates, enqueued before the error words are read (a corrupt frame
+  // only writes within its own output; its status then reports the error)
+  for (int f : live) {
+    const uint64_t* keys = lv.key[D] + fr.off[f][D];
+    int32_t* dst = xdev[f] ? xyz_out[f] : xyz_stage + 3 * fr.off[f][D];
+    HIPC(launch_keys_to_xyz(keys, fr.N[f][D], D, dst, st));
+    if (!xdev[f])
+      HIPC(hipMemcpyAsync(xyz_out[f], dst, (size_t)fr.N[f][D] * 12, hipMemcpyDeviceToHost, st));
+  }
+  s = reserve_pinned(c, desc_off + 256);
+  if (s) return s;
+  uint32_t* herr = (uint32_t*)(c->pinned + c->pinned_cap - 256);
   HIPC(hipMemcpyAsync(herr, err, 16, hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
   if (herr[0] | herr[1]) {
@@ -1954,14 +1955,6 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
     return ret;
   }
-  for (int f : live) {
-    const uint64_t* keys = lv.key[D] + fr.off[f][D];
-    int32_t* dst = xdev[f] ? xyz_out[f] : xyz_stage + 3 * fr.off[f][D];
-    HIPC(launch_keys_to_xyz(keys, fr.N[f][D], D, dst, st));
-    if (!xdev[f])
-      HIPC(hipMemcpyAsync(xyz_out[f], dst, (size_t)fr.N[f][D] * 12, hipMemcpyDeviceToHost, st));
-  }
-  HIPC(hipStreamSynchronize(st));
   int ret = LPCC_OK;
   for (int f = 0; f < nf; f++)
     if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
