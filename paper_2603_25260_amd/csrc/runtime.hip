@@ -1403,9 +1403,14 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   // ---- stream assembly: lengths -> headers -> payload placement
   const size_t nch = chunks.size();
   std::vector<uint32_t> hl(nch);
-  if (nch) {
-    HIPC(hipMemcpyAsync(hl.data(), lens, nch * 4, hipMemcpyDeviceToHost, st));
+  if (nch) {  // through pinned memory, past this call's descriptor blocks
+    const size_t lb = align_up(nch * 4, 256);
+    s = reserve_pinned(c, desc_off + lb);
+    if (s) return s;
+    uint32_t* hp = (uint32_t*)(c->pinned + c->pinned_cap - lb);
+    HIPC(hipMemcpyAsync(hp, lens, nch * 4, hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
+    memcpy(hl.data(), hp, nch * 4);
   }
   std::vector<std::vector<uint8_t>> hdr(nf);
   std::vector<size_t> total(nf, 0);
@@ -1469,19 +1474,44 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
       ci += nchf;
     }
   }
+  // payload placement and the headers of device outputs in one batch: the
+  // headers travel with the descriptor block and are copied on the device
   if (nch) {
     const size_t co = b.add(chunks), po = b.add(dst);
     const int n_ch = (int)nch;
     b.launch("pack", 0, [=](const uint8_t* base) {
       return launch_rc_pack((const Chunk*)(base + co), n_ch, scratch, lens, (uint8_t* const*)(base + po), st);
     });
+  }
+  {
+    std::vector<uint8_t> hblob;
+    std::vector<size_t> hoff(nf, 0);
+    for (int f = 0; f < nf; f++) {
+      if (status[f] != LPCC_OK || !odev[f]) continue;
+      hoff[f] = hblob.size();
+      hblob.insert(hblob.end(), hdr[f].begin(), hdr[f].end());
+      hblob.resize(align_up(hblob.size(), 16), 0);
+    }
+    if (!hblob.empty()) {
+      const size_t ho = b.add(hblob);
+      for (int f = 0; f < nf; f++) {
+        if (status[f] != LPCC_OK || !odev[f]) continue;
+        uint8_t* o = os.out[f];
+        const size_t at = ho + hoff[f], n_ = hdr[f].size();
+        b.launch("header", 0, [=](const uint8_t* base) {
+          return hipMemcpyAsync(o, base + at, n_, hipMemcpyDeviceToDevice, st);
+        });
+      }
+    }
+  }
+  if (!b.launches.empty()) {
     s = run_batch(c, b, &desc_off);
     if (s) return s;
   }
   for (int f = 0; f < nf; f++) {
     if (status[f] != LPCC_OK) continue;
     if (odev[f]) {
-      HIPC(hipMemcpyAsync(os.out[f], hdr[f].data(), hdr[f].size(), hipMemcpyHostToDevice, st));
+      // written by the batch above
     } else {
       memcpy(os.out[f], hdr[f].data(), hdr[f].size());
       if (total[f] > hdr[f].size())
