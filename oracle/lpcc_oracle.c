@@ -185,6 +185,7 @@ typedef struct {
 
 typedef struct {
     int C, D, n_deep, k0;
+    int xfp;  /* 1: cross-scale feature propagation (blob version 1); 0: the ablation without it (version 2) */
     uint32_t blob_id;
     int n_layers;
     layer_t *L;
@@ -203,19 +204,24 @@ static uint32_t rd32(const uint8_t *p)
     return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
 }
 
-/* expected (kind, j, taps, cin, cout) sequence of one coded depth */
-static int expected_layers(int C, int D, int n_deep, int d, int out[][5])
+/* expected (kind, j, taps, cin, cout) sequence of one coded depth; without */
+/* cross-scale propagation (xfp = 0) a shallow depth first embeds X_{d-1}   */
+/* and the deep ResBlock reads G alone (C -> C, identity skip)              */
+static int expected_layers(int C, int D, int n_deep, int xfp, int d, int out[][5])
 {
     int k0 = D - n_deep - 1, n = 0;
     if (d >= 1 && d <= k0) {
+        if (!xfp) { int e[5] = {K_EMB, d - 1, 1, 8, C}; memcpy(out[n++], e, sizeof(e)); }
         int a[3][5] = {{K_CONV1, 0, 27, C, C}, {K_CONV2, 0, 27, C, C}, {K_UP, d - 1, 1, C + 8, 8 * C}};
         for (int i = 0; i < 3; i++) memcpy(out[n++], a[i], sizeof(a[i]));
     } else if (d > k0) {
         int e[5] = {K_EMB, d - 1, 1, 8, C};
         memcpy(out[n++], e, sizeof(e));
         for (int j = d - 1; j > k0; j--) { int t[5] = {K_DOWN, j, 8, C, C}; memcpy(out[n++], t, sizeof(t)); }
-        int r1[5] = {K_CONV1, k0, 27, 2 * C, C}, r2[5] = {K_CONV2, k0, 27, C, C}, sk[5] = {K_SKIP, k0, 1, 2 * C, C};
-        memcpy(out[n++], r1, sizeof(r1)); memcpy(out[n++], r2, sizeof(r2)); memcpy(out[n++], sk, sizeof(sk));
+        int cin = xfp ? 2 * C : C;
+        int r1[5] = {K_CONV1, k0, 27, cin, C}, r2[5] = {K_CONV2, k0, 27, C, C}, sk[5] = {K_SKIP, k0, 1, 2 * C, C};
+        memcpy(out[n++], r1, sizeof(r1)); memcpy(out[n++], r2, sizeof(r2));
+        if (xfp) memcpy(out[n++], sk, sizeof(sk));
         for (int j = k0; j < d; j++) { int t[5] = {K_UP, j, 1, C + 8, 8 * C}; memcpy(out[n++], t, sizeof(t)); }
     }
     int f1[5] = {K_FC1, d, 1, C, C}, f2[5] = {K_FC2, d, 1, C, NSYM};
@@ -228,7 +234,8 @@ static void model_free(model_t *M) { free(M->L); M->L = NULL; }
 static int model_parse(const uint8_t *b, size_t len, model_t *M)
 {
     memset(M, 0, sizeof(*M));
-    if (!b || len < 32 || rd32(b) != 0x5743504Cu || rd32(b + 4) != 1) return ORC_E_MODEL;
+    if (!b || len < 32 || rd32(b) != 0x5743504Cu || (rd32(b + 4) != 1 && rd32(b + 4) != 2)) return ORC_E_MODEL;
+    M->xfp = rd32(b + 4) == 1;
     M->C = (int)rd32(b + 8); M->D = (int)rd32(b + 12); M->n_deep = (int)rd32(b + 16);
     M->n_layers = (int)rd32(b + 20);
     if (M->C < 1 || M->C > 256 || M->D < 1 || M->D > MAXD || M->n_deep < 0 || M->n_deep > M->D - 1)
@@ -242,7 +249,7 @@ static int model_parse(const uint8_t *b, size_t len, model_t *M)
     int exp[64][5];
     for (int d = 0; d < M->D; d++) {
         M->first[d] = li;
-        int ne = expected_layers(M->C, M->D, M->n_deep, d, exp);
+        int ne = expected_layers(M->C, M->D, M->n_deep, M->xfp, d, exp);
         for (int e = 0; e < ne; e++, li++) {
             if (li >= M->n_layers || off + 44 > len) goto bad;
             layer_t *L = &M->L[li];
@@ -464,6 +471,12 @@ static void counts_to_cdf(const uint32_t *n, int32_t *cdf)
 /*                  for j = k0 .. d-1; F_d = Z_d.                           */
 /* ResBlock(x) = clamp(rq(conv2(relu-rq(conv1(x)))) + skip(x)), skip = x    */
 /* when the widths agree, else a requantised 2C -> C linear layer.          */
+/* Without cross-scale propagation (the ablation of Sec. 4.4, Table 4;     */
+/* blob version 2) nothing is carried from F_{d-1} or F_k0:                 */
+/*   B < d <= k0  : E = Emb(bits(X_{d-1})) on V_{d-1}, S = ResBlock(E);     */
+/*                  F_d = Prune(Up([S | bits(X_{d-1})]), X_{d-1})           */
+/*   d > k0       : H = ResBlock(G) on V_k0 (identity skip), then as above. */
+/* With n_deep = 0 (no re-densified depth) this is the ablation baseline.   */
 /* ------------------------------------------------------------------------ */
 static int resblock(const model_t *M, const layer_t *c1, const layer_t *c2, const layer_t *sk,
                     const octree_t *T, int j, const int8_t *x, int8_t *out)
@@ -508,10 +521,24 @@ static int features(const model_t *M, const octree_t *T, int d, int B, const int
         int64_t Np = T->N[d - 1], rows;
         int8_t *S = (int8_t *)malloc((size_t)(Np > 0 ? Np : 1) * C);
         if (!S) { free(out); return ORC_E_NOMEM; }
-        st = resblock(M, &L[0], &L[1], NULL, T, d - 1, F_prev, S);
-        if (st == ORC_OK) st = up_prune(&L[2], C, S, T->code[d - 1], Np, out, &rows);
+        int li = 0;
+        const int8_t *x = F_prev;
+        int8_t *E = NULL;
+        if (!M->xfp) {
+            /* the ResBlock input is the embedding of the parent codes */
+            int8_t *bits = (int8_t *)malloc((size_t)(Np > 0 ? Np : 1) * 8);
+            E = (int8_t *)malloc((size_t)(Np > 0 ? Np : 1) * C);
+            if (!bits || !E) { free(bits); free(E); free(S); free(out); return ORC_E_NOMEM; }
+            for (int64_t i = 0; i < Np; i++) code_bits(T->code[d - 1][i], bits + 8 * i);
+            st = linear(&L[li++], bits, Np, E);
+            free(bits);
+            x = E;
+        }
+        if (st == ORC_OK) st = resblock(M, &L[li], &L[li + 1], NULL, T, d - 1, x, S);
+        if (st == ORC_OK) st = up_prune(&L[li + 2], C, S, T->code[d - 1], Np, out, &rows);
         if (st == ORC_OK && rows != Nd) st = ORC_E_CORRUPT;
         free(S);
+        free(E);
     } else {
         /* Down: embed bits(X_{d-1}) at depth d-1, then k2s2 steps to k0 */
         int li = 0;
@@ -531,18 +558,21 @@ static int features(const model_t *M, const octree_t *T, int d, int B, const int
             st = down_k2s2(dn, G, T->key[j], cs, T->N[j - 1], G2);
             free(cs); free(G); G = G2;
         }
-        /* ResBlock on [F_k0 | G] at depth k0 */
+        /* ResBlock on [F_k0 | G] at depth k0 (on G alone without propagation) */
         int64_t Nk = T->N[k0];
         int8_t *cat = (int8_t *)malloc((size_t)(Nk > 0 ? Nk : 1) * 2 * C);
         int8_t *Z = (int8_t *)malloc((size_t)(Nk > 0 ? Nk : 1) * C);
         if (st == ORC_OK && (!cat || !Z)) st = ORC_E_NOMEM;
-        if (st == ORC_OK) {
+        if (st == ORC_OK && M->xfp) {
             for (int64_t i = 0; i < Nk; i++) {
                 memcpy(cat + i * 2 * C, F_k0 + i * C, (size_t)C);
                 memcpy(cat + i * 2 * C + C, G + i * C, (size_t)C);
             }
             st = resblock(M, &L[li], &L[li + 1], &L[li + 2], T, k0, cat, Z);
             li += 3;
+        } else if (st == ORC_OK) {
+            st = resblock(M, &L[li], &L[li + 1], NULL, T, k0, G, Z);
+            li += 2;
         }
         free(G); free(cat);
         /* Re-sparsification: upsample and prune from k0 to d */

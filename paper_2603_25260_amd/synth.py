@@ -54,8 +54,14 @@ BLOB_MAGIC = 0x5743504C  # b"LPCW"
 N_SYMBOLS = 255
 
 
-def layer_plan(C: int, D: int, n_deep: int):
-    """List of (kind, depth, j, taps, cin, cout) in blob order."""
+def layer_plan(C: int, D: int, n_deep: int, xfp: bool = True):
+    """List of (kind, depth, j, taps, cin, cout) in blob order.
+
+    ``xfp = False`` is the ablation without cross-scale feature propagation
+    (blob version 2): the features of depth d come from the codes of depth
+    d-1 alone (an embedding of X_{d-1}, a ResBlock with identity skip, the
+    upsampling), and the deep ResBlock reads G alone (C -> C, identity skip,
+    no skip layer).  With n_deep = 0 as well it is the ablation's baseline."""
     if not (1 <= D <= 21):
         raise ValueError("D must be in [1, 21]")
     if not (0 <= n_deep <= D - 1):
@@ -66,14 +72,19 @@ def layer_plan(C: int, D: int, n_deep: int):
         if d == 0:
             pass
         elif d <= k0:
+            if not xfp:
+                plan.append((EMB, d, d - 1, 1, 8, C))
             plan += [(CONV1, d, 0, 27, C, C), (CONV2, d, 0, 27, C, C),
                      (UP, d, d - 1, 1, C + 8, 8 * C)]
         else:
             plan.append((EMB, d, d - 1, 1, 8, C))
             for j in range(d - 1, k0, -1):
                 plan.append((DOWN, d, j, 8, C, C))
-            plan += [(CONV1, d, k0, 27, 2 * C, C), (CONV2, d, k0, 27, C, C),
-                     (SKIP, d, k0, 1, 2 * C, C)]
+            if xfp:
+                plan += [(CONV1, d, k0, 27, 2 * C, C), (CONV2, d, k0, 27, C, C),
+                         (SKIP, d, k0, 1, 2 * C, C)]
+            else:
+                plan += [(CONV1, d, k0, 27, C, C), (CONV2, d, k0, 27, C, C)]
             for j in range(k0, d):
                 plan.append((UP, d, j, 1, C + 8, 8 * C))
         plan += [(FC1, d, d, 1, C, C), (FC2, d, d, 1, C, N_SYMBOLS)]
@@ -99,7 +110,7 @@ def splitmix64(seed: int, start: int, n: int) -> np.ndarray:
 
 def make_weights(seed: int, C: int, D: int, n_deep: int, *,
                  zero_points: bool = False, gain: float = 1.0,
-                 shift: int = 24) -> bytes:
+                 shift: int = 24, xfp: bool = True) -> bytes:
     """Random-init integer weight blob for channel width C and D levels.
 
     W ~ uniform integers in [-127, 127]; bias uniform in [-4096, 4096];
@@ -109,9 +120,9 @@ def make_weights(seed: int, C: int, D: int, n_deep: int, *,
     m_neg = (m_pos * 64) >> 8.  With ``zero_points`` every layer also gets
     input/output zero points in [-8, 8] (to exercise that part of Eq. 13-14).
     """
-    plan = layer_plan(C, D, n_deep)
+    plan = layer_plan(C, D, n_deep, xfp)
     out = bytearray()
-    out += struct.pack("<6IQ", BLOB_MAGIC, 1, C, D, n_deep, len(plan), seed)
+    out += struct.pack("<6IQ", BLOB_MAGIC, 1 if xfp else 2, C, D, n_deep, len(plan), seed)
     ctr = 0
     for (kind, depth, j, taps, cin, cout) in plan:
         nW = taps * cin * cout

@@ -6,11 +6,12 @@ import numpy as np
 from paper_2603_25260_amd import synth
 
 
-def build_blob(C, D, n_deep, fill):
+def build_blob(C, D, n_deep, fill, xfp=True):
     """Blob whose layer (kind, depth, j) gets the arrays ``fill(kind, depth, j, taps, cin, cout)``
-    returns: dict with W [taps, cin, cout] int8, bias [cout] int32, m_pos, m_neg, r, z_in, z_out."""
-    plan = synth.layer_plan(C, D, n_deep)
-    out = bytearray(struct.pack("<6IQ", synth.BLOB_MAGIC, 1, C, D, n_deep, len(plan), 0))
+    returns: dict with W [taps, cin, cout] int8, bias [cout] int32, m_pos, m_neg, r, z_in, z_out.
+    ``xfp = False``: the schedule without cross-scale propagation (blob version 2)."""
+    plan = synth.layer_plan(C, D, n_deep, xfp)
+    out = bytearray(struct.pack("<6IQ", synth.BLOB_MAGIC, 1 if xfp else 2, C, D, n_deep, len(plan), 0))
     for (kind, depth, j, taps, cin, cout) in plan:
         p = fill(kind, depth, j, taps, cin, cout)
         W = np.asarray(p["W"], np.int8).reshape(taps, cin, cout)
