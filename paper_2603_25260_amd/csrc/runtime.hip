@@ -30,6 +30,7 @@ struct HostLayer {
 struct lpcc_model {
   int device = 0;
   int C = 0, D = 0, n_deep = 0, k0 = 0;
+  int xfp = 1;                   // 0: the ablation schedule without cross-scale propagation
   uint32_t blob_id = 0;
   std::vector<int> first;        // first layer index of each depth (size D+1)
   std::vector<HostLayer> host;   // parsed layers
@@ -58,19 +59,23 @@ uint32_t fnv1a(const uint8_t* p, size_t n) {
 struct Spec {
   int kind, j, taps, cin, cout;
 };
-std::vector<Spec> depth_layers(int C, int D, int n_deep, int d) {
+// Without cross-scale propagation (xfp = 0) a shallow depth starts with an
+// embedding of the parent codes, and the deep ResBlock reads G alone (C -> C,
+// identity skip, no skip layer).
+std::vector<Spec> depth_layers(int C, int D, int n_deep, int xfp, int d) {
   const int k0 = D - n_deep - 1;
   std::vector<Spec> v;
   if (d >= 1 && d <= k0) {
+    if (!xfp) v.push_back({K_EMB, d - 1, 1, 8, C});
     v.push_back({K_CONV1, 0, 27, C, C});
     v.push_back({K_CONV2, 0, 27, C, C});
     v.push_back({K_UP, d - 1, 1, C + 8, 8 * C});
   } else if (d > k0) {
     v.push_back({K_EMB, d - 1, 1, 8, C});
     for (int j = d - 1; j > k0; j--) v.push_back({K_DOWN, j, 8, C, C});
-    v.push_back({K_CONV1, k0, 27, 2 * C, C});
+    v.push_back({K_CONV1, k0, 27, xfp ? 2 * C : C, C});
     v.push_back({K_CONV2, k0, 27, C, C});
-    v.push_back({K_SKIP, k0, 1, 2 * C, C});
+    if (xfp) v.push_back({K_SKIP, k0, 1, 2 * C, C});
     for (int j = k0; j < d; j++) v.push_back({K_UP, j, 1, C + 8, 8 * C});
   }
   v.push_back({K_FC1, d, 1, C, C});
@@ -92,7 +97,8 @@ void softmax_table(int32_t* E) {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int parse_blob(const uint8_t* b, size_t len, lpcc_model* m) {
-  if (len < 32 || rd32(b) != 0x5743504Cu || rd32(b + 4) != 1) return LPCC_E_MODEL;
+  if (len < 32 || rd32(b) != 0x5743504Cu || (rd32(b + 4) != 1 && rd32(b + 4) != 2)) return LPCC_E_MODEL;
+  m->xfp = rd32(b + 4) == 1;
   m->C = (int)rd32(b + 8);
   m->D = (int)rd32(b + 12);
   m->n_deep = (int)rd32(b + 16);
@@ -105,7 +111,7 @@ int parse_blob(const uint8_t* b, size_t len, lpcc_model* m) {
   m->first.assign(m->D + 1, 0);
   for (int d = 0; d < m->D; d++) {
     m->first[d] = (int)m->host.size();
-    for (const Spec& sp : depth_layers(m->C, m->D, m->n_deep, d)) {
+    for (const Spec& sp : depth_layers(m->C, m->D, m->n_deep, m->xfp, d)) {
       if (off + 44 > len) return LPCC_E_MODEL;
       HostLayer L;
       L.kind = (int)rd32(b + off);
@@ -589,6 +595,7 @@ struct ModelBufs {
   uint64_t* hash_lo = nullptr;        // first word of the contiguous key arrays
   size_t hash_words = 0;              // their extent in u64 words
   int8_t *h = nullptr, *S = nullptr;  // shallow ResBlock temporaries
+  int8_t* E = nullptr;                // embedded parent codes (schedule without propagation)
   // deep temporaries per target depth d
   int8_t* G[kMaxD + 1][kMaxD + 1] = {};  // [d][j] embedding / down-sampled features at depth j
   int8_t* Gk[kMaxD + 1] = {};            // [tot[k0]][C]: G of target d at depth k0
@@ -612,6 +619,7 @@ void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, cons
   }
   B.h = A.take<int8_t>((size_t)tmax * C);
   B.S = A.take<int8_t>((size_t)tmax * C);
+  if (!m->xfp) B.E = A.take<int8_t>((size_t)tmax * C);
   // all hash-table key arrays first and contiguous, so that one fill clears them
   const int kmax = std::min(last, k0);
   auto hashed = [&](int j) { return j >= base && need_kmap(m, j) && !(j >= last && !(j == k0 && last > k0)); };
@@ -788,24 +796,39 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
 // Shallow depth d (1 <= d <= k0): S = ResBlock(F_{d-1}); F_d = Prune(Up([S | bits X_{d-1}]))
 // The ResBlock part of shallow depth d (needs F_{d-1} and the neighbour
 // table of depth d-1, not the codes of depth d-1)
-void plan_shallow_convs(Batch& b, const lpcc_model* m, const Frames& fr, ModelBufs& B, int d, hipStream_t st) {
+// ResBlock at depth d-1 for shallow depth d: on F_{d-1}, or, without
+// cross-scale propagation, on the embedding of the codes X_{d-1}
+void plan_shallow_convs(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B, int d,
+                        hipStream_t st) {
   const int C = m->C;
   const int j = d - 1;
   const int rows = (int)fr.tot[j];
+  const int8_t* x = B.F[j];
+  int li = 0;
+  if (!m->xfp) {
+    GemmSeg e = seg0();
+    e.code = lv.code[j];
+    e.L = dlayer(m, d, li++);
+    e.out = B.E;
+    e.out_stride = C;
+    e.rows = rows;
+    plan_gemm(b, m, "emb", 0, 8, C, {e}, st);
+    x = B.E;
+  }
   GemmSeg s = seg0();
-  s.in = B.F[j];
+  s.in = x;
   s.in_stride = C;
   s.kmap = B.kmap[j];
   s.kstride = fr.tot[j];
-  s.L = dlayer(m, d, 0);
+  s.L = dlayer(m, d, li);
   s.out = B.h;
   s.out_stride = C;
   s.rows = rows;
   plan_gemm(b, m, "conv", G_CONV, C, C, {s}, st);
   s.in = B.h;
-  s.L = dlayer(m, d, 1);
+  s.L = dlayer(m, d, li + 1);
   s.out = B.S;
-  s.resid = B.F[j];
+  s.resid = x;
   s.resid_stride = C;
   plan_gemm(b, m, "conv", G_CONV, C, C, {s}, st);
 }
@@ -821,7 +844,7 @@ void plan_shallow_up(Batch& b, const lpcc_model* m, const Levels& lv, const Fram
   u.in_stride = C;
   u.code = lv.code[j];
   u.cstart = lv.cstart[j];
-  u.L = dlayer(m, d, 2);
+  u.L = dlayer(m, d, m->xfp ? 2 : 3);
   u.out = B.F[d];
   u.out_stride = C;
   u.rows = rows;
@@ -831,7 +854,7 @@ void plan_shallow_up(Batch& b, const lpcc_model* m, const Levels& lv, const Fram
 
 void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B, int d,
                   hipStream_t st) {
-  plan_shallow_convs(b, m, fr, B, d, st);
+  plan_shallow_convs(b, m, lv, fr, B, d, st);
   plan_shallow_up(b, m, lv, fr, B, d, st);
 }
 
@@ -903,16 +926,23 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
   }
   }
   if (part == 1) return;
-  // ResBlock at k0: conv1 (2C -> C), skip (2C -> C), conv2 (+ skip)
+  // ResBlock at k0: conv1 (2C -> C), skip (2C -> C), conv2 (+ skip); without
+  // cross-scale propagation conv1 (C -> C) reads G alone and the skip is G
+  const bool xfp = m->xfp != 0;
   std::vector<GemmSeg> c1, sk, c2;
   for (int d : dset) {
     const int base = 1 + (d - 1 - k0);  // index of conv1 in depth d's layer list
     GemmSeg s = seg0();
-    s.in = B.F[k0];  // [F_k0 | G] without materialising the concatenation
-    s.in_stride = C;
-    s.in2 = B.Gk[d];
-    s.in2_stride = C;
-    s.split = C;
+    if (xfp) {
+      s.in = B.F[k0];  // [F_k0 | G] without materialising the concatenation
+      s.in_stride = C;
+      s.in2 = B.Gk[d];
+      s.in2_stride = C;
+      s.split = C;
+    } else {
+      s.in = B.Gk[d];
+      s.in_stride = C;
+    }
     s.kmap = B.kmap[k0];
     s.kstride = fr.tot[k0];
     s.L = dlayer(m, d, base);
@@ -939,13 +969,17 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
     s2.L = dlayer(m, d, base + 1);
     s2.out = B.Z[d][k0];
     s2.out_stride = C;
-    s2.resid = B.ds[d];
+    s2.resid = xfp ? B.ds[d] : B.Gk[d];
     s2.resid_stride = C;
     s2.rows = (int)fr.tot[k0];
     c2.push_back(s2);
   }
-  plan_gemm(b, m, "conv", G_CONV, 2 * C, C, c1, st);
-  plan_gemm(b, m, "skip", G_DENSE, 2 * C, C, sk, st);
+  if (xfp) {
+    plan_gemm(b, m, "conv", G_CONV, 2 * C, C, c1, st);
+    plan_gemm(b, m, "skip", G_DENSE, 2 * C, C, sk, st);
+  } else {
+    plan_gemm(b, m, "conv", G_CONV, C, C, c1, st);
+  }
   plan_gemm(b, m, "conv", G_CONV, C, C, c2, st);
   // upsample + prune k0 -> d
   int maxup = 0;
@@ -955,7 +989,7 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
     for (int d : dset) {
       const int j = k0 + t;
       if (j >= d) continue;
-      const int base = 1 + (d - 1 - k0) + 3;  // first up layer
+      const int base = 1 + (d - 1 - k0) + (xfp ? 3 : 2);  // first up layer
       GemmSeg u = seg0();
       u.in = B.Z[d][j];
       u.in_stride = C;
@@ -1883,9 +1917,11 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     }
     hipEvent_t resblock = nullptr;
     const bool modelled = d >= nb;  // base depths carry no features
-    if (t <= k0 && modelled) {
+    // the ResBlock of depth t reads F_d (now), or without cross-scale
+    // propagation the codes X_d (after the coder below)
+    if (t <= k0 && modelled && m->xfp) {
       join(st, sd);  // F_d
-      plan_shallow_convs(b, m, fr, B, t, sd);
+      plan_shallow_convs(b, m, lv, fr, B, t, sd);
       resblock = mark(sd);
     }
     if (modelled) {
@@ -1916,6 +1952,11 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       b.launch("rc_decode", fr.tot[d], [=](const uint8_t* base) {
         return launch_rc_decode_sized((const Chunk*)(base + co), nch, payload, cdf16, codes, cs, err + 0, ml, st);
       });
+    }
+    if (t <= k0 && modelled && !m->xfp) {
+      join(st, sd);  // X_d decoded
+      plan_shallow_convs(b, m, lv, fr, B, t, sd);
+      resblock = mark(sd);
     }
     {
       // children of depth d from the chunks' child counts; when depth d+1
