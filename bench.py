@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-base", action="store_true", help="skip the base-geometry lines")
     ap.add_argument("--no-schedules", action="store_true",
-                    help="skip the re-densification threshold variants (t = L-3, L-4, L-5)")
+                    help="skip the schedule variants of the ablations")
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration under a profiler)")
@@ -295,7 +295,7 @@ def main():
                           "same_lengths": plain_lens == ln and lg == ln}
         res["batched_128beam"] = _bench_128beam(lpcc, synth, torch, dev, ctx)
     if not args.no_schedules:
-        res["schedules_t"] = _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout)
+        res["schedules"] = _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout)
     if not args.no_base:
         res["base_geometry"] = _bench_base(lpcc, torch, model, frames, dxyz, cl, dbs, dout, D - cfg.n_deep - 1)
     if not args.no_serve:
@@ -355,13 +355,15 @@ def _bench_128beam(lpcc, synth, torch, dev, ctx):
 
 
 def _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout):
-    """Plain encode+decode of the same 64-beam frames under the threshold
-    variants of the paper's ablation: t = L - n_deep with n_deep = 3, 4
-    (the default) and 5 re-densified depths, each its own seeded model."""
+    """Plain encode+decode of the same 64-beam frames under the schedule
+    variants of the paper's ablations, each its own seeded model: the
+    threshold t = L - n_deep with n_deep = 3, 4 (the default) and 5, and the
+    module ablation without cross-scale propagation, with re-densification
+    (+GRED, n_deep = 4) and without (the baseline, n_deep = 0)."""
     cfg = synth.CONFIGS["cfg2"]
     out = []
-    for nd in (3, 4, 5):
-        m = lpcc.Model(synth.make_weights(cfg.weight_seed, cfg.C, cfg.scan.D, nd), 0)
+    for nd, xfp in ((3, True), (4, True), (5, True), (4, False), (0, False)):
+        m = lpcc.Model(synth.make_weights(cfg.weight_seed, cfg.C, cfg.scan.D, nd, xfp=xfp), 0)
         lens = []
         for k in range(len(frames)):  # warm-up (and the first call's tile tuning)
             n = lpcc.encode_frame(ctx, m, dxyz[k], cl, out=dbs)
@@ -377,7 +379,8 @@ def _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout):
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / reps
         pts = sum(len(f) for f in frames)
-        out.append({"n_deep": nd, "t": f"L-{nd}", "k0": cfg.scan.D - nd - 1,
+        name = ("GRED+XFP" if xfp else "GRED") + f", t = L-{nd}" if nd > 0 or xfp else "baseline (no GRED, no XFP)"
+        out.append({"schedule": name, "n_deep": nd, "xfp": xfp, "k0": cfg.scan.D - nd - 1,
                     "mpts_s": round(pts / wall / 1e6, 3), "ms_per_frame": round(wall / len(frames) * 1e3, 3),
                     "bytes_per_point": round(sum(lens) / pts, 3)})
     return out
