@@ -1888,11 +1888,23 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     c->side = nullptr;
   }
   two = two && c->side;
-  const hipStream_t sd = two ? c->side : st;
+  // Depths with few nodes stay on one stream: their kernels are short, and
+  // the event records and waits of the split would cost the host more than
+  // the overlap gains.  The split starts at the first depth of kSplitRows
+  // nodes (node counts only grow with depth) and lasts to the end.
+  constexpr int64_t kSplitRows = 4096;
+  int dsplit = D;
+  for (int d = 0; d < D; d++)
+    if (fr.tot[d] >= kSplitRows) {
+      dsplit = d;
+      break;
+    }
+  bool two_now = false;  // this iteration runs work on the side stream
+  hipStream_t sd = st;
   bool ok_ev = true;
-  // record an event on `s` now (null when one stream is used)
+  // record an event on `s` now (null while one stream is used)
   auto mark = [&](hipStream_t s) -> hipEvent_t {
-    if (!two) return nullptr;
+    if (!two_now) return nullptr;
     hipEvent_t e = sync_event(c);
     if (!e) {
       ok_ev = false;
@@ -1901,8 +1913,8 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
     plan_record(b, e, s);
     return e;
   };
-  auto wait = [&](hipStream_t s, hipEvent_t e) {
-    if (two && e) plan_wait(b, s, e);
+  auto wait = [&](hipStream_t s, hipEvent_t e) {  // an event from an earlier split iteration still counts
+    if (e) plan_wait(b, s, e);
   };
   auto join = [&](hipStream_t from, hipStream_t to) {
     wait(to, mark(from));
@@ -1910,6 +1922,8 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   };
   hipEvent_t kmap_k0 = nullptr;
   for (int d = 0; d < D; d++) {
+    two_now = two && d >= dsplit;
+    sd = two_now ? c->side : st;
     const int t = d + 1;  // the shallow depth whose features this iteration prepares
     if (d > k0) {
       if (d == k0 + 1) wait(st, kmap_k0);  // the neighbour table of k0
@@ -1987,7 +2001,10 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       plan_shallow_up(b, m, lv, fr, B, t, st);
     }
   }
-  join(sd, st);
+  if (two && dsplit < D) {  // the main stream waits for the side stream's last work
+    two_now = true;
+    join(c->side, st);
+  }
   if (!ok_ev) {
     c->err = "event creation failed";
     return LPCC_E_DEVICE;
