@@ -509,6 +509,14 @@ std::vector<Tile> make_tiles(const std::vector<int64_t>& rows, int rows_per_tile
 
 int64_t nchunks_of(int64_t N, int c) { return (N + (1ll << c) - 1) >> c; }
 
+// number of tiles make_tiles would produce (single-segment launches need only
+// the count: their kernels take the segment by value)
+int64_t count_tiles(const std::vector<int64_t>& rows, int rows_per_tile = 64) {
+  int64_t n = 0;
+  for (int64_t r : rows) n += (r + rows_per_tile - 1) / rows_per_tile;
+  return n;
+}
+
 // ---- tile autotuner ----
 constexpr int kTileRB[3] = {1, 2, 4};
 
@@ -734,9 +742,8 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
     so = b.add(segs);
   }
   if (f == "emb") {
-    auto tiles = make_tiles(rows);
-    const size_t to = segs.size() == 1 ? 0 : b.add(tiles);
-    const int nt = (int)tiles.size();
+    const size_t to = segs.size() == 1 ? 0 : b.add(make_tiles(rows));
+    const int nt = (int)count_tiles(rows);
     b.launch(f, units, [=](const uint8_t* base) {
       return launch_emb((const GemmSeg*)(base + so), (const Tile*)(base + to), nt, cout, one, st);
     });
@@ -758,9 +765,8 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
   std::vector<std::pair<int, size_t>> plan;  // (rb, tile offset)
   std::vector<int> ntiles;
   for (int rb : cands) {
-    auto tiles = make_tiles(rows, 64 * rb);
-    plan.push_back({rb, segs.size() == 1 ? 0 : b.add(tiles)});
-    ntiles.push_back((int)tiles.size());
+    plan.push_back({rb, segs.size() == 1 ? 0 : b.add(make_tiles(rows, 64 * rb))});
+    ntiles.push_back((int)count_tiles(rows, 64 * rb));
   }
   const bool timed = rec != nullptr && cands.size() > 1;
   if (timed) b.has_events = true;
@@ -793,11 +799,10 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
   });
 }
 
-// Shallow depth d (1 <= d <= k0): S = ResBlock(F_{d-1}); F_d = Prune(Up([S | bits X_{d-1}]))
-// The ResBlock part of shallow depth d (needs F_{d-1} and the neighbour
-// table of depth d-1, not the codes of depth d-1)
-// ResBlock at depth d-1 for shallow depth d: on F_{d-1}, or, without
-// cross-scale propagation, on the embedding of the codes X_{d-1}
+// Shallow depth d (1 <= d <= k0): S = ResBlock(F_{d-1}); F_d = Prune(Up([S | bits X_{d-1}])).
+// The ResBlock part: on F_{d-1} with the neighbour table of depth d-1 (not
+// the codes of depth d-1), or, without cross-scale propagation, on the
+// embedding of the codes X_{d-1}.
 void plan_shallow_convs(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr, ModelBufs& B, int d,
                         hipStream_t st) {
   const int C = m->C;
@@ -1017,9 +1022,8 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
     rows.push_back(s.rows);
     units += s.rows;
   }
-  auto tiles = make_tiles(rows);
-  if (tiles.empty()) return;
-  const int nt = (int)tiles.size(), C = m->C;
+  const int nt = (int)count_tiles(rows), C = m->C;
+  if (nt == 0) return;
   PredArg one;
   memset(&one, 0, sizeof(one));
   size_t so = 0, to = 0;
@@ -1030,7 +1034,7 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
     one.one = 1;
   } else {
     so = b.add(segs);
-    to = b.add(tiles);
+    to = b.add(make_tiles(rows));
   }
   const int32_t* lut = m->d_lut;
   b.launch("predict", units, [=](const uint8_t* base) {
