@@ -122,18 +122,21 @@ hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scrat
 // padded: bytes past the end read as 0) and consumed through a dword window.
 // CDF rows are loaded kDecBlock at a time straight into registers (one
 // memory round trip per block, the next block in flight while this one is
-// decoded).  Lane l holds the boundaries b_j = cdf[4l + j], j = 0..4, of the
-// current node (b_4 is lane l+1's b_0; cdf[255] = 65536 and lane 63 has no
-// b_4).  The symbol s is the last index with r * cdf[s] <= code (r, cdf <
-// 2^17, so 24-bit multiplies are exact).  Every lane resolves the candidate
-// inside its own four entries (lo, freq) with compares and selects; the
-// owning lane is popcount(ballot(r * b_0 <= code)) - 1 (lane 0 always
-// qualifies, cdf[0] = 0), and one readlane brings its packed (lo, freq) to
-// the scalar coder state.  A corrupt stream is one where no symbol fits
-// (code >= r * 2^16): lane 63 then resolves to lo = 65536, freq = 0, the
-// range becomes 0 and stays 0, which is checked once per block.  Decoded
-// codes are collected one per lane and stored kDecBlock at a time.
-// Chunk.pad_ carries the payload length in bytes, Chunk.scratch its offset.
+// decoded).  Lane l holds the boundaries b_j = cdf[4l + j], j = 0..3, of the
+// current node as two packed words (b_0 b_1 | b_2 b_3), and b_4 is lane l+1's
+// b_0.  cdf[255] = 2^16 is stored as 0.  The symbol s is the last index with
+// r * cdf[s] <= code (r < 2^16, cdf <= 2^16, so 24-bit multiplies are exact).
+// Every lane compares its four entries and selects the packed pair
+// (b_j, b_j+1) of the last entry passed; the owning lane is
+// popcount(ballot(r * b_0 <= code)) - 1 (lane 0 always qualifies, cdf[0] =
+// 0), and one readlane brings the pair to the scalar coder state, where an
+// upper boundary of 0 stands for 2^16 (the frequency is taken mod 2^16).  A
+// corrupt stream is one where no symbol fits (code >= r * 2^16): lane 63,
+// whose b_3 compares as 2^16, then passes all four entries and yields the
+// pair (0, 0), so the range becomes 0 and stays 0, which is checked once per
+// block.  Decoded codes are collected one per lane and stored kDecBlock at a
+// time.  Chunk.pad_ carries the payload length in bytes, Chunk.scratch its
+// offset.
 // ---------------------------------------------------------------------------
 constexpr int kDecBlock = 32;
 
@@ -193,61 +196,77 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
     }
     return (uint32_t)__builtin_amdgcn_readlane((int)creg, (int)(w & 63u));
   };
-  // bit buffer: the next `nb` stream bytes, first byte in bits 63..56
+  // bit buffer: the next `nbit` stream bits (whole bytes), first byte in bits 63..56
   uint64_t bb = 0;
-  uint32_t nb = 0, wnext = 0;
-  auto refill = [&]() {  // append one dword (4 bytes, stream order)
-    bb |= (uint64_t)dword(wnext++) << (32 - 8 * nb);
-    nb += 4;
+  uint32_t nbit = 0, wnext = 0;
+  auto refill = [&]() {  // append one dword (4 bytes, stream order); nbit < 32
+    bb |= (uint64_t)dword(wnext++) << (32 - nbit);
+    nbit += 32;
   };
   refill();
   refill();
   // the first 5 bytes: the first is always 0 and shifts out of 32 bits
   uint32_t code = (uint32_t)(bb >> 24);
   bb <<= 40;
-  nb -= 5;
+  nbit -= 40;
   uint32_t range = 0xFFFFFFFFu;
 
   uint32_t kids = 0;  // children announced by the codes this lane stored
-  const bool last_lane = lane == 63;
   const uint32_t lane4p1 = 4u * (uint32_t)lane + 1u;
+  // high half of b_3 for the compare: lane 63's b_3 = cdf[255] is stored as 0
+  // and compares as 2^16
+  const uint32_t b3hi = lane == 63 ? 1u : 0u;
   bool bad = false;
 
+  // one symbol from the row (b_0 b_1 | b_2 b_3) of this lane; its code goes to lane k of cv
+  auto symbol = [&](const uint2 row, const int k, uint32_t& cv) {
+    const uint32_t x = row.x, y = row.y;
+    // lane+1's (b_0, b_1); 0 in lane 63 (bound_ctrl: out-of-range source reads 0)
+    const uint32_t nx = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130, 0xF, 0xF, true);
+    const uint32_t r = range >> 16;
+    const uint32_t b3 = __builtin_amdgcn_alignbit(b3hi, y, 16);
+    const bool m0 = __umul24(r, x & 0xFFFFu) <= code;
+    const bool m1 = __umul24(r, x >> 16) <= code;
+    const bool m2 = __umul24(r, y & 0xFFFFu) <= code;
+    const bool m3 = __umul24(r, b3) <= code;
+    // (b_j, b_{j+1}) packed low/high for the last entry j passed
+    // (bytes 2, 3 of the low word, bytes 0, 1 of the high word)
+    const uint32_t q1 = __builtin_amdgcn_perm(y, x, 0x05040302u);
+    const uint32_t q3 = __builtin_amdgcn_perm(nx, y, 0x05040302u);
+    uint32_t q = m1 ? q1 : x;
+    q = m2 ? y : q;
+    q = m3 ? q3 : q;
+    // code (symbol + 1) of this lane's candidate: 4 lane + 1 + entries passed
+    const uint32_t cand = lane4p1 + (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
+    const int L = (int)__popcll(__ballot(m0)) - 1;
+    const uint32_t Q = (uint32_t)__builtin_amdgcn_readlane((int)q, L);
+    const uint32_t lo = Q & 0xFFFFu;
+    // an upper boundary stored as 0 is 2^16; both 0 on a corrupt stream
+    const uint32_t freq = ((Q >> 16) - lo) & 0xFFFFu;
+    code -= r * lo;
+    range = r * freq;
+    // renormalise: a valid step leaves range >= 2^8, so take 0, 1 or 2 bytes
+    const uint32_t sh = (uint32_t)__builtin_clz(range | 1u) & 24u;
+    // (code, top 4 buffered bytes) as one 64-bit register pair, shifted up
+    const uint64_t cx = __builtin_bit_cast(uint64_t, make_uint2((uint32_t)(bb >> 32), code));
+    code = (uint32_t)((cx << sh) >> 32);
+    bb <<= sh;
+    nbit -= sh;
+    range <<= sh;
+    const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cand, L);
+    cv = lane == k ? c1 : cv;
+  };
   // one block of up to kDecBlock symbols from the rows in t (fully unrolled:
-  // row k is register t[k]); then t is reloaded with the block two ahead
+  // row k is register t[k]); then t is reloaded with the block two ahead.
+  // A symbol takes at most 2 bytes: 4 buffered bytes cover a pair.
   auto block = [&](uint2 (&t)[kDecBlock], int base) {
     const int cnt = min(kDecBlock, n - base);
     uint32_t cv = 0;  // decoded code k of this block in lane k
 #pragma unroll
     for (int k = 0; k < kDecBlock; k++) {
       if (k < cnt) {
-        const uint2 row = t[k];
-        const uint32_t nx = (uint32_t)__builtin_amdgcn_mov_dpp((int)row.x, 0x130, 0xF, 0xF, false);  // lane+1
-        if (__builtin_expect(nb < 2u, 0)) refill();
-        const uint32_t r = range >> 16;
-        const uint32_t b0 = row.x & 0xFFFFu, b1 = row.x >> 16, b2 = row.y & 0xFFFFu;
-        const uint32_t b3 = last_lane ? 65536u : (row.y >> 16);
-        const uint32_t b4 = last_lane ? 65536u : (nx & 0xFFFFu);
-        const bool m0 = __umul24(r, b0) <= code;
-        const bool m1 = __umul24(r, b1) <= code;
-        const bool m2 = __umul24(r, b2) <= code;
-        const bool m3 = __umul24(r, b3) <= code;
-        const uint32_t lo = m3 ? b3 : (m2 ? b2 : (m1 ? b1 : b0));
-        const uint32_t hi = m3 ? b4 : (m2 ? b3 : (m1 ? b2 : b1));
-        // code (symbol + 1) of this lane's candidate: 4 lane + 1 + entries passed
-        const uint32_t cand = lane4p1 + (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
-        const int L = (int)__popcll(__ballot(m0)) - 1;
-        const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)(lo | ((hi - lo) << 16)), L);
-        code -= r * (P & 0xFFFFu);
-        range = r * (P >> 16);
-        // renormalise: a valid step leaves range >= 2^8, so take 0, 1 or 2 bytes
-        const uint32_t sh = range < (1u << 16) ? 16u : (range < (1u << 24) ? 8u : 0u);
-        code = (uint32_t)((((uint64_t)code << 32) | (bb >> 32)) >> (32 - sh));
-        bb <<= sh;
-        nb -= sh >> 3;
-        range <<= sh;
-        const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cand, L);
-        cv = lane == k ? c1 : cv;
+        if ((k & 1) == 0 && nbit < 32u) refill();
+        symbol(t[k], k, cv);
       }
     }
     bad = range == 0u;
