@@ -710,42 +710,68 @@ hipError_t launch_emb(const GemmSeg* segs, const Tile* tiles, int ntiles, int C,
 //   M = max l, E_i = LUT[M - l_i], S = sum E_i
 //   f_i = 1 + floor(E_i * 65281 / S), the remainder 65536 - sum f goes to the
 //   lowest index holding M;  cdf[s] = sum_{i<s} f_i.
-// Division: floor(n / S) = q or q+1 with q = mulhi(n, floor(2^32 / S)); the
-// reciprocal comes from a shift-subtract long division.  Integer-only.
+// Division: for E <= 2^15 and 2^15 <= S < 2^23, floor(E * 65281 / S) is
+// q' or q'+1 with q' = (E * K) >> 22 and K = floor(65281 * 2^22 / S): the
+// two quotients differ by less than E / 2^22 < 1.  K < 2^23 and E < 2^16, so
+// every product is a full-rate 24-bit multiply; K comes from a shift-subtract
+// long division once per node.  Integer-only.
 // A wave handles 16 nodes; lane l owns rows 4(l/16)+i and columns 16b + l%16.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t recip32(uint32_t S) {  // floor(2^32 / S), 2^15 <= S < 2^23
-  uint64_t rem = 1ull << 32;
+__device__ __forceinline__ uint32_t recip_k(uint32_t S) {  // floor(65281 * 2^22 / S), 2^15 <= S < 2^23
+  uint64_t rem = 65281ull << 22;
   uint32_t q = 0;
 #pragma unroll
-  for (int b = 17; b >= 0; b--) {
-    uint64_t t = (uint64_t)S << b;
+  for (int b = 22; b >= 0; b--) {
+    const uint64_t t = (uint64_t)S << b;
     if (rem >= t) { rem -= t; q |= 1u << b; }
   }
   return q;
 }
 
-__device__ __forceinline__ uint32_t divS(uint32_t n, uint32_t S, uint32_t inv) {
-  uint32_t q = __umulhi(n, inv);
-  uint32_t rem = n - q * S;
+// E < 2^16 (a 16-bit table entry), K < 2^23 (masked by the caller), S < 2^23.
+// The quotient is at most 65281, so q' fits 16 bits; the masks only tell the
+// instruction selector that 24-bit multiplies suffice.
+__device__ __forceinline__ uint32_t div_freq(uint32_t E, uint32_t S, uint32_t K) {  // floor(E * 65281 / S)
+  const uint32_t q = (uint32_t)(((uint64_t)E * (uint64_t)K) >> 22);
+  const uint32_t rem = __umul24(E, 65281u) - __umul24(q & 0xFFFFu, S & 0xFFFFFFu);  // in [0, 2S)
   return rem >= S ? q + 1 : q;
 }
 
-// reductions over the 16 lanes sharing l/16
+// reductions over the 16 lanes of a DPP row (rotations by 8, 4, 2, 1 leave the
+// result in every lane of the row)
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
 __device__ __forceinline__ int red16_max(int v) {
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) v = max(v, __shfl_xor(v, o));
-  return v;
+  v = max(v, dpp_mov<0x128>(v));
+  v = max(v, dpp_mov<0x124>(v));
+  v = max(v, dpp_mov<0x122>(v));
+  return max(v, dpp_mov<0x121>(v));
 }
 __device__ __forceinline__ int red16_min(int v) {
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) v = min(v, __shfl_xor(v, o));
-  return v;
+  v = min(v, dpp_mov<0x128>(v));
+  v = min(v, dpp_mov<0x124>(v));
+  v = min(v, dpp_mov<0x122>(v));
+  return min(v, dpp_mov<0x121>(v));
 }
 __device__ __forceinline__ int red16_sum(int v) {
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_mov<0x128>(v);
+  v += dpp_mov<0x124>(v);
+  v += dpp_mov<0x122>(v);
+  return v + dpp_mov<0x121>(v);
+}
+// inclusive prefix sum over the 16 lanes of a row: row_shr by 1, 2, 4, 8, with
+// lanes whose source lies before the row reading 0 (bound_ctrl)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_shr0(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t scan16_incl(uint32_t v) {
+  v += dpp_shr0<0x111>(v);
+  v += dpp_shr0<0x112>(v);
+  v += dpp_shr0<0x114>(v);
+  return v + dpp_shr0<0x118>(v);
 }
 
 enum { P_ENCODE = 0, P_CDF16 = 1, P_CDF32 = 2 };
@@ -759,10 +785,10 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   static_assert(NI == 4 || NI == 1, "NI");
   // node (within the wave) of output group g, row i, and the MFMA row of a node
   auto node_of = [](int g_, int i_) { return NI == 4 ? 4 * g_ + i_ : g_; };
-  __shared__ int32_t lut[256];
+  __shared__ uint16_t lut[256];  // E_j = round(2^15 e^(-j/16)) <= 2^15
   __shared__ int8_t hs[4][16][64];
   __shared__ __attribute__((aligned(16))) uint16_t fs[MODE == P_ENCODE ? 1 : 4][16][256];
-  lut[threadIdx.x] = gp(lut_g)[threadIdx.x];
+  lut[threadIdx.x] = (uint16_t)gp(lut_g)[threadIdx.x];
 
   PredSeg S;
   LayerDev L1, L2;
@@ -858,22 +884,23 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   if (NI == 4) {
     const int ri = r & 3;
     const uint32_t Ssel = ri == 0 ? Sr[0] : (ri == 1 ? Sr[1 % NI] : (ri == 2 ? Sr[2 % NI] : Sr[3 % NI]));
-    const uint32_t invsel = recip32(Ssel);
+    const uint32_t invsel = recip_k(Ssel);
 #pragma unroll
     for (int i = 0; i < NI; i++) inv[i] = (uint32_t)__shfl((int)invsel, (lane & 48) | i);
   } else {
-    inv[0] = recip32(Sr[0]);
+    inv[0] = recip_k(Sr[0]);
   }
 
 #pragma unroll
   for (int i = 0; i < NI; i++) {
     const int nrow = row0 + node_of(g, i);
     const uint32_t S_ = Sr[i];
+    const uint32_t K_ = inv[i] & 0x7FFFFFu;
     int f[16];
     int fsum = 0;
 #pragma unroll
     for (int b = 0; b < 16; b++) {
-      f[b] = (16 * b + r < kNSym) ? 1 + (int)divS((uint32_t)lg[i][b] * 65281u, S_, inv[i]) : 0;
+      f[b] = (16 * b + r < kNSym) ? 1 + (int)div_freq((uint32_t)lg[i][b], S_, K_) : 0;
       fsum += f[b];
     }
     const int R = 65536 - red16_sum(fsum);
@@ -921,13 +948,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
         ex[2 * k + 1] = run;
         run += w[k] >> 16;
       }
-      uint32_t incl = run;
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 16);
-        if (r >= o) incl += v;
-      }
-      const uint32_t off = incl - run;
+      const uint32_t off = scan16_incl(run) - run;
       const int nrow = row0 + prow;
       if (nrow < S.rows) {
         if (MODE == P_CDF16) {
