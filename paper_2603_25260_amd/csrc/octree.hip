@@ -406,6 +406,12 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cb = blockIdx.x;
   const Chunk ch = chunks[cb];
+  // the first round's codes and parent keys are requested before the child
+  // offset of the chunk is summed, so the two memory round trips overlap
+  const int64_t i_first = ch.node0 + threadIdx.x;
+  const bool v_first = (int)threadIdx.x < ch.count && i_first < n;
+  const uint32_t code_first = v_first ? codes[i_first] : 0u;
+  const uint64_t pk_first = v_first ? pkeys[i_first] : 0ull;
   if (sums_are_offsets) {
     if (threadIdx.x == 0) run = csum[cb];
   } else {
@@ -420,7 +426,7 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
   for (int k0 = 0; k0 < ch.count; k0 += 256) {
     const int64_t i = ch.node0 + k0 + threadIdx.x;
     const bool valid = k0 + (int)threadIdx.x < ch.count && i < n;
-    const uint32_t code = valid ? codes[i] : 0u;
+    const uint32_t code = k0 == 0 ? code_first : (valid ? codes[i] : 0u);
     const uint32_t c = __popc(code);
     uint32_t inc = c;
     for (int off = 1; off < 64; off <<= 1) {
@@ -435,7 +441,7 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
     const uint32_t r0 = run;  // first child of this round
     if (valid) {
       cstart[i] = (int32_t)first;
-      const uint64_t pk = pkeys[i];
+      const uint64_t pk = k0 == 0 ? pk_first : pkeys[i];
       uint32_t r = first - r0;
       for (int o = 0; o < 8; o++)
         if ((code >> o) & 1u) kids[r++] = (pk << 3) | (uint64_t)o;

@@ -48,12 +48,15 @@ struct RcEnc {
   uint32_t cache;
   uint32_t pending;
   __device__ __forceinline__ void shift_low(WaveSink& o) {
-    if (low < 0xFF000000ull || low >= 0x100000000ull) {
-      const uint32_t carry = (uint32_t)(low >> 32);
+    // low < 2^33: bits 24..32 hold the carry and the top byte; a byte leaves
+    // unless they read 0x0FF (one 32-bit scalar compare)
+    const uint32_t top = (uint32_t)(low >> 24);
+    if (top != 0xFFu) {
+      const uint32_t carry = top >> 8;
       o.put(cache + carry);
       for (; pending > 1; pending--) o.put(0xFFu + carry);
       pending = 0;
-      cache = (uint32_t)((low >> 24) & 0xFFu);
+      cache = top & 0xFFu;
     }
     pending++;
     low = (low & 0x00FFFFFFull) << 8;
@@ -83,7 +86,8 @@ __global__ __launch_bounds__(64) void k_rc_encode(const Chunk* __restrict__ chun
   const int n = ch.count;
   uint32_t v = lane < n ? p[lane] : 0u;
   for (int base = 0; base < n; base += 64) {
-    const int cnt = min(64, n - base);
+    // wave-uniform trip count kept in a scalar register
+    const int cnt = __builtin_amdgcn_readfirstlane(min(64, n - base));
     const uint32_t vn = base + 64 + lane < n ? p[base + 64 + lane] : 0u;  // next 64 in flight
     for (int k = 0; k < cnt; k++) e.encode((uint32_t)__builtin_amdgcn_readlane((int)v, k), o);
     v = vn;
