@@ -260,8 +260,10 @@ int lpcc_softmax_table(int32_t* out);
  * if none), a_lo the largest a < 0 with q(a) <= -128 (INT32_MIN if none), so
  * no output changes and the shifted product stays below 2^31.  With r = 0 a
  * multiplier above 256 is replaced by 256 (the same function).
- * out[0..3] = {m_pos, m_neg, a_lo, a_hi} as used; host memory, needs no
- * device.  LPCC_E_INVAL for parameters a weight blob may not hold (negative
+ * out[0..4] = {m_pos, m_neg, a_lo, a_hi, rq24} as used, where rq24 = 1 when
+ * a m + 2^(r-1) over the clamped range is an exact 24-bit signed
+ * multiply-add inside int32 (the kernels then skip the 64-bit product); host
+ * memory (5 int32), needs no device.  LPCC_E_INVAL for parameters a weight blob may not hold (negative
  * multipliers, r outside [0, 62], z_out outside int8).
  */
 int lpcc_requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z_out, int32_t* out);

@@ -33,7 +33,7 @@ struct LayerDev {
   int32_t ksteps;       // Kpad / 64
   int32_t npad;
   int32_t a_lo, a_hi;   // accumulator range outside which the output saturates
-  int32_t pad_;
+  int32_t rq24;         // 1: |a| and m below 2^23 and a m + rnd inside int32 on [a_lo, a_hi]
   int64_t rnd;          // 2^(r-1) for r > 0, else 0 (half-up rounding term)
 };
 
@@ -47,6 +47,15 @@ __device__ __forceinline__ int requant_l(int acc, const LayerDev& L) {
   const int a = min(max(acc, L.a_lo), L.a_hi);
   const long long m = a >= 0 ? L.m_pos : L.m_neg;
   const int p = (int)(((long long)a * m + L.rnd) >> L.r);
+  return min(max(p + L.z_out, -128), 127);
+}
+
+// The same function for layers with rq24 set: a 24-bit signed multiply-add
+// gives a m + rnd exactly, so no 64-bit product is needed.
+__device__ __forceinline__ int requant_l24(int acc, const LayerDev& L) {
+  const int a = min(max(acc, L.a_lo), L.a_hi);
+  const int m = a >= 0 ? L.m_pos : L.m_neg;
+  const int p = (__mul24(a, m) + (int)L.rnd) >> L.r;
   return min(max(p + L.z_out, -128), 127);
 }
 
@@ -81,7 +90,7 @@ __device__ __forceinline__ LayerDev load_layer(const LayerDev* p) {
   L.npad = q->npad;
   L.a_lo = q->a_lo;
   L.a_hi = q->a_hi;
-  L.pad_ = q->pad_;
+  L.rq24 = q->rq24;
   L.rnd = q->rnd;
   return L;
 }
@@ -147,7 +156,7 @@ struct PredArg {
   PredSeg seg;
   LayerDev fc1, fc2;
   int32_t one;
-  int32_t pad_;
+  int32_t rq24;  // every segment's logit layer has rq24 set
 };
 
 // Coordinate hash and 3x3x3 neighbour table of one depth j; several depths

@@ -779,7 +779,7 @@ enum { P_ENCODE = 0, P_CDF16 = 1, P_CDF32 = 2 };
 // NI = nodes per group of 16 lanes: 4 (a wave handles 16 nodes) or 1 for
 // small launches (4 nodes per wave at MFMA rows 0, 4, 8, 12: a quarter of the
 // per-lane softmax work, so short launches finish sooner).
-template <int C, int MODE, int NI>
+template <int C, int MODE, int NI, int RQ24>
 __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ segs, const Tile* __restrict__ tiles,
                                                  const int32_t* __restrict__ lut_g, const PredArg A) {
   static_assert(NI == 4 || NI == 1, "NI");
@@ -847,12 +847,12 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   int lg[NI][16];
 #pragma unroll
   for (int b = 0; b < 16; b++) {
-    v4i acc = mfma16(h, w2[b], v4i{0, 0, 0, 0});
-    const int col = 16 * b + r;
-    const int bias = b2[b];
+    const v4i acc = mfma16(h, w2[b], v4i{0, 0, 0, 0});
 #pragma unroll
-    for (int i = 0; i < NI; i++)
-      lg[i][b] = col < kNSym ? requant_l(acc[i] + bias, L2) : -1000;
+    for (int i = 0; i < NI; i++) {
+      const int a = acc[i] + b2[b];
+      lg[i][b] = 16 * b + r < kNSym ? (RQ24 ? requant_l24(a, L2) : requant_l(a, L2)) : -1000;
+    }
   }
 
   // per row: max, lowest argmax, E_i = LUT[M - l_i] (replacing the logits), S
@@ -860,15 +860,14 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   uint32_t Sr[NI];
 #pragma unroll
   for (int i = 0; i < NI; i++) {
-    int M = -1000;
+    // key = 256 l + (255 - index): its maximum holds M and, among the
+    // entries equal to M, the lowest index (padding logits are -1000)
+    int key = -(1 << 30);
 #pragma unroll
-    for (int b = 0; b < 16; b++) M = max(M, lg[i][b]);
-    M = red16_max(M);
-    int am = 1000;
-#pragma unroll
-    for (int b = 0; b < 16; b++)
-      if (lg[i][b] == M) am = min(am, 16 * b + r);
-    arg[i] = red16_min(am);
+    for (int b = 0; b < 16; b++) key = max(key, lg[i][b] * 256 + (255 - 16 * b - r));
+    key = red16_max(key);
+    const int M = key >> 8;
+    arg[i] = 255 - (key & 255);
     int sum = 0;
 #pragma unroll
     for (int b = 0; b < 16; b++) {
@@ -881,6 +880,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   // one reciprocal per lane (lane r computes row r % 4 of its group), shared
   // within the group of 16 lanes
   uint32_t inv[NI];
+  int rem[NI];
   if (NI == 4) {
     const int ri = r & 3;
     const uint32_t Ssel = ri == 0 ? Sr[0] : (ri == 1 ? Sr[1 % NI] : (ri == 2 ? Sr[2 % NI] : Sr[3 % NI]));
@@ -903,10 +903,9 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
       f[b] = (16 * b + r < kNSym) ? 1 + (int)div_freq((uint32_t)lg[i][b], S_, K_) : 0;
       fsum += f[b];
     }
+    // the remainder R goes to entry arg, added once per node below
     const int R = 65536 - red16_sum(fsum);
-#pragma unroll
-    for (int b = 0; b < 16; b++)
-      if (16 * b + r == arg[i]) f[b] += R;
+    rem[i] = R;
 
     if (MODE == P_ENCODE) {
       const int sym = nrow < S.rows ? (int)gp(S.code)[nrow] - 1 : 0;
@@ -917,8 +916,8 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
         st_ += col < sym ? f[b] : 0;
         fr += col == sym ? f[b] : 0;
       }
-      st_ = red16_sum(st_);
-      fr = red16_sum(fr);
+      st_ = red16_sum(st_) + (arg[i] < sym ? R : 0);
+      fr = red16_sum(fr) + (arg[i] == sym ? R : 0);
       if (r == 0 && nrow < S.rows) gp(S.sf)[nrow] = (uint32_t)st_ | ((uint32_t)fr << 16);
     } else {
       // frequencies of the node into LDS for the row-wise prefix below
@@ -927,6 +926,13 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
     }
   }
   if (MODE != P_ENCODE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (r == 0) {
+#pragma unroll
+      for (int i = 0; i < NI; i++) fs[wave][node_of(g, i)][arg[i]] += (uint16_t)rem[i];
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -985,10 +991,14 @@ hipError_t launch_predict(int C, int mode, const PredSeg* segs, const Tile* tile
   const int grid = small ? (A.seg.rows + 15) / 16 : ntiles;
 #define LPCC_P(CC, MM)                                                                                   \
   if (C == CC && mode == MM) {                                                                           \
-    if (small)                                                                                           \
-      hipLaunchKernelGGL((k_predict<CC, MM, 1>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);      \
+    if (small && A.rq24)                                                                                 \
+      hipLaunchKernelGGL((k_predict<CC, MM, 1, 1>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
+    else if (small)                                                                                      \
+      hipLaunchKernelGGL((k_predict<CC, MM, 1, 0>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
+    else if (A.rq24)                                                                                     \
+      hipLaunchKernelGGL((k_predict<CC, MM, 4, 1>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
     else                                                                                                 \
-      hipLaunchKernelGGL((k_predict<CC, MM, 4>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);      \
+      hipLaunchKernelGGL((k_predict<CC, MM, 4, 0>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
     return hipGetLastError();                                                                            \
   }
   LPCC_P(16, 0) LPCC_P(16, 1) LPCC_P(16, 2)

@@ -169,6 +169,19 @@ int64_t requant_q(int64_t a, int64_t m, int r, int z) {
   return ((a * m + rnd) >> r) + z;
 }
 
+// Whether a m + rnd is an exact 24-bit signed multiply-add inside int32 over
+// the clamped range: on each side of 0 either the multiplier is 0 (any
+// truncation of a times 0 is 0) or |a| and m are below 2^23 and a m + rnd
+// stays in [-2^31, 2^31) (rnd >= 0 moves negative products towards 0).
+bool requant_fits24(int32_t m_pos, int32_t m_neg, int32_t a_lo, int32_t a_hi, int64_t rnd) {
+  if (rnd >= (1ll << 30)) return false;
+  const int64_t top = 1ll << 31, lim = 1ll << 23;
+  const bool pos = m_pos == 0 || (m_pos > 0 && m_pos < lim && a_hi < lim && (int64_t)a_hi * m_pos + rnd < top);
+  const bool neg = m_neg == 0 || (m_neg > 0 && m_neg < lim && -(int64_t)a_lo < lim &&
+                                  -(int64_t)a_lo * m_neg - rnd <= top);
+  return pos && neg;
+}
+
 RqBounds requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z) {
   RqBounds B;
   B.m_pos = r == 0 ? std::min<int32_t>(m_pos, 256) : m_pos;
@@ -1026,6 +1039,8 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
   if (nt == 0) return;
   PredArg one;
   memset(&one, 0, sizeof(one));
+  one.rq24 = 1;
+  for (auto& s : segs) one.rq24 &= hlayer(m, s.fc2).rq24;
   size_t so = 0, to = 0;
   if (segs.size() == 1) {
     one.seg = segs[0];
@@ -2109,6 +2124,7 @@ int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out) 
     D.ksteps = im[i].ksteps;
     D.npad = im[i].npad;
     D.rnd = L.r > 0 ? (1ll << (L.r - 1)) : 0;
+    D.rq24 = requant_fits24(D.m_pos, D.m_neg, D.a_lo, D.a_hi, D.rnd) ? 1 : 0;
   }
   int32_t lut[256];
   softmax_table(lut);
@@ -2318,6 +2334,7 @@ int lpcc_requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z_out, int32_t*
   out[1] = B.m_neg;
   out[2] = B.a_lo;
   out[3] = B.a_hi;
+  out[4] = requant_fits24(B.m_pos, B.m_neg, B.a_lo, B.a_hi, r > 0 ? (1ll << (r - 1)) : 0) ? 1 : 0;
   return LPCC_OK;
 }
 

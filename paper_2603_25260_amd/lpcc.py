@@ -124,9 +124,9 @@ def softmax_table() -> np.ndarray:
 
 
 def requant_bounds(m_pos: int, m_neg: int, r: int, z_out: int):
-    """(m_pos, m_neg, a_lo, a_hi) of a requantisation as the kernels use it
-    (host computation)."""
-    out = np.zeros(4, np.int32)
+    """(m_pos, m_neg, a_lo, a_hi, rq24) of a requantisation as the kernels
+    use it (host computation)."""
+    out = np.zeros(5, np.int32)
     _check(lib().lpcc_requant_bounds(m_pos, m_neg, r, z_out, out.ctypes.data))
     return tuple(int(v) for v in out)
 

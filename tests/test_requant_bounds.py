@@ -27,9 +27,32 @@ def lib():
 
 
 def bounds(lib, m_pos, m_neg, r, z):
-    out = np.zeros(4, np.int32)
+    return bounds5(lib, m_pos, m_neg, r, z)[:4]
+
+
+def bounds5(lib, m_pos, m_neg, r, z):
+    out = np.zeros(5, np.int32)
     assert lib.lpcc_requant_bounds(m_pos, m_neg, r, z, out.ctypes.data) == 0
     return [int(v) for v in out]
+
+
+def s24(v):
+    """Low 24 bits of v as a signed value (the operand of a 24-bit multiply)."""
+    v &= (1 << 24) - 1
+    return v - (1 << 24) if v >= (1 << 23) else v
+
+
+def wrap32(v):
+    v &= (1 << 32) - 1
+    return v - (1 << 32) if v >= (1 << 31) else v
+
+
+def form24(acc, mp, mn, a_lo, a_hi, r, z):
+    """The 24-bit form: signed 24-bit multiply-add kept to 32 bits, 32-bit shift."""
+    a = min(max(acc, a_lo), a_hi)
+    m = mp if a >= 0 else mn
+    p = wrap32(s24(a) * s24(m) + ((1 << (r - 1)) if r > 0 else 0)) >> r
+    return min(max(p + z, -128), 127)
 
 
 def kernel_form(acc, mp, mn, a_lo, a_hi, r, z):
@@ -82,3 +105,29 @@ def test_rejects_parameters_outside_the_blob_format(lib):
     out = np.zeros(4, np.int32)
     for args in ((-1, 0, 5, 0), (0, -1, 5, 0), (1, 1, 63, 0), (1, 1, -1, 0), (1, 1, 5, 128), (1, 1, 5, -129)):
         assert lib.lpcc_requant_bounds(*args, out.ctypes.data) == -1
+
+
+@pytest.mark.parametrize("m_pos,m_neg,r,z", param_sets())
+def test_24bit_form_when_flagged(lib, m_pos, m_neg, r, z):
+    """Where the host flags a layer for the 24-bit multiply-add, that form
+    equals the oracle on accumulators across int32, the clamp ends included."""
+    mp, mn, a_lo, a_hi, rq24 = bounds5(lib, m_pos, m_neg, r, z)
+    if not rq24:
+        return
+    rng = np.random.default_rng(m_pos * 5 + m_neg + r * 13 + z + 1000)
+    acc = accumulators(a_lo, a_hi, rng)
+    want = O.requant(acc, m_pos, m_neg, r, z)
+    got = np.array([form24(int(a), mp, mn, a_lo, a_hi, r, z) for a in acc], np.int8)
+    assert np.array_equal(got, want)
+
+
+def test_24bit_flag_on_the_synthetic_logit_layers(lib):
+    """The seeded logit layers (shift 24, C = 16/32/64) take the 24-bit path;
+    a negative output zero point near the int8 edge pushes the product past
+    int32 and keeps the 64-bit one."""
+    for C in (16, 32, 64):
+        m = int(int((1 << 24) / (73.6 * np.sqrt(C))) * 0.75)
+        assert bounds5(lib, m, m, 24, 0)[4] == 1, C
+    m = int(int((1 << 24) / (73.6 * np.sqrt(32))) * 0.75)
+    assert bounds5(lib, m, m, 24, -8)[4] == 0
+    assert bounds5(lib, 1 << 23, 1 << 23, 1, 0)[4] == 0
