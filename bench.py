@@ -420,8 +420,8 @@ def _bench_base(lpcc, torch, model, frames, dxyz, cl, dbs, dout, k0):
 # decode-mode launches of 16 nodes per wave, 612 of 4 nodes per wave and 96
 # encode-mode launches of that run) and the kernel source they were taken on;
 # a changed kernel source reports traffic = null
-PROFILED_MODEL_HIP = "e87f71d5a1ea82e6"
-PREDICT_BYTES_PER_LAUNCH = (340 * (2404.3 + 30761.3) + 612 * (206.3 + 376.0) + 96 * (9196.3 + 966.6)) / 1048 * 1024
+PROFILED_MODEL_HIP = "97428f804563bbc7"
+PREDICT_BYTES_PER_LAUNCH = (340 * (2354.3 + 30761.3) + 612 * (210.1 + 376.0) + 96 * (9157.3 + 966.6)) / 1048 * 1024
 
 
 def _source_hash():
