@@ -11,34 +11,16 @@ namespace lpcc {
 // Encoder: one wave per chunk.  The coder state is wave-uniform (scalar
 // registers); the node values start | freq << 16 are loaded 64 at a time
 // (one per lane, the next 64 in flight) and taken one by one with readlane.
-// Output bytes are packed into 32-bit words; word w of the chunk is kept in
-// lane w % 64 of a vector register and every 64 words are stored at once.
+// Each output byte is one vector byte store that every lane issues with the
+// same address and value (a single memory transaction), so emitting a byte
+// needs no branch and no packing.
 // ---------------------------------------------------------------------------
 struct WaveSink {
-  GAS uint32_t* out;
-  uint32_t pos;   // bytes emitted
-  uint32_t word;  // the word being filled
-  uint32_t ob;    // words of the current group of 64, word w in lane w % 64
-  int lane;
+  GAS uint8_t* out;
+  uint32_t pos;  // bytes emitted
   __device__ __forceinline__ void put(uint32_t b) {
-    word |= (b & 0xFFu) << (8 * (pos & 3u));
-    if ((pos & 3u) == 3u) {
-      const uint32_t wi = pos >> 2;
-      ob = lane == (int)(wi & 63u) ? word : ob;
-      word = 0;
-      if ((wi & 63u) == 63u) out[(wi & ~63u) + (uint32_t)lane] = ob;
-    }
+    out[pos] = (uint8_t)b;
     pos++;
-  }
-  // the last partial word and the group not stored yet: put() stores a group
-  // when its word 63 completes, so words from (complete words & ~63) on are
-  // still in ob
-  __device__ __forceinline__ void finish() {
-    const uint32_t cw = pos >> 2;  // complete words
-    if (pos & 3u) ob = lane == (int)(cw & 63u) ? word : ob;
-    const uint32_t g0 = cw & ~63u;
-    const uint32_t left = ((pos + 3u) >> 2) - g0;  // 0 .. 64
-    if ((uint32_t)lane < left) out[g0 + (uint32_t)lane] = ob;
   }
 };
 
@@ -80,7 +62,7 @@ __global__ __launch_bounds__(64) void k_rc_encode(const Chunk* __restrict__ chun
                                                   uint32_t* __restrict__ lens) {
   const int lane = threadIdx.x;
   const Chunk ch = chunks[blockIdx.x];
-  WaveSink o{(GAS uint32_t*)(scratch + ch.scratch), 0u, 0u, 0u, lane};
+  WaveSink o{(GAS uint8_t*)(scratch + ch.scratch), 0u};
   RcEnc e{0ull, 0xFFFFFFFFu, 0u, 1u};
   const GAS uint32_t* p = gp(sf) + ch.node0;
   const int n = ch.count;
@@ -93,7 +75,6 @@ __global__ __launch_bounds__(64) void k_rc_encode(const Chunk* __restrict__ chun
     v = vn;
   }
   for (int k = 0; k < 5; k++) e.shift_low(o);
-  o.finish();
   if (lane == 0) lens[blockIdx.x] = o.pos;
 }
 
