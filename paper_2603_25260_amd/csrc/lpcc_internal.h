@@ -236,6 +236,20 @@ hipError_t launch_rc_encode(const Chunk* chunks, int nchunks, const uint32_t* sf
                             uint32_t* lens, hipStream_t s);
 hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scratch, const uint32_t* lens,
                           uint8_t* const* dst, hipStream_t s);
+// One frame's stream in device memory: output, capacity, its first chunk,
+// the offset of its chunk-length table and the header size.
+struct PackFrame {
+  uint8_t* out;
+  uint64_t cap;
+  uint32_t first;
+  uint32_t pre;
+  uint64_t hsz;
+};
+// Payloads and 16-bit chunk lengths placed straight into the frames' device
+// outputs (each chunk after the header and its frame's earlier chunks);
+// nothing at or past a frame's capacity is written.
+hipError_t launch_rc_pack_dev(const Chunk* chunks, int nchunks, const int32_t* frame_of, const PackFrame* frames,
+                              const uint8_t* scratch, const uint32_t* lens, hipStream_t s);
 // csum (optional): per chunk, the number of children its decoded codes announce
 hipError_t launch_rc_decode_sized(const Chunk* chunks, int nchunks, const uint8_t* payload, const uint16_t* cdf16,
                                   uint8_t* codes, uint32_t* csum, uint32_t* err, size_t max_len, hipStream_t s);

@@ -102,6 +102,42 @@ hipError_t launch_rc_pack(const Chunk* chunks, int nchunks, const uint8_t* scrat
   return hipGetLastError();
 }
 
+// Placement without a host round trip: block c sums the lengths of its
+// frame's earlier chunks itself (a frame has at most a few thousand), writes
+// its length into the header's table and copies its bytes; every write is
+// checked against the frame's capacity.
+__global__ __launch_bounds__(256) void k_rc_pack_dev(const Chunk* __restrict__ chunks,
+                                                     const int32_t* __restrict__ frame_of,
+                                                     const PackFrame* __restrict__ frames,
+                                                     const uint8_t* __restrict__ scratch,
+                                                     const uint32_t* __restrict__ lens) {
+  __shared__ uint32_t wsum[4];
+  const uint32_t c = blockIdx.x;
+  const PackFrame F = frames[frame_of[c]];
+  const uint32_t n = lens[c];
+  uint32_t part = 0;
+  for (uint32_t k = F.first + threadIdx.x; k < c; k += 256) part += lens[k];
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+  __syncthreads();
+  const uint64_t off = F.hsz + wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  GAS uint8_t* out = gp(F.out);
+  if (threadIdx.x < 2) {
+    const uint64_t p = (uint64_t)F.pre + 2ull * (c - F.first) + threadIdx.x;
+    if (p < F.cap) out[p] = (uint8_t)(n >> (8 * threadIdx.x));
+  }
+  const uint8_t* src = scratch + chunks[c].scratch;
+  for (uint32_t i = threadIdx.x; i < n; i += 256)
+    if (off + i < F.cap) out[off + i] = src[i];
+}
+
+hipError_t launch_rc_pack_dev(const Chunk* chunks, int nchunks, const int32_t* frame_of, const PackFrame* frames,
+                              const uint8_t* scratch, const uint32_t* lens, hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rc_pack_dev, dim3(nchunks), dim3(256), 0, s, chunks, frame_of, frames, scratch, lens);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Decoder: one wave per chunk.  The chunk's bytes are staged in LDS (zero
 // padded: bytes past the end read as 0) and consumed through a dword window.

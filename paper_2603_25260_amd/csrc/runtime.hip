@@ -1435,12 +1435,99 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     c->err = "event creation failed";
     return LPCC_E_DEVICE;
   }
-  if (!probe && !chunks.empty()) {
+  // ---- stream layout: header (fixed part, then one 16-bit length per
+  // chunk), then the payloads in chunk order
+  const size_t nch = chunks.size();
+  std::vector<size_t> nchf(nf, 0), first(nf, 0), hpre(nf, 0);
+  for (size_t k = 0; k < nch; k++) nchf[chunk_frame[k]]++;
+  for (int f = 1; f < nf; f++) first[f] = first[f - 1] + nchf[f - 1];
+  // header of frame f; the chunk lengths are filled in when hl is given
+  auto make_header = [&](int f, const uint32_t* hl) {
+    std::vector<uint8_t> H;
+    const size_t pre = 16 + 4 * (size_t)D + tbytes[f];
+    hpre[f] = pre;
+    H.assign(pre + 2 * nchf[f], 0);
+    H[0] = 'L'; H[1] = 'P'; H[2] = 'C'; H[3] = '1';
+    H[4] = nb > 0 ? 2 : 1; H[5] = (uint8_t)D; H[6] = (uint8_t)m->n_deep; H[7] = (uint8_t)cl;
+    auto w32 = [&](size_t o, uint32_t v) { for (int k = 0; k < 4; k++) H[o + k] = (uint8_t)(v >> (8 * k)); };
+    w32(8, m->blob_id);
+    w32(12, (uint32_t)fr.N[f][D]);
+    for (int d = 0; d < D; d++) w32(16 + 4 * d, (uint32_t)fr.N[f][d]);
+    if (nb > 0) {  // B, then per base depth the (code, count) pairs of its present codes
+      size_t o = 16 + 4 * (size_t)D;
+      H[o++] = (uint8_t)nb;
+      for (int d = 0; d < nb; d++) {
+        const uint32_t* cnt = bhist.data() + ((size_t)f * nb + d) * 256;
+        int mcodes = 0;
+        for (int k = 1; k < 256; k++) mcodes += cnt[k] ? 1 : 0;
+        H[o++] = (uint8_t)mcodes;
+        for (int k = 1; k < 256; k++)
+          if (cnt[k]) {
+            H[o] = (uint8_t)k;
+            w32(o + 1, cnt[k]);
+            o += 5;
+          }
+      }
+    }
+    if (hl)
+      for (size_t k = 0; k < nchf[f]; k++) {
+        H[pre + 2 * k] = (uint8_t)(hl[first[f] + k] & 0xFF);
+        H[pre + 2 * k + 1] = (uint8_t)(hl[first[f] + k] >> 8);
+      }
+    return H;
+  };
+  // Device outputs: the payloads and the length table are placed on the
+  // device right after the coder, and the header's fixed part travels in the
+  // descriptor block, so no host round trip separates coding and placement.
+  bool on_dev = !probe && nch > 0;
+  for (int f = 0; f < nf && on_dev; f++) on_dev = is_device_ptr(os.out[f]);
+  uint32_t* hlens = nullptr;  // chunk lengths in pinned memory (device-output path)
+  std::vector<std::vector<uint8_t>> hdr(nf);
+  if (!probe && nch > 0) {
     const size_t co = b.add(chunks);
-    const int nch = (int)chunks.size();
+    const int n_ch = (int)nch;
     b.launch("rc_encode", dbase[D], [=](const uint8_t* base) {
-      return launch_rc_encode((const Chunk*)(base + co), nch, sf, scratch, lens, st);
+      return launch_rc_encode((const Chunk*)(base + co), n_ch, sf, scratch, lens, st);
     });
+    if (on_dev) {
+      std::vector<PackFrame> pf(nf);
+      std::vector<int32_t> fof(chunk_frame.begin(), chunk_frame.end());
+      std::vector<uint8_t> hblob;
+      std::vector<size_t> hoff(nf, 0);
+      for (int f = 0; f < nf; f++) {
+        hdr[f] = make_header(f, nullptr);
+        pf[f].out = os.out[f];
+        pf[f].cap = (uint64_t)os.cap[f];
+        pf[f].first = (uint32_t)first[f];
+        pf[f].pre = (uint32_t)hpre[f];
+        pf[f].hsz = hdr[f].size();
+        hoff[f] = hblob.size();
+        hblob.insert(hblob.end(), hdr[f].begin(), hdr[f].begin() + hpre[f]);
+        hblob.resize(align_up(hblob.size(), 16), 0);
+      }
+      const size_t fo = b.add(fof), pfo = b.add(pf), ho = b.add(hblob);
+      b.launch("pack", 0, [=](const uint8_t* base) {
+        return launch_rc_pack_dev((const Chunk*)(base + co), n_ch, (const int32_t*)(base + fo),
+                                  (const PackFrame*)(base + pfo), scratch, lens, st);
+      });
+      for (int f = 0; f < nf; f++) {
+        uint8_t* o = os.out[f];
+        const size_t at = ho + hoff[f], n_ = std::min<size_t>(hpre[f], (size_t)os.cap[f]);
+        if (n_ == 0) continue;
+        b.launch("header", 0, [=](const uint8_t* base) {
+          return hipMemcpyAsync(o, base + at, n_, hipMemcpyDeviceToDevice, st);
+        });
+      }
+      // the lengths come back with the same batch, for the totals
+      const size_t lb = align_up(nch * 4, 256);
+      s = reserve_pinned(c, desc_off + align_up(b.bytes.size(), 256) + lb);
+      if (s) return s;
+      hlens = (uint32_t*)(c->pinned + c->pinned_cap - lb);
+      uint32_t* hl_ = hlens;
+      const uint32_t* dl = lens;
+      const size_t nb_ = nch * 4;
+      b.launch("lens", 0, [=](const uint8_t*) { return hipMemcpyAsync(hl_, dl, nb_, hipMemcpyDeviceToHost, st); });
+    }
   }
   s = run_batch(c, b, &desc_off);
   if (s) return s;
@@ -1452,9 +1539,20 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     status[0] = LPCC_OK;
     return LPCC_OK;
   }
+  if (on_dev) {
+    HIPC(hipStreamSynchronize(st));
+    int ret = LPCC_OK;
+    for (int f = 0; f < nf; f++) {
+      size_t total = hdr[f].size();
+      for (size_t k = 0; k < nchf[f]; k++) total += hlens[first[f] + k];
+      os.out_len[f] = total;
+      status[f] = total > os.cap[f] ? LPCC_E_CAPACITY : LPCC_OK;
+      if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
+    }
+    return ret;
+  }
 
-  // ---- stream assembly: lengths -> headers -> payload placement
-  const size_t nch = chunks.size();
+  // ---- host outputs (or none): lengths first, then headers and placement
   std::vector<uint32_t> hl(nch);
   if (nch) {  // through pinned memory, past this call's descriptor blocks
     const size_t lb = align_up(nch * 4, 256);
@@ -1465,66 +1563,25 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     HIPC(hipStreamSynchronize(st));
     memcpy(hl.data(), hp, nch * 4);
   }
-  std::vector<std::vector<uint8_t>> hdr(nf);
   std::vector<size_t> total(nf, 0);
   std::vector<uint8_t*> dst(nch, nullptr);
   std::vector<bool> odev(nf, false);
-  {
-    size_t ci = 0;
-    for (int f = 0; f < nf; f++) {
-      size_t nchf = 0;
-      for (int d = 0; d < D; d++) nchf += (size_t)nchunks_of(fr.N[f][d], cl);
-      std::vector<uint8_t>& H = hdr[f];
-      const size_t pre = 16 + 4 * (size_t)D + tbytes[f];
-      H.assign(pre + 2 * nchf, 0);
-      H[0] = 'L'; H[1] = 'P'; H[2] = 'C'; H[3] = '1';
-      H[4] = nb > 0 ? 2 : 1; H[5] = (uint8_t)D; H[6] = (uint8_t)m->n_deep; H[7] = (uint8_t)cl;
-      auto w32 = [&](size_t o, uint32_t v) { for (int k = 0; k < 4; k++) H[o + k] = (uint8_t)(v >> (8 * k)); };
-      w32(8, m->blob_id);
-      w32(12, (uint32_t)fr.N[f][D]);
-      for (int d = 0; d < D; d++) w32(16 + 4 * d, (uint32_t)fr.N[f][d]);
-      if (nb > 0) {  // B, then per base depth the (code, count) pairs of its present codes
-        size_t o = 16 + 4 * (size_t)D;
-        H[o++] = (uint8_t)nb;
-        for (int d = 0; d < nb; d++) {
-          const uint32_t* cnt = bhist.data() + ((size_t)f * nb + d) * 256;
-          int mcodes = 0;
-          for (int k = 1; k < 256; k++) mcodes += cnt[k] ? 1 : 0;
-          H[o++] = (uint8_t)mcodes;
-          for (int k = 1; k < 256; k++)
-            if (cnt[k]) {
-              H[o] = (uint8_t)k;
-              w32(o + 1, cnt[k]);
-              o += 5;
-            }
-        }
-      }
-      size_t pay = 0;
-      for (size_t k = 0; k < nchf; k++) {
-        H[pre + 2 * k] = (uint8_t)(hl[ci + k] & 0xFF);
-        H[pre + 2 * k + 1] = (uint8_t)(hl[ci + k] >> 8);
-        pay += hl[ci + k];
-      }
-      total[f] = H.size() + pay;
-      os.out_len[f] = total[f];
-      status[f] = total[f] > os.cap[f] ? LPCC_E_CAPACITY : LPCC_OK;
-      odev[f] = is_device_ptr(os.out[f]);
-      ci += nchf;
-    }
+  for (int f = 0; f < nf; f++) {
+    hdr[f] = make_header(f, hl.data());
+    size_t pay = 0;
+    for (size_t k = 0; k < nchf[f]; k++) pay += hl[first[f] + k];
+    total[f] = hdr[f].size() + pay;
+    os.out_len[f] = total[f];
+    status[f] = total[f] > os.cap[f] ? LPCC_E_CAPACITY : LPCC_OK;
+    odev[f] = is_device_ptr(os.out[f]);
   }
-  {
-    size_t ci = 0;
-    for (int f = 0; f < nf; f++) {
-      size_t nchf = 0;
-      for (int d = 0; d < D; d++) nchf += (size_t)nchunks_of(fr.N[f][d], cl);
-      const bool direct = status[f] == LPCC_OK && odev[f];
-      uint8_t* base = direct ? os.out[f] : stage + stage_off[f];
-      size_t o = hdr[f].size();
-      for (size_t k = 0; k < nchf; k++) {
-        dst[ci + k] = base + o;
-        o += hl[ci + k];
-      }
-      ci += nchf;
+  for (int f = 0; f < nf; f++) {
+    const bool direct = status[f] == LPCC_OK && odev[f];
+    uint8_t* base = direct ? os.out[f] : stage + stage_off[f];
+    size_t o = hdr[f].size();
+    for (size_t k = 0; k < nchf[f]; k++) {
+      dst[first[f] + k] = base + o;
+      o += hl[first[f] + k];
     }
   }
   // payload placement and the headers of device outputs in one batch: the
@@ -1563,9 +1620,7 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   }
   for (int f = 0; f < nf; f++) {
     if (status[f] != LPCC_OK) continue;
-    if (odev[f]) {
-      // written by the batch above
-    } else {
+    if (!odev[f]) {
       memcpy(os.out[f], hdr[f].data(), hdr[f].size());
       if (total[f] > hdr[f].size())
         HIPC(hipMemcpyAsync(os.out[f] + hdr[f].size(), stage + stage_off[f] + hdr[f].size(),

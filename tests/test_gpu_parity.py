@@ -151,16 +151,53 @@ def test_device_resident_buffers(L, ctx):
     xyz = synth.make_scan(cfg.scan, cfg.seeds[1])
     want = O.encode(blob, xyz, 8)
     dx = torch.from_numpy(xyz).cuda()
-    out = torch.zeros(len(want) + 100, dtype=torch.uint8, device="cuda")
+    out = torch.full((len(want) + 100,), 0x5A, dtype=torch.uint8, device="cuda")
     n = L.encode_frame(ctx, m, dx, 8, out=out)
     assert n == len(want)
     assert out[:n].cpu().numpy().tobytes() == want
+    assert bool((out[n:] == 0x5A).all())  # nothing written past the stream
     dec = torch.zeros((len(xyz), 3), dtype=torch.int32, device="cuda")
     k = L.decode_frame(ctx, m, out, length=n, out=dec)
     assert np.array_equal(dec[:k].cpu().numpy(), sorted_unique(xyz, cfg.scan.D))
     cdf = torch.zeros((20000, 256), dtype=torch.int32, device="cuda")
     nn = L.level_probs(ctx, m, dx, 9, out=cdf)
     assert np.array_equal(cdf[:nn].cpu().numpy(), O.level_probs(blob, xyz, 9))
+
+
+def test_device_output_capacity(L, ctx):
+    """A device output shorter than the stream: LPCC_E_CAPACITY, and no byte
+    at or past the given capacity is written; an exact one holds the stream."""
+    cfg = synth.CONFIGS["cfg1"]
+    blob, m = model(L, cfg.weight_seed, cfg.C, cfg.scan.D, cfg.n_deep)
+    xyz = synth.make_scan(cfg.scan, cfg.seeds[2])
+    want = O.encode(blob, xyz, 8)
+    dx = torch.from_numpy(xyz).cuda()
+    for cap in (len(want) - 1, len(want) // 2, 20):
+        big = torch.full((len(want) + 64,), 0xC3, dtype=torch.uint8, device="cuda")
+        with pytest.raises(L.LpccError) as e:
+            L.encode_frame(ctx, m, dx, 8, out=big[:cap])
+        assert e.value.code == L.E_CAPACITY
+        assert bool((big[cap:] == 0xC3).all()), cap
+    exact = torch.zeros(len(want), dtype=torch.uint8, device="cuda")
+    assert L.encode_frame(ctx, m, dx, 8, out=exact) == len(want)
+    assert exact.cpu().numpy().tobytes() == want
+
+
+def test_batch_device_outputs(L, ctx):
+    """Several frames into device outputs in one call (payloads placed on the
+    device): every stream equals the oracle's, including empty frames."""
+    D, C, nd = 9, 32, 3
+    blob, m = model(L, 11, C, D, nd)
+    frames = [synth.random_cloud(n, D, 300 + i) for i, n in enumerate([700, 0, 5, 2500, 64])]
+    want = [O.encode(blob, x, 7) for x in frames]
+    outs = [torch.full((len(w) + 32,), 0x77, dtype=torch.uint8, device="cuda") for w in want]
+    got, st = L.encode_batch(ctx, m, [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in frames], 7,
+                             outs=outs)
+    assert st == [0] * len(frames)
+    for f, w in enumerate(want):
+        assert got[f] == len(w), f
+        assert outs[f][:len(w)].cpu().numpy().tobytes() == w, f
+        assert bool((outs[f][len(w):] == 0x77).all()), f
 
 
 def test_batch_equals_per_frame(L, ctx):
