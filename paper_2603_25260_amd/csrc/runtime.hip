@@ -333,6 +333,7 @@ struct lpcc_ctx {
   };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> ev_free;
+  hipEvent_t poll_ev = nullptr;  // stream_wait's event
   int tiling = 0;
   // graph mode: every launch batch of a call is captured into a HIP graph and
   // replayed; the executable graph of each (call kind, batch) slot is kept and
@@ -877,6 +878,22 @@ void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames&
 }
 
 // Cross-stream ordering inside a launch batch
+// Waits for the work enqueued on s by polling an event instead of the
+// runtime's blocking wait, so the calling thread keeps its core and the host
+// code after the wait does not start on a core woken from sleep.
+hipError_t stream_wait(lpcc_ctx* c, hipStream_t s) {
+  if (!c->poll_ev && hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    c->poll_ev = nullptr;
+    return hipStreamSynchronize(s);
+  }
+  hipError_t e = hipEventRecord(c->poll_ev, s);
+  if (e != hipSuccess) return e;
+  while ((e = hipEventQuery(c->poll_ev)) == hipErrorNotReady) {
+  }
+  return e;
+}
+
 hipEvent_t sync_event(lpcc_ctx* c) {
   if (c->sync_used == c->sync_ev.size()) {
     hipEvent_t e = nullptr;
@@ -1183,7 +1200,7 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
   HIPC(hipMemcpyAsync(h + (D + 1) * (nf + 1), err, (size_t)nf * 4, hipMemcpyDeviceToHost, st));
   if (nbh && ntot > 0)
     HIPC(hipMemcpyAsync(h + (D + 1) * (nf + 1) + nf, bhist, nbh * 4, hipMemcpyDeviceToHost, st));
-  HIPC(hipStreamSynchronize(st));
+  HIPC(stream_wait(c, st));
   if (base_hist) {
     base_hist->assign(nbh, 0u);
     if (nbh && ntot > 0) memcpy(base_hist->data(), h + (D + 1) * (nf + 1) + nf, nbh * 4);
@@ -1535,12 +1552,12 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   if (probe) {
     if (!cdf_dev && fr.tot[probe_level] > 0)
       HIPC(hipMemcpyAsync(cdf_out, cdf_stage, (size_t)fr.tot[probe_level] * 1024, hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
+    HIPC(stream_wait(c, st));
     status[0] = LPCC_OK;
     return LPCC_OK;
   }
   if (on_dev) {
-    HIPC(hipStreamSynchronize(st));
+    HIPC(stream_wait(c, st));
     int ret = LPCC_OK;
     for (int f = 0; f < nf; f++) {
       size_t total = hdr[f].size();
@@ -1560,7 +1577,7 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     if (s) return s;
     uint32_t* hp = (uint32_t*)(c->pinned + c->pinned_cap - lb);
     HIPC(hipMemcpyAsync(hp, lens, nch * 4, hipMemcpyDeviceToHost, st));
-    HIPC(hipStreamSynchronize(st));
+    HIPC(stream_wait(c, st));
     memcpy(hl.data(), hp, nch * 4);
   }
   std::vector<size_t> total(nf, 0);
@@ -1627,7 +1644,7 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
                             total[f] - hdr[f].size(), hipMemcpyDeviceToHost, st));
     }
   }
-  HIPC(hipStreamSynchronize(st));
+  HIPC(stream_wait(c, st));
   int ret = LPCC_OK;
   for (int f = 0; f < nf; f++)
     if (status[f] != LPCC_OK && ret == LPCC_OK) ret = status[f];
@@ -1753,7 +1770,7 @@ int read_headers(lpcc_ctx* c, int nf, const uint8_t* const* bs, const size_t* le
   if (s) return s;
   for (int f = 0; f < nf; f++)
     if (dev[f] && got[f]) HIPC(hipMemcpyAsync(c->pinned + off[f], bs[f], got[f], hipMemcpyDeviceToHost, c->stream));
-  HIPC(hipStreamSynchronize(c->stream));
+  HIPC(stream_wait(c, c->stream));
   std::vector<int> more;
   std::vector<size_t> want(nf, 0);
   size_t need2 = 0;
@@ -1781,7 +1798,7 @@ int read_headers(lpcc_ctx* c, int nf, const uint8_t* const* bs, const size_t* le
     HIPC(hipMemcpyAsync(c->pinned + o, bs[f], want[f], hipMemcpyDeviceToHost, c->stream));
     o += align_up(want[f], 64);
   }
-  HIPC(hipStreamSynchronize(c->stream));
+  HIPC(stream_wait(c, c->stream));
   for (int f : more) {
     st[f] = parse_header(c->pinned + off[f], want[f], len[f], H[f], true);
     if (st[f] == LPCC_E_CAPACITY) st[f] = LPCC_E_CORRUPT;  // the bound held the whole header
@@ -2098,7 +2115,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   if (s) return s;
   uint32_t* herr = (uint32_t*)(c->pinned + c->pinned_cap - 256);
   HIPC(hipMemcpyAsync(herr, err, 16, hipMemcpyDeviceToHost, st));
-  HIPC(hipStreamSynchronize(st));
+  HIPC(stream_wait(c, st));
   if (herr[0] | herr[1]) {
     // a corrupt frame misaligns the shared arrays: report per frame by
     // decoding the frames one at a time
@@ -2244,6 +2261,7 @@ void lpcc_ctx_free(lpcc_ctx* c) {
   for (auto e : c->ev_free) (void)hipEventDestroy(e);
   for (auto& kv : c->gexec) (void)hipGraphExecDestroy(kv.second);
   for (auto e : c->sync_ev) (void)hipEventDestroy(e);
+  if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
   if (c->side) (void)hipStreamDestroy(c->side);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   delete c;
