@@ -2091,6 +2091,17 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       wait(st, resblock);  // the ResBlock output (not the neighbour table)
       plan_shallow_up(b, m, lv, fr, B, t, st);
     }
+    // From the first large depth on the GPU is the bottleneck: submit what
+    // is planned, so that planning the remaining depths overlaps its work
+    // (every later launch uses descriptors added after this point)
+    if (d == dsplit && d + 1 < D && d + 1 >= nb && !c->graphs) {
+      if (!ok_ev) {
+        c->err = "event creation failed";
+        return LPCC_E_DEVICE;
+      }
+      s = run_batch(c, b, &desc_off);
+      if (s) return s;
+    }
   }
   if (two && dsplit < D) {  // the main stream waits for the side stream's last work
     two_now = true;
