@@ -233,7 +233,6 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   uint32_t range = 0xFFFFFFFFu;
 
   uint32_t kids = 0;  // children announced by the codes this lane stored
-  const uint32_t lane4p1 = 4u * (uint32_t)lane + 1u;
   // high half of b_3 for the compare: lane 63's b_3 = cdf[255] is stored as 0
   // and compares as 2^16
   const uint32_t b3hi = lane == 63 ? 1u : 0u;
@@ -257,8 +256,6 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
     uint32_t q = m1 ? q1 : x;
     q = m2 ? y : q;
     q = m3 ? q3 : q;
-    // code (symbol + 1) of this lane's candidate: 4 lane + 1 + entries passed
-    const uint32_t cand = lane4p1 + (uint32_t)m1 + (uint32_t)m2 + (uint32_t)m3;
     const int L = (int)__popcll(__ballot(m0)) - 1;
     const uint32_t Q = (uint32_t)__builtin_amdgcn_readlane((int)q, L);
     const uint32_t lo = Q & 0xFFFFu;
@@ -274,15 +271,34 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
     bb <<= sh;
     nbit -= sh;
     range <<= sh;
-    const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cand, L);
-    cv = lane == k ? c1 : cv;
+    // the symbol is resolved later from (lo, owning lane): lane k keeps them
+    const uint32_t pk = lo | ((uint32_t)L << 16);
+    cv = lane == k ? pk : cv;
   };
   // one block of up to kDecBlock symbols from the rows in t (fully unrolled:
   // row k is register t[k]); then t is reloaded with the block two ahead.
   // A symbol takes at most 2 bytes: 4 buffered bytes cover a pair.
+  // Symbols of a block are resolved one block later: lane k holds (lo, L) of
+  // symbol k, reads its node's entries b_0..b_3 of lane L (the read is issued
+  // at the end of the block and used at the end of the next one) and finds
+  // j with b_j = lo (the entries of a row are distinct; cdf[255] is stored as
+  // 0 but is never a lower boundary of a valid symbol): code = 4 L + j + 1.
+  uint32_t pend_pk = 0;
+  uint2 pend_e = make_uint2(0u, 0u);
+  int pend_base = 0, pend_cnt = 0;  // pend_cnt = 0: nothing pending
+  auto resolve = [&]() {
+    if (pend_cnt > 0 && lane < pend_cnt) {
+      const uint32_t lo = pend_pk & 0xFFFFu, L = pend_pk >> 16;
+      const uint32_t j = lo == (pend_e.x >> 16) ? 1u : (lo == (pend_e.y & 0xFFFFu) ? 2u : (lo == (pend_e.y >> 16) ? 3u : 0u));
+      const uint32_t cv = 4u * L + j + 1u;
+      codes[node0 + pend_base + lane] = (uint8_t)cv;
+      kids += __popc(cv & 0xFFu);
+    }
+    pend_cnt = 0;
+  };
   auto block = [&](uint2 (&t)[kDecBlock], int base) {
     const int cnt = min(kDecBlock, n - base);
-    uint32_t cv = 0;  // decoded code k of this block in lane k
+    uint32_t cv = 0;  // (lo, owning lane) of symbol k of this block in lane k
 #pragma unroll
     for (int k = 0; k < kDecBlock; k++) {
       if (k < cnt) {
@@ -291,9 +307,13 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
       }
     }
     bad = range == 0u;
-    if (!bad && lane < cnt) {
-      codes[node0 + base + lane] = (uint8_t)cv;
-      kids += __popc(cv & 0xFFu);
+    resolve();  // the previous block (decoded before any corruption here)
+    if (!bad) {
+      pend_pk = cv;
+      pend_base = base;
+      pend_cnt = cnt;
+      const int64_t node = node0 + base + min(lane, cnt - 1);
+      pend_e = *(const uint2*)(cdf16 + node * 256 + 4 * (cv >> 16 & 63u));
     }
     const int nbk = base + 2 * kDecBlock;
 #pragma unroll
@@ -303,6 +323,7 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
     block(ta, base);
     if (base + kDecBlock < n && !bad) block(tb, base + kDecBlock);
   }
+  resolve();
   if (bad && lane == 0) atomicOr(err, ERR_CORRUPT);
   if (csum != nullptr) {
     for (int off = 32; off > 0; off >>= 1) kids += __shfl_xor(kids, off);
