@@ -68,7 +68,7 @@ __device__ __forceinline__ int dstar(const uint64_t* keys, int64_t i, int D) {
 
 constexpr int kLevelThreads = 256;
 
-// hist[tile][v] = #elements of the tile with d* = v (v = 0..D)
+// hist[tile][v] = #elements of the tile with d* <= v (v = 0..D)
 __global__ void k_level_hist(const uint64_t* __restrict__ keys, int64_t n, int D, int tile,
                              uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[kMaxD + 2];
@@ -80,7 +80,12 @@ __global__ void k_level_hist(const uint64_t* __restrict__ keys, int64_t n, int D
     if (i < n) atomicAdd(&h[dstar(keys, i, D)], 1u);
   }
   __syncthreads();
-  for (int v = threadIdx.x; v <= D; v += blockDim.x) hist[(int64_t)blockIdx.x * (D + 1) + v] = h[v];
+  // cumulative over depth: hist[tile][d] = #elements of the tile with d* <= d
+  for (int v = threadIdx.x; v <= D; v += blockDim.x) {
+    uint32_t c = 0;
+    for (int u = 0; u <= v; u++) c += h[u];
+    hist[(int64_t)blockIdx.x * (D + 1) + v] = c;
+  }
 }
 
 hipError_t launch_level_hist(const uint64_t* keys, int64_t n, int D, int tile, uint32_t* hist, hipStream_t s) {
@@ -91,47 +96,43 @@ hipError_t launch_level_hist(const uint64_t* keys, int64_t n, int D, int tile, u
 }
 
 // In place: hist[t][d] <- #elements of tiles < t with d* <= d (exclusive over
-// tiles, cumulative over depth).  totals[d] = N_d.  One block: every thread
+// tiles; the histogram is already cumulative over depth).  totals[d] = N_d.
+// One block per depth, so the depths are scanned side by side: every thread
 // sums a run of tiles, a block-wide exclusive scan (wave shuffles, then the
-// four wave totals) gives each run its offsets, the runs are rewritten.
+// four wave totals) gives each run its offset, the run is rewritten.
 __global__ __launch_bounds__(kLevelThreads) void k_level_scan(uint32_t* __restrict__ hist, int nb, int D,
                                                              uint32_t* __restrict__ totals) {
-  __shared__ uint32_t wsum[kLevelThreads / 64][kMaxD + 1];
+  __shared__ uint32_t wsum[kLevelThreads / 64];
+  const int d = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int per = (nb + kLevelThreads - 1) / kLevelThreads;
   const int t0 = tid * per, t1 = min(nb, t0 + per);
-  uint32_t run[kMaxD + 1];
-  for (int d = 0; d <= D; d++) run[d] = 0;
-  for (int t = t0; t < t1; t++) {
-    uint32_t c = 0;
-    for (int d = 0; d <= D; d++) { c += hist[(int64_t)t * (D + 1) + d]; run[d] += c; }
+  uint32_t run = 0;
+  for (int t = t0; t < t1; t++) run += hist[(int64_t)t * (D + 1) + d];
+  uint32_t inc = run;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t v = __shfl_up(inc, off);
+    if (lane >= off) inc += v;
   }
-  for (int d = 0; d <= D; d++) {
-    uint32_t inc = run[d];
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t v = __shfl_up(inc, off);
-      if (lane >= off) inc += v;
-    }
-    if (lane == 63) wsum[wave][d] = inc;
-    run[d] = inc - run[d];  // exclusive within the wave
-  }
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
-  for (int d = 0; d <= D; d++)
-    for (int w = 0; w < wave; w++) run[d] += wsum[w][d];
-  if (tid <= D) {
+  uint32_t ex = inc - run;
+  for (int w = 0; w < wave; w++) ex += wsum[w];
+  if (tid == 0) {
     uint32_t tot = 0;
-    for (int w = 0; w < kLevelThreads / 64; w++) tot += wsum[w][tid];
-    totals[tid] = tot;
+    for (int w = 0; w < kLevelThreads / 64; w++) tot += wsum[w];
+    totals[d] = tot;
   }
   for (int t = t0; t < t1; t++) {
-    uint32_t c = 0, inc[kMaxD + 1];
-    for (int d = 0; d <= D; d++) { c += hist[(int64_t)t * (D + 1) + d]; inc[d] = c; }
-    for (int d = 0; d <= D; d++) { hist[(int64_t)t * (D + 1) + d] = run[d]; run[d] += inc[d]; }
+    const int64_t o = (int64_t)t * (D + 1) + d;
+    const uint32_t v = hist[o];
+    hist[o] = ex;
+    ex += v;
   }
 }
 
 hipError_t launch_level_scan(uint32_t* hist, int nb, int D, uint32_t* totals, hipStream_t s) {
-  hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(kLevelThreads), 0, s, hist, nb, D, totals);
+  hipLaunchKernelGGL(k_level_scan, dim3(D + 1), dim3(kLevelThreads), 0, s, hist, nb, D, totals);
   return hipGetLastError();
 }
 
