@@ -1934,12 +1934,17 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   carve(A);
   size_t desc_off = 0;
 
-  // payloads and roots
-  for (int f : live) {
-    const size_t pl = H[f].total - H[f].hdr;
-    if (!pl) continue;
-    HIPC(hipMemcpyAsync(payload + payoff[f], bs[f] + H[f].hdr, pl,
-                        is_device_ptr(bs[f]) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  // payloads and roots: one device-resident stream is read in place (its
+  // chunk offsets already start at 0), others are gathered into one buffer
+  if (live.size() == 1 && is_device_ptr(bs[live[0]])) {
+    payload = const_cast<uint8_t*>(bs[live[0]]) + H[live[0]].hdr;
+  } else {
+    for (int f : live) {
+      const size_t pl = H[f].total - H[f].hdr;
+      if (!pl) continue;
+      HIPC(hipMemcpyAsync(payload + payoff[f], bs[f] + H[f].hdr, pl,
+                          is_device_ptr(bs[f]) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    }
   }
   // V_0: one root per live frame; its key is the frame's position tag
   HIPC(launch_iota_u64(lv.key[0], (int64_t)live.size(), st));
