@@ -1301,6 +1301,11 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   std::vector<int> chunk_frame;
   int64_t scratch_bytes = 0;
   if (!probe) {
+    size_t nch_all = 0;
+    for (int f = 0; f < nf; f++)
+      for (int d = 0; d < D; d++) nch_all += (size_t)nchunks_of(fr.N[f][d], cl);
+    chunks.reserve(nch_all);
+    chunk_frame.reserve(nch_all);
     for (int f = 0; f < nf; f++)
       for (int d = 0; d < D; d++) {
         const int64_t Nfd = fr.N[f][d];
