@@ -200,6 +200,28 @@ def test_batch_device_outputs(L, ctx):
         assert bool((outs[f][len(w):] == 0x77).all()), f
 
 
+def test_batch_device_outputs_one_too_small(L, ctx):
+    """One frame's device output is too short: that frame reports
+    LPCC_E_CAPACITY with its required size and nothing at or past its
+    capacity is written; the other frames' streams are complete."""
+    D, C, nd = 9, 32, 3
+    blob, m = model(L, 11, C, D, nd)
+    frames = [synth.random_cloud(n, D, 400 + i) for i, n in enumerate([900, 300, 1500])]
+    want = [O.encode(blob, x, 7) for x in frames]
+    caps = [len(want[0]) + 8, len(want[1]) // 2, len(want[2])]
+    bigs = [torch.full((c + 64,), 0x3C, dtype=torch.uint8, device="cuda") for c in caps]
+    outs = [b[:c] for b, c in zip(bigs, caps)]
+    got, st = L.encode_batch(ctx, m, [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in frames], 7,
+                             outs=outs)
+    assert st == [0, L.E_CAPACITY, 0]
+    assert got[1] == len(want[1])  # the required size
+    for f in (0, 2):
+        assert got[f] == len(want[f])
+        assert bigs[f][:len(want[f])].cpu().numpy().tobytes() == want[f], f
+    for f in range(3):
+        assert bool((bigs[f][caps[f]:] == 0x3C).all()), f
+
+
 def test_batch_equals_per_frame(L, ctx):
     D, C, nd = 9, 32, 3
     blob, m = model(L, 11, C, D, nd)
