@@ -144,6 +144,12 @@ __global__ void k_level_write(const uint64_t* __restrict__ keys, int64_t n, int 
                               const uint32_t* __restrict__ offs, LevelOut lo) {
   __shared__ uint32_t wtot[4][kMaxD + 1];
   __shared__ uint32_t run[kMaxD + 1];
+  // occupancy words of the round's parents, combined here before one global
+  // OR per word: the parents of a round's 256 elements at depth d-1 span at
+  // most 256 consecutive nodes, i.e. at most 65 words from word wb[d]
+  constexpr int kCW = 66;
+  __shared__ uint32_t cw[kMaxD + 1][kCW];
+  __shared__ uint32_t wb[kMaxD + 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   if (threadIdx.x <= D) run[threadIdx.x] = offs[(int64_t)blockIdx.x * (D + 1) + threadIdx.x];
@@ -160,15 +166,22 @@ __global__ void k_level_write(const uint64_t* __restrict__ keys, int64_t n, int 
       excl[d] = __popcll(m & lt);
       if (lane == 0) wtot[wave][d] = __popcll(m);
     }
+    for (int k = threadIdx.x; k < (D + 1) * kCW; k += blockDim.x) cw[k / kCW][k % kCW] = 0;
     __syncthreads();
+    uint32_t node[kMaxD + 1];
     if (valid) {
-      uint32_t node[kMaxD + 1];
       for (int d = 0; d <= D; d++) {
         uint32_t before = run[d];
         for (int w = 0; w < wave; w++) before += wtot[w][d];
         // index of the depth-d node holding element i
         node[d] = before + excl[d] + (ds <= d ? 1u : 0u) - 1u;
       }
+      // the round's first element holds the lowest parent of every depth
+      if (threadIdx.x == 0)
+        for (int d = 1; d <= D; d++) wb[d] = node[d - 1] >> 2;
+    }
+    __syncthreads();
+    if (valid) {
       if (ds == 0) {  // first element of a frame: record its node per depth
         const uint64_t f = (3 * D >= 64) ? 0 : (key >> (3 * D));
         for (int d = 0; d <= D; d++) lo.frame_off[f * (D + 1) + d] = node[d];
@@ -180,9 +193,17 @@ __global__ void k_level_write(const uint64_t* __restrict__ keys, int64_t n, int 
         if (d >= 1) {
           uint32_t slot = (uint32_t)((key >> (3 * (D - d))) & 7u);
           uint32_t p = node[d - 1];
-          atomicOr((uint32_t*)(lo.code[d - 1] + (p & ~3u)), (1u << slot) << (8 * (p & 3u)));
+          atomicOr(&cw[d][(p >> 2) - wb[d]], (1u << slot) << (8 * (p & 3u)));
         }
       }
+    }
+    __syncthreads();
+    // one global OR per touched word (words at the round's edges may be
+    // shared with the neighbouring rounds and blocks)
+    for (int k = threadIdx.x; k < D * kCW; k += blockDim.x) {
+      const int d = 1 + k / kCW, w = k % kCW;
+      const uint32_t v = cw[d][w];
+      if (v) atomicOr((uint32_t*)(lo.code[d - 1]) + wb[d] + w, v);
     }
     __syncthreads();
     if (threadIdx.x <= D) {
