@@ -201,9 +201,9 @@ struct LevelOut {
   int32_t* cstart[kMaxD + 1];
   uint32_t* frame_off;  // [frames][D+1]: first node of every frame per depth
 };
+// (also writes the sentinel cstart[d][N_d] = N_{d+1} of every depth)
 hipError_t launch_level_write(const uint64_t* keys, int64_t n, int D, int tile, const uint32_t* hist,
-                              const LevelOut& lo, hipStream_t s);
-hipError_t launch_sentinels(const LevelOut& lo, const uint32_t* totals, int D, hipStream_t s);
+                              const uint32_t* totals, const LevelOut& lo, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_iota_u64(uint64_t* p, int64_t n, hipStream_t s);  // p[i] = i

@@ -141,7 +141,8 @@ hipError_t launch_level_scan(uint32_t* hist, int nb, int D, uint32_t* totals, hi
 // byte) and the first-child index of every node.  Tiles hold `tile`
 // elements, processed in rounds of 256 in order.
 __global__ void k_level_write(const uint64_t* __restrict__ keys, int64_t n, int D, int tile,
-                              const uint32_t* __restrict__ offs, LevelOut lo) {
+                              const uint32_t* __restrict__ offs, const uint32_t* __restrict__ totals,
+                              LevelOut lo) {
   __shared__ uint32_t wtot[4][kMaxD + 1];
   __shared__ uint32_t run[kMaxD + 1];
   // occupancy words of the round's parents, combined here before one global
@@ -153,6 +154,13 @@ __global__ void k_level_write(const uint64_t* __restrict__ keys, int64_t n, int 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
   if (threadIdx.x <= D) run[threadIdx.x] = offs[(int64_t)blockIdx.x * (D + 1) + threadIdx.x];
+  // cstart[d][N_d] = N_{d+1}: the sentinel after the last node of every depth
+  if (blockIdx.x == 0 && threadIdx.x < D) {
+    const uint32_t nd = totals[threadIdx.x], nd1 = totals[threadIdx.x + 1];
+#pragma unroll
+    for (int d = 0; d < kMaxD; d++)  // constant indices into the pointer table
+      if (d == (int)threadIdx.x) lo.cstart[d][nd] = (int32_t)nd1;
+  }
   __syncthreads();
   int64_t base = (int64_t)blockIdx.x * tile;
   for (int k0 = 0; k0 < tile; k0 += blockDim.x) {
@@ -216,21 +224,11 @@ __global__ void k_level_write(const uint64_t* __restrict__ keys, int64_t n, int 
 }
 
 hipError_t launch_level_write(const uint64_t* keys, int64_t n, int D, int tile, const uint32_t* hist,
-                              const LevelOut& lo, hipStream_t s) {
+                              const uint32_t* totals, const LevelOut& lo, hipStream_t s) {
   int64_t nb = (n + tile - 1) / tile;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_level_write, dim3((unsigned)nb), dim3(kLevelThreads), 0, s, keys, n, D, tile, hist, lo);
-  return hipGetLastError();
-}
-
-// cstart[d][N_d] = N_{d+1}: sentinel after the last node of every depth
-__global__ void k_sentinels(LevelOut lo, const uint32_t* __restrict__ totals, int D) {
-  int d = threadIdx.x;
-  if (d < D) lo.cstart[d][totals[d]] = (int32_t)totals[d + 1];
-}
-
-hipError_t launch_sentinels(const LevelOut& lo, const uint32_t* totals, int D, hipStream_t s) {
-  hipLaunchKernelGGL(k_sentinels, dim3(1), dim3(64), 0, s, lo, totals, D);
+  hipLaunchKernelGGL(k_level_write, dim3((unsigned)nb), dim3(kLevelThreads), 0, s, keys, n, D, tile, hist, totals,
+                     lo);
   return hipGetLastError();
 }
 

@@ -1170,8 +1170,7 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
       lo.cstart[d] = lv.cstart[d];
     }
     lo.frame_off = foff;
-    HIPC(launch_level_write(kout, ntot, D, tile, hist, lo, st));
-    HIPC(launch_sentinels(lo, totals, D, st));
+    HIPC(launch_level_write(kout, ntot, D, tile, hist, totals, lo, st));
     if (nbh) {
       // code counts per (frame, base depth); the node counts are still on
       // the device, so the range covers the upper bounds and the kernel
