@@ -1189,33 +1189,36 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
       HIPC(launch_base_hist(bl, bhist, st));
     }
   }
-  // read back counts, frame offsets, errors (and the base depths' code counts)
-  const size_t rb = (size_t)(D + 1 + nf * (D + 1) + nf) * 4 + nbh * 4;
-  s = reserve_pinned(c, *desc_off + rb + 256);
+  // read back frame offsets, errors, counts (and the base depths' code
+  // counts) in one copy: they were carved one after another
+  const bool with_bh = nbh && ntot > 0;
+  const char* rb0 = (const char*)foff;
+  const char* rb1 = with_bh ? (const char*)(bhist + nbh) : (const char*)(totals + D + 1);
+  const size_t rb = (size_t)(rb1 - rb0);
+  s = reserve_pinned(c, *desc_off + align_up(rb, 256) + 256);
   if (s) return s;
-  uint32_t* h = (uint32_t*)(c->pinned + c->pinned_cap - align_up(rb, 256));
-  HIPC(hipMemcpyAsync(h, totals, (D + 1) * 4, hipMemcpyDeviceToHost, st));
-  HIPC(hipMemcpyAsync(h + D + 1, foff, (size_t)nf * (D + 1) * 4, hipMemcpyDeviceToHost, st));
-  HIPC(hipMemcpyAsync(h + (D + 1) * (nf + 1), err, (size_t)nf * 4, hipMemcpyDeviceToHost, st));
-  if (nbh && ntot > 0)
-    HIPC(hipMemcpyAsync(h + (D + 1) * (nf + 1) + nf, bhist, nbh * 4, hipMemcpyDeviceToHost, st));
+  char* h8 = (char*)(c->pinned + c->pinned_cap - align_up(rb, 256));
+  HIPC(hipMemcpyAsync(h8, rb0, rb, hipMemcpyDeviceToHost, st));
   HIPC(stream_wait(c, st));
+  const uint32_t* h_foff = (const uint32_t*)h8;
+  const uint32_t* h_err = (const uint32_t*)(h8 + ((const char*)err - rb0));
+  const uint32_t* h_tot = (const uint32_t*)(h8 + ((const char*)totals - rb0));
   if (base_hist) {
     base_hist->assign(nbh, 0u);
-    if (nbh && ntot > 0) memcpy(base_hist->data(), h + (D + 1) * (nf + 1) + nf, nbh * 4);
+    if (with_bh) memcpy(base_hist->data(), h8 + ((const char*)bhist - rb0), nbh * 4);
   }
   fr.nf = nf;
   fr.tot.assign(D + 1, 0);
-  for (int d = 0; d <= D; d++) fr.tot[d] = h[d];
+  for (int d = 0; d <= D; d++) fr.tot[d] = h_tot[d];
   fr.N.assign(nf, std::vector<int64_t>(D + 1, 0));
   fr.off.assign(nf, std::vector<int64_t>(D + 1, 0));
   fstatus.assign(nf, LPCC_OK);
   for (int f = 0; f < nf; f++)
-    if (h[(D + 1) * (nf + 1) + f] & ERR_COORD) fstatus[f] = LPCC_E_INVAL;
+    if (h_err[f] & ERR_COORD) fstatus[f] = LPCC_E_INVAL;
   for (int d = 0; d <= D; d++) {
     int64_t next = fr.tot[d];
     for (int f = nf - 1; f >= 0; f--) {
-      const uint32_t o = h[D + 1 + f * (D + 1) + d];
+      const uint32_t o = h_foff[f * (D + 1) + d];
       if (n[f] <= 0 || o == 0xFFFFFFFFu) {
         fr.off[f][d] = next;
         fr.N[f][d] = 0;
