@@ -90,7 +90,9 @@ const char* lpcc_last_error(const lpcc_ctx* c);
  *   chunk_log2 c in [4, 14]: nodes per range-coder chunk = 2^c
  *   out        bitstream buffer (host or device) of `cap` bytes
  *   out_len    bytes written, or the required size on LPCC_E_CAPACITY
- * Errors: LPCC_E_INVAL (bad coordinate / argument), LPCC_E_CAPACITY.
+ * Errors: LPCC_E_INVAL (bad coordinate / argument), LPCC_E_CAPACITY.  On
+ * LPCC_E_CAPACITY no byte at or past `cap` is written (the bytes below it
+ * are unspecified).
  */
 int lpcc_encode_frame(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int chunk_log2,
                       uint8_t* out, size_t cap, size_t* out_len);
