@@ -68,6 +68,24 @@ __device__ __forceinline__ int dstar(const uint64_t* keys, int64_t i, int D) {
 
 constexpr int kLevelThreads = 256;
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP: shifts by 1, 2,
+// 4, 8 within each row of 16 lanes (lanes without a source in the row add
+// 0), then lane 15 of rows 0 and 2 is added to rows 1 and 3 and lane 31 to
+// rows 2 and 3 (row broadcasts; the rows left out add 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_add_src(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, CTRL < 0x140);
+}
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  v += dpp_add_src<0x111, 0xF>(v);
+  v += dpp_add_src<0x112, 0xF>(v);
+  v += dpp_add_src<0x114, 0xF>(v);
+  v += dpp_add_src<0x118, 0xF>(v);
+  v += dpp_add_src<0x142, 0xA>(v);
+  v += dpp_add_src<0x143, 0xC>(v);
+  return v;
+}
+
 // hist[tile][v] = #elements of the tile with d* <= v (v = 0..D)
 __global__ void k_level_hist(const uint64_t* __restrict__ keys, int64_t n, int D, int tile,
                              uint32_t* __restrict__ hist) {
@@ -109,11 +127,7 @@ __global__ __launch_bounds__(kLevelThreads) void k_level_scan(uint32_t* __restri
   const int t0 = tid * per, t1 = min(nb, t0 + per);
   uint32_t run = 0;
   for (int t = t0; t < t1; t++) run += hist[(int64_t)t * (D + 1) + d];
-  uint32_t inc = run;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t v = __shfl_up(inc, off);
-    if (lane >= off) inc += v;
-  }
+  const uint32_t inc = wave_scan_incl(run);
   if (lane == 63) wsum[wave] = inc;
   __syncthreads();
   uint32_t ex = inc - run;
@@ -448,11 +462,7 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
     const bool valid = k0 + (int)threadIdx.x < ch.count && i < n;
     const uint32_t code = k0 == 0 ? code_first : (valid ? codes[i] : 0u);
     const uint32_t c = __popc(code);
-    uint32_t inc = c;
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t v = __shfl_up(inc, off);
-      if (lane >= off) inc += v;
-    }
+    const uint32_t inc = wave_scan_incl(c);
     if (lane == 63) wtot[wave] = inc;
     __syncthreads();
     uint32_t before = run;
