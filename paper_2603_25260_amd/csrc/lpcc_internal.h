@@ -95,6 +95,24 @@ __device__ __forceinline__ LayerDev load_layer(const LayerDev* p) {
   return L;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP: shifts by 1, 2,
+// 4, 8 within each row of 16 lanes (lanes without a source in the row add
+// 0), then lane 15 of rows 0 and 2 is added to rows 1 and 3 and lane 31 to
+// rows 2 and 3 (row broadcasts; the rows left out add 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_add_src(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, CTRL < 0x140);
+}
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  v += dpp_add_src<0x111, 0xF>(v);
+  v += dpp_add_src<0x112, 0xF>(v);
+  v += dpp_add_src<0x114, 0xF>(v);
+  v += dpp_add_src<0x118, 0xF>(v);
+  v += dpp_add_src<0x142, 0xA>(v);
+  v += dpp_add_src<0x143, 0xC>(v);
+  return v;
+}
+
 __device__ __forceinline__ v4i mfma16(v4i a, v4i b, v4i c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }

@@ -68,23 +68,6 @@ __device__ __forceinline__ int dstar(const uint64_t* keys, int64_t i, int D) {
 
 constexpr int kLevelThreads = 256;
 
-// Inclusive prefix sum over the 64 lanes of a wave with DPP: shifts by 1, 2,
-// 4, 8 within each row of 16 lanes (lanes without a source in the row add
-// 0), then lane 15 of rows 0 and 2 is added to rows 1 and 3 and lane 31 to
-// rows 2 and 3 (row broadcasts; the rows left out add 0).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp_add_src(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, CTRL < 0x140);
-}
-__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
-  v += dpp_add_src<0x111, 0xF>(v);
-  v += dpp_add_src<0x112, 0xF>(v);
-  v += dpp_add_src<0x114, 0xF>(v);
-  v += dpp_add_src<0x118, 0xF>(v);
-  v += dpp_add_src<0x142, 0xA>(v);
-  v += dpp_add_src<0x143, 0xC>(v);
-  return v;
-}
 
 // hist[tile][v] = #elements of the tile with d* <= v (v = 0..D)
 __global__ void k_level_hist(const uint64_t* __restrict__ keys, int64_t n, int D, int tile,
@@ -451,8 +434,8 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
   } else {
     uint32_t part = 0;
     for (int k = threadIdx.x; k < cb; k += 256) part += csum[k];
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if (lane == 0) wtot[wave] = part;
+    part = wave_scan_incl(part);  // lane 63: the wave's sum
+    if (lane == 63) wtot[wave] = part;
     __syncthreads();
     if (threadIdx.x == 0) run = wtot[0] + wtot[1] + wtot[2] + wtot[3];
   }

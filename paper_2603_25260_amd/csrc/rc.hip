@@ -117,8 +117,8 @@ __global__ __launch_bounds__(256) void k_rc_pack_dev(const Chunk* __restrict__ c
   const uint32_t n = lens[c];
   uint32_t part = 0;
   for (uint32_t k = F.first + threadIdx.x; k < c; k += 256) part += lens[k];
-  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = part;
+  part = wave_scan_incl(part);  // lane 63: the wave's sum
+  if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = part;
   __syncthreads();
   const uint64_t off = F.hsz + wsum[0] + wsum[1] + wsum[2] + wsum[3];
   GAS uint8_t* out = gp(F.out);
@@ -326,8 +326,8 @@ __global__ __launch_bounds__(64) void k_rc_decode(const Chunk* __restrict__ chun
   resolve();
   if (bad && lane == 0) atomicOr(err, ERR_CORRUPT);
   if (csum != nullptr) {
-    for (int off = 32; off > 0; off >>= 1) kids += __shfl_xor(kids, off);
-    if (lane == 0) csum[blockIdx.x] = kids;
+    kids = wave_scan_incl(kids);  // lane 63: the chunk's child count
+    if (lane == 63) csum[blockIdx.x] = kids;
   }
 }
 
