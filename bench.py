@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-base", action="store_true", help="skip the base-geometry lines")
     ap.add_argument("--no-schedules", action="store_true",
                     help="skip the schedule variants of the ablations")
+    ap.add_argument("--no-chunks", action="store_true",
+                    help="skip the range-coder chunk-size lines")
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration under a profiler)")
@@ -298,6 +300,8 @@ def main():
         res["schedules"] = _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout)
     if not args.no_base:
         res["base_geometry"] = _bench_base(lpcc, torch, model, frames, dxyz, cl, dbs, dout, D - cfg.n_deep - 1)
+    if not args.no_chunks:
+        res["chunk_sizes"] = _bench_chunks(lpcc, torch, ctx, model, frames, dxyz, dbs, dout)
     if not args.no_serve:
         from paper_2603_25260_amd import serve
         rep_ = serve.run(duration_s=args.serve_seconds, n_sensors=24, rate_hz=10.0, seed=5000, slots=4,
@@ -383,6 +387,34 @@ def _bench_schedules(lpcc, synth, torch, dev, ctx, frames, dxyz, cl, dbs, dout):
         out.append({"schedule": name, "n_deep": nd, "xfp": xfp, "k0": cfg.scan.D - nd - 1,
                     "mpts_s": round(pts / wall / 1e6, 3), "ms_per_frame": round(wall / len(frames) * 1e3, 3),
                     "bytes_per_point": round(sum(lens) / pts, 3)})
+    return out
+
+
+def _bench_chunks(lpcc, torch, ctx, model, frames, dxyz, dbs, dout):
+    """Plain encode+decode of the same 64-beam frames with range-coder chunks
+    of 2^c nodes: the decoder's serial path per depth is one chunk, so a
+    smaller c shortens it at the cost of a length field and a coder flush per
+    chunk (c = 8 is the headline setting)."""
+    out = []
+    for c in (6, 7, 8, 10):
+        lens = []
+        for k in range(len(frames)):  # warm-up
+            n = lpcc.encode_frame(ctx, model, dxyz[k], c, out=dbs)
+            lpcc.decode_frame(ctx, model, dbs, length=n, out=dout)
+            lens.append(n)
+        reps = 2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for k in range(len(frames)):
+                n = lpcc.encode_frame(ctx, model, dxyz[k], c, out=dbs)
+                lpcc.decode_frame(ctx, model, dbs, length=n, out=dout)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        pts = sum(len(f) for f in frames)
+        out.append({"chunk_log2": c, "mpts_s": round(pts / wall / 1e6, 3),
+                    "ms_per_frame": round(wall / len(frames) * 1e3, 3),
+                    "bytes_per_point": round(sum(lens) / pts, 4)})
     return out
 
 
