@@ -1995,7 +1995,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   // the event records and waits of the split would cost the host more than
   // the overlap gains.  The split starts at the first depth of kSplitRows
   // nodes (node counts only grow with depth) and lasts to the end.
-  constexpr int64_t kSplitRows = 4096;
+  constexpr int64_t kSplitRows = 16384;
   int dsplit = D;
   for (int d = 0; d < D; d++)
     if (fr.tot[d] >= kSplitRows) {
