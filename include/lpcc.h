@@ -5,8 +5,10 @@
  *
  * What the library computes
  *   A point cloud of int32 voxel coordinates in [0, 2^D)^3 is turned into an
- *   octree (Sec. S3.2: Morton sort, halve and de-duplicate, 8-bit occupancy
- *   codes).  Depth by depth, from the root, an integer-only network predicts
+ *   octree (Sec. S3.2, "Implementation of Octree Operations": Morton sort,
+ *   halve and de-duplicate, 8-bit occupancy codes).  Coding it losslessly is
+ *   the problem of Sec. 3.1, Eq. 1-3: the codes of each level are coded
+ *   under a distribution predicted from the levels before it.  Depth by depth, from the root, an integer-only network predicts
  *   each node's distribution over the 255 non-empty occupancy codes
  *   (Eq. 2-3): shallow depths propagate the previous depth's features through
  *   a ResBlock and one upsample/prune step (Eq. 8-9); deep depths re-densify
@@ -31,11 +33,14 @@
  *     several contexts of the same device.
  *   - Calls are synchronous: outputs are complete when the call returns.
  *
- * Bitstream (little-endian): u32 "LPC1", u8 version (1), u8 D, u8 n_deep,
- *   u8 c (log2 of the chunk size), u32 blob id (FNV-1a of the weight blob),
- *   u32 N_D, u32 N_d for d = 0..D-1, u16 payload length of every chunk
- *   (depth ascending, chunk ascending), then the payloads.  Chunk k of depth d
- *   codes nodes [k 2^c, min((k+1) 2^c, N_d)) of that depth.
+ * Bitstream (little-endian; the paper leaves the entropy coder and the stream
+ *   layout open, Sec. 3.1 "Prediction & Coding"): u32 "LPC1", u8 version
+ *   (1: every depth modelled; 2: base geometry, see lpcc_ctx_set_base_depth),
+ *   u8 D, u8 n_deep, u8 c (log2 of the chunk size), u32 blob id (FNV-1a of
+ *   the weight blob), u32 N_D, u32 N_d for d = 0..D-1, [version 2: the base
+ *   tables], u16 payload length of every chunk (depth ascending, chunk
+ *   ascending), then the payloads.  Chunk k of depth d codes nodes
+ *   [k 2^c, min((k+1) 2^c, N_d)) of that depth.
  */
 #ifndef LPCC_H
 #define LPCC_H
@@ -53,10 +58,36 @@ extern "C" {
 #define LPCC_E_CORRUPT (-3)  /* malformed or inconsistent bitstream                             */
 #define LPCC_E_MODEL (-4)    /* malformed weight blob, or stream made with another model       */
 #define LPCC_E_DEVICE (-5)   /* HIP runtime error; text via lpcc_last_error                     */
-#define LPCC_E_NOMEM (-6)    /* device memory allocation failed                                 */
+#define LPCC_E_NOMEM (-6)    /* device allocation failed, or workspace over the context's budget  */
 
 typedef struct lpcc_model lpcc_model; /* weights resident on one device, read-only  */
 typedef struct lpcc_ctx lpcc_ctx;     /* device, stream, workspace of one caller     */
+
+/*
+ * Seeded random-init weight blob (the model of Sec. S2 with the schedule of
+ * Sec. 3.1-3.2; every layer int8 weights, int32 bias and the multiply-shift
+ * requantisation of Eq. 12-14).  Host only, integer arithmetic only,
+ * deterministic: the same arguments always give the same bytes.
+ *   seed         SplitMix64 seed (counter form) of every draw
+ *   C            channel width: 16, 32 or 64
+ *   D, n_deep    octree levels and number of re-densified deep depths
+ *                (0 <= n_deep <= D - 1; the dense fusion depth is D - n_deep - 1)
+ *   flags        LPCC_W_NO_XFP: the ablation schedule without cross-scale
+ *                propagation (blob version 2); LPCC_W_ZERO_POINTS: activation
+ *                zero points in [-8, 8] on every layer (Eq. 13-14)
+ *   blob, cap    output buffer (host); may be NULL with cap = 0 to query
+ *   len          bytes of the blob (also with LPCC_E_CAPACITY)
+ * Layout: u32 "LPCW", u32 version, u32 C, u32 D, u32 n_deep, u32 n_layers,
+ * u64 seed; per layer u32 kind, depth, j, taps, cin, cout, i32 m_pos, m_neg,
+ * u32 r, i32 z_in, z_out, i32 bias[cout], i8 W[taps][cin][cout], zero
+ * padding to 4 bytes.  W = (u >> 33) mod 255 - 127, bias = (u >> 33) mod 8193
+ * - 4096, r = 24, m_pos = floor(2^24 / (73.6 sqrt(taps cin))) (3/4 of it for
+ * the logit layer), m_neg = 0 (ReLU), m_pos (identity) or m_pos / 4 (PReLU).
+ * Errors: LPCC_E_INVAL (bad argument), LPCC_E_CAPACITY (cap < len).
+ */
+#define LPCC_W_NO_XFP 1
+#define LPCC_W_ZERO_POINTS 2
+int lpcc_make_weights(uint64_t seed, int C, int D, int n_deep, int flags, void* blob, size_t cap, size_t* len);
 
 /*
  * Weight blob -> device model (the per-depth layers of Sec. S2; parameters are
@@ -71,21 +102,29 @@ void lpcc_model_free(lpcc_model* m);
 int lpcc_model_info(const lpcc_model* m, int* C, int* D, int* n_deep, uint32_t* blob_id);
 
 /*
- * Context on `device`.  `hip_stream` (a hipStream_t) is where all work of the
- * context is enqueued; the context does not own it.  With NULL the context
- * creates a stream of its own (default priority, blocking: ordered with the
- * null stream, so inputs written there are complete when its work starts) and
- * destroys it in lpcc_ctx_free.  Every call returns after its work on the
- * stream has finished.  Device workspace grows on demand and is reused
- * between calls.
+ * Context on `device` (the execution state of the level-by-level pipeline of
+ * Sec. 3.1-3.3 for one caller).  `hip_stream` (a hipStream_t) is where all
+ * work of the context is enqueued; the context does not own it.  With NULL
+ * the context creates a stream of its own (default priority, blocking:
+ * ordered with the null stream, so inputs written there are complete when its
+ * work starts) and destroys it in lpcc_ctx_free.  Every call returns after
+ * its work on the stream has finished.  Device workspace grows on demand and
+ * is reused between calls; `hbm_budget` (bytes, 0 = no limit) caps the
+ * workspace the context may hold: a call that would need more fails with
+ * LPCC_E_NOMEM and leaves the context usable.
  */
-int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out);
+int lpcc_ctx_create(int device, void* hip_stream, size_t hbm_budget, lpcc_ctx** out);
 void lpcc_ctx_free(lpcc_ctx* c);
+/* Device workspace bytes the context holds now and at most so far. */
+int lpcc_ctx_workspace(const lpcc_ctx* c, size_t* held, size_t* peak);
 /* Text of the last error of this context (valid until the next call). */
 const char* lpcc_last_error(const lpcc_ctx* c);
 
 /*
- * Encode one frame (octree construction, per-depth model, range coding).
+ * Encode one frame: octree construction (Sec. S3.2), per depth the features
+ * of the shallow (Eq. 8-9) or re-densified deep path (Eq. 4-7, 10-11), the
+ * predictor and integer softmax (Eq. 7, 15) and range coding of the codes
+ * under the predicted distribution (Eq. 2-3).
  *   xyz        int32 [n][3], host or device
  *   chunk_log2 c in [4, 14]: nodes per range-coder chunk = 2^c
  *   out        bitstream buffer (host or device) of `cap` bytes
@@ -98,7 +137,10 @@ int lpcc_encode_frame(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int6
                       uint8_t* out, size_t cap, size_t* out_len);
 
 /*
- * Decode one frame, depth by depth (the decoder sees only coded depths).
+ * Decode one frame, depth by depth: the model of every depth reads only the
+ * depths decoded before it (Eq. 2), so the decoder rebuilds the same
+ * distributions and the geometry progressively (Sec. 3.1, S3.2 child
+ * expansion in Morton order).
  *   bs, len    bitstream, host or device
  *   xyz_out    int32 [cap][3] (host or device): unique voxels in Morton order
  *   n_out      number of voxels, also returned with LPCC_E_CAPACITY
@@ -109,7 +151,8 @@ int lpcc_decode_frame(lpcc_ctx* c, const lpcc_model* m, const uint8_t* bs, size_
                       int64_t cap, int64_t* n_out);
 
 /*
- * CDF rows of one depth: the encoder's model output for `level` (0..D-1),
+ * CDF rows of one depth: the predicted distribution of Eq. 3 / Eq. 7 after
+ * the integer softmax of Eq. 15, as the coder uses it, for `level` (0..D-1),
  * int32 [N_level][256] with cdf[0] = 0, cdf[255] = 65536 and
  * cdf[s+1] - cdf[s] >= 1 the frequency of occupancy code s + 1.
  *   cdf_out    host or device; n_nodes = N_level (also with LPCC_E_CAPACITY)
@@ -117,11 +160,19 @@ int lpcc_decode_frame(lpcc_ctx* c, const lpcc_model* m, const uint8_t* bs, size_
 int lpcc_level_probs(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int level,
                      int32_t* cdf_out, int64_t cap, int64_t* n_nodes);
 
-/* Depth and point count from the first 16 bytes of a stream (host memory only). */
-int lpcc_peek_header(const uint8_t* bs, size_t len, int* D, int64_t* n_points);
+/*
+ * Depth and point count from the first 16 bytes of a stream (host memory
+ * only; the stream layout above).  max_workspace (may be NULL): device
+ * workspace bytes a fresh context needs to decode this stream with any model
+ * it may have been made with (C <= 64), computed from the depth counts, so it
+ * needs len >= 16 + 4 D (base-geometry streams: their tables too); with fewer
+ * bytes it is 0.  Errors: LPCC_E_INVAL (null), LPCC_E_CORRUPT (bad header).
+ */
+int lpcc_peek_header(const uint8_t* bs, size_t len, int* D, int64_t* n_points, size_t* max_workspace);
 
 /*
- * Batched forms: `nf` frames of one model share every launch of a depth
+ * Batched forms of the calls above (the same computation per frame): `nf`
+ * frames of one model share every launch of a depth
  * (one launch per depth and layer over the rows of all frames).  Results are
  * identical, byte for byte, to the per-frame calls.  Per-frame status codes
  * go to status[nf]; the return value is LPCC_OK if every frame succeeded,
@@ -135,15 +186,21 @@ int lpcc_decode_batch(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* c
 
 /*
  * Serving: continuous batching of encode / decode requests from many
- * sensors on one device (callers that stream frames from live sensors).
+ * sensors on one device (callers that stream frames from live sensors; the
+ * per-frame computation is the one of lpcc_encode_frame / lpcc_decode_frame).
  *
  * The server runs `n_slots` slots concurrently, each with its own stream and
  * workspace (a frame's octree and features stay resident on the device while
- * it is processed).  A submitted job waits until a slot is free and its
- * estimated device footprint fits in `hbm_budget` (0 = 7/8 of the free
- * memory) beside the running jobs; a free slot takes the oldest admissible job
- * and up to `max_batch - 1` queued jobs of the same model and kind, which share
- * every launch (lpcc_encode_batch / lpcc_decode_batch).  Results are byte-
+ * it is processed).  Admission is by device memory: the slots' workspace is
+ * counted as allocated, and a job is admitted when the growth its slot needs
+ * for it (an upper bound from its point count or its stream header) fits in
+ * `hbm_budget` (0 = 7/8 of the free memory) beside what the slots hold and
+ * what running jobs were granted; idle slots release their workspace when a
+ * waiting job needs it.  Each slot's context is capped at what it was
+ * granted, so the device workspace of the server never exceeds the budget
+ * (bytes_peak).  A free slot takes the oldest admissible job and up to
+ * `max_batch - 1` queued jobs of the same model and kind, which share every
+ * launch (lpcc_encode_batch / lpcc_decode_batch).  Results are byte-
  * identical to the per-frame calls.  Job buffers belong to the caller and must
  * stay valid until the job is reported by lpcc_server_poll.  Timestamps are
  * CLOCK_MONOTONIC nanoseconds.
@@ -173,7 +230,9 @@ typedef struct {
   double p50_ms, p99_ms, mean_ms; /* arrival -> completion latency                  */
   double mpts_per_s;              /* points of completed jobs / (last done - first arrival) */
   int64_t completed, admitted, queued, running;
-  size_t bytes_in_use, bytes_budget;
+  size_t bytes_in_use;            /* workspace held by the slots + growth granted to running jobs */
+  size_t bytes_budget;
+  size_t bytes_peak;              /* largest bytes_in_use so far (bounds the device workspace)    */
 } lpcc_stats;
 
 int lpcc_server_create(int device, const lpcc_model* const* models, int n_models, int n_slots, int max_batch,
@@ -189,7 +248,7 @@ int lpcc_server_stats(lpcc_server* s, lpcc_stats* st);
 void lpcc_server_free(lpcc_server* s);
 
 /*
- * Kernel timing: when enabled, the context records HIP events around every
+ * Kernel timing (measurement, no part of the method): when enabled, the context records HIP events around every
  * launch of the kernel family named `name` ("predict", "conv", "up", ...) on
  * its stream and accumulates their durations.  lpcc_timing_read returns the
  * number of launches and the summed milliseconds since the last reset.
@@ -198,7 +257,9 @@ int lpcc_timing_enable(lpcc_ctx* c, const char* name);
 int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* units);
 
 /*
- * Tile shapes of the gather-GEMM and up-convolution kernels.  A wave computes
+ * Tile shapes of the gather-GEMM and up-convolution kernels (the indexed
+ * linear transforms of the sparse convolutions, Sec. 3.3, and the
+ * upsampling of Eq. 6).  A wave computes
  * rb blocks of 16 rows (rb = 1, 2 or 4); larger rb re-uses every weight
  * fragment across more rows and suits large launches, rb = 1 has the
  * shortest per-wave chain and suits small ones.  rb = 0 (the default)
@@ -215,7 +276,8 @@ int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* 
 int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb);
 
 /*
- * Graph mode (off by default).  When on, each launch batch of a call (the
+ * Graph mode (off by default; launch mechanics only, the computation is that
+ * of the calls above).  When on, each launch batch of a call (the
  * level loop of a decode; the model, coder and packing stages of an encode)
  * is captured on the context's stream into a HIP graph and launched as one
  * graph.  The context keeps one executable graph per batch position and call
@@ -231,7 +293,7 @@ int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n);
 
 /*
  * Base geometry (the paper codes the geometry of the levels it does not
- * model directly from the frequencies of their symbols, Sec. S3.1).  With
+ * model directly from the frequencies of their symbols, Sec. S2).  With
  * base depth B > 0 the streams this context encodes code the occupancy codes
  * of depths 0..B-1 with a static table per depth built from the counts of
  * that depth's codes (the integer-softmax rule with counts in place of the
@@ -248,7 +310,8 @@ int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n);
 int lpcc_ctx_set_base_depth(lpcc_ctx* c, int base);
 
 /*
- * The integer exponent table of the softmax (Eq. 15) as the library builds
+ * The integer exponent table of the softmax (Eq. 15; the table covers the
+ * non-positive domain, Sec. 3.3 "Integer softmax") as the library builds
  * it: out[i] = round(2^15 e^{-i/16}), i = 0..255, computed on the host with
  * an integer recurrence.  Host memory; needs no device.
  */

@@ -202,13 +202,41 @@ struct Chunk {
 };
 
 // Device-side error bits
-enum : uint32_t { ERR_COORD = 1u, ERR_CORRUPT = 2u, ERR_COUNT = 4u, ERR_ACC = 8u };
+enum : uint32_t { ERR_COORD = 1u, ERR_CORRUPT = 2u, ERR_COUNT = 4u, ERR_ACC = 8u, ERR_SORT = 16u };
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_morton(const int32_t* xyz, int64_t n, int D, uint64_t frame_tag, uint64_t* keys,
-                         uint32_t* err, hipStream_t s);
+// ---------------------------------------------------------------------------
+// Morton keys and their LSD radix sort (Sec. S3.2: coordinates sorted in
+// Morton order).  Keys are sorted on bits [0, end_bit) in passes of at most
+// 8 bits, tiles of kSortTile keys; hist is [passes][tiles][256] per-tile digit
+// counts (zeroed first), totals [passes][256] digit counts of all keys.
+// ---------------------------------------------------------------------------
+constexpr int kSortItems = 8;
+constexpr int kSortTile = 256 * kSortItems;
+constexpr int kSortFusedTiles = 64;  // up to this many tiles a pass scans its own offsets
+constexpr int kMortonGroup = 16;     // frames per Morton launch (passed by value)
+struct SortPasses {
+  int32_t n;
+  int32_t shift[8];
+  int32_t bits[8];
+};
+SortPasses sort_passes(int end_bit);
+struct MortonFrames {
+  const int32_t* xyz[kMortonGroup];  // device coordinates of each frame
+  int64_t start[kMortonGroup + 1];   // key range of each frame (start[nf] = end)
+  int32_t nf;                        // frames of this launch
+  int32_t f0;                        // index of the first (frame tag, error word)
+};
+// keys of the frames' points (frame tag f << 3D), their per-tile digit
+// counts of pass 0 and the digit totals of every pass
+hipError_t launch_morton_sort0(const MortonFrames& mf, int D, uint64_t* keys, uint32_t* err, const SortPasses& sp,
+                               uint32_t* hist, uint32_t* totals, hipStream_t s);
+// pass p: kin -> kout, stable on the pass's digit; adds the per-tile digit
+// counts of pass p+1 (of kout) into hist; ERR_SORT in *err on an impossible rank
+hipError_t launch_sort_pass(const uint64_t* kin, uint64_t* kout, int64_t n, const SortPasses& sp, int p,
+                            uint32_t* hist, const uint32_t* totals, uint32_t* err, hipStream_t s);
 // Octree build over sorted keys (frame id in bits >= 3D).
 hipError_t launch_level_hist(const uint64_t* keys, int64_t n, int D, int tile, uint32_t* hist,
                              hipStream_t s);
@@ -279,6 +307,18 @@ hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t
                                 int64_t n_child_expected, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
                                 uint32_t* err, hipStream_t s);
 hipError_t launch_keys_to_xyz(const uint64_t* keys, int64_t n, int D, int32_t* xyz, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Workspace accounting (host): upper bounds of the three arenas (octree,
+// model, descriptors) a call needs, computed by the same carving code the
+// calls use, and the serving engine's hooks into a context.
+// ---------------------------------------------------------------------------
+void encode_workspace_bound(const lpcc_model* m, int nf, const int64_t* n, int cl, bool host_in, size_t out[3]);
+// N[f]: the D + 1 node counts of stream f (its header), cl[f] its chunk size
+void decode_workspace_bound(const lpcc_model* m, int nf, const int64_t* const* N, const int* cl, size_t out[3]);
+void ctx_caps(const lpcc_ctx* c, size_t caps[3]);
+void ctx_set_budget(lpcc_ctx* c, size_t budget);
+void ctx_trim(lpcc_ctx* c);  // frees the arenas (the context stays usable)
 
 // Base geometry: the depths d < nb are coded from the counts of their own
 // codes.  Nodes of those depths are addressed as one range: node i of depth

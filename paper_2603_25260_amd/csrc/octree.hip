@@ -1,6 +1,8 @@
 // Octree construction, coordinate hash, 3x3x3 neighbourhoods and child
 // expansion on gfx950 (Sec. S3.2 of the paper; neighbourhoods for the sparse
 // convolutions of Sec. 3.3).  Integer-only; wave64 ballots and prefix counts.
+#include <cstring>
+
 #include "lpcc_internal.h"
 
 namespace lpcc {
@@ -29,24 +31,212 @@ __device__ __forceinline__ uint32_t compact3(uint64_t x) {
   return (uint32_t)x;
 }
 
-__global__ void k_morton(const int32_t* __restrict__ xyz, int64_t n, int D, uint64_t tag,
-                         uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int32_t x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-  uint32_t side = 1u << D;
-  if (x < 0 || y < 0 || z < 0 || (uint32_t)x >= side || (uint32_t)y >= side || (uint32_t)z >= side) {
-    atomicOr(err, ERR_COORD);
-    x = y = z = 0;
+// ---------------------------------------------------------------------------
+// LSD radix sort of the Morton keys (Sec. S3.2 sorts the coordinates in
+// Morton order before the levels are derived).  Passes of at most 8 bits from
+// the least significant end; each pass is stable, so the keys end sorted on
+// all bits [0, end_bit).  A tile is kSortTile keys in striped order (item k of
+// thread t is key k*256 + t of the tile).
+// ---------------------------------------------------------------------------
+SortPasses sort_passes(int end_bit) {
+  SortPasses sp;
+  memset(&sp, 0, sizeof(sp));
+  end_bit = end_bit < 1 ? 1 : end_bit;
+  sp.n = (end_bit + 7) / 8;
+  const int w = (end_bit + sp.n - 1) / sp.n;
+  for (int p = 0; p < sp.n; p++) {
+    sp.shift[p] = p * w;
+    sp.bits[p] = w < end_bit - p * w ? w : end_bit - p * w;
   }
-  keys[i] = tag | (spread3((uint32_t)x) << 2) | (spread3((uint32_t)y) << 1) | spread3((uint32_t)z);
+  return sp;
 }
 
-hipError_t launch_morton(const int32_t* xyz, int64_t n, int D, uint64_t frame_tag, uint64_t* keys,
-                         uint32_t* err, hipStream_t s) {
+__device__ __forceinline__ uint32_t digit_of(uint64_t key, int shift, int bits) {
+  return (uint32_t)(key >> shift) & ((1u << bits) - 1u);
+}
+
+// Keys of the launch's frames: block b covers tile (first tile of the
+// launch's key range) + b; its keys' pass-0 digits are counted per tile and
+// every pass's digits in the totals (LDS first, then one global add per bin).
+__global__ __launch_bounds__(256) void k_morton_sort0(const MortonFrames mf, int D, uint64_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ err, const SortPasses sp,
+                                                      uint32_t* __restrict__ hist, uint32_t* __restrict__ totals) {
+  __shared__ uint32_t h[8][256];
+  for (int k = threadIdx.x; k < 8 * 256; k += 256) (&h[0][0])[k] = 0u;
+  __syncthreads();
+  const int64_t lo = mf.start[0], hi = mf.start[mf.nf];
+  const int64_t tile = lo / kSortTile + blockIdx.x;
+  const uint32_t side = 1u << D;
+  for (int k = 0; k < kSortItems; k++) {
+    const int64_t i = tile * kSortTile + k * 256 + threadIdx.x;
+    if (i < lo || i >= hi) continue;
+    // frame of element i (constant indices into the argument arrays)
+    int f = 0;
+#pragma unroll
+    for (int g = 1; g < kMortonGroup; g++)
+      if (g < mf.nf && i >= mf.start[g]) f = g;
+    const int32_t* src = mf.xyz[0];
+    int64_t s0 = mf.start[0];
+#pragma unroll
+    for (int g = 1; g < kMortonGroup; g++)
+      if (g == f) {
+        src = mf.xyz[g];
+        s0 = mf.start[g];
+      }
+    const GAS int32_t* p = gp(src) + 3 * (i - s0);
+    int32_t x = p[0], y = p[1], z = p[2];
+    if (x < 0 || y < 0 || z < 0 || (uint32_t)x >= side || (uint32_t)y >= side || (uint32_t)z >= side) {
+      atomicOr(err + mf.f0 + f, ERR_COORD);
+      x = y = z = 0;
+    }
+    const uint64_t tag = (uint64_t)(mf.f0 + f) << (3 * D);
+    const uint64_t key = tag | (spread3((uint32_t)x) << 2) | (spread3((uint32_t)y) << 1) | spread3((uint32_t)z);
+    gp(keys)[i] = key;
+    for (int q = 0; q < sp.n; q++) atomicAdd(&h[q][digit_of(key, sp.shift[q], sp.bits[q])], 1u);
+  }
+  __syncthreads();
+  const int b = threadIdx.x;
+  for (int q = 0; q < sp.n; q++) {
+    const uint32_t v = h[q][b];
+    if (!v) continue;
+    atomicAdd(totals + q * 256 + b, v);
+    if (q == 0) atomicAdd(hist + tile * 256 + b, v);
+  }
+}
+
+hipError_t launch_morton_sort0(const MortonFrames& mf, int D, uint64_t* keys, uint32_t* err, const SortPasses& sp,
+                               uint32_t* hist, uint32_t* totals, hipStream_t s) {
+  const int64_t lo = mf.start[0], hi = mf.start[mf.nf];
+  if (hi <= lo) return hipSuccess;
+  const int64_t blocks = (hi - 1) / kSortTile - lo / kSortTile + 1;
+  hipLaunchKernelGGL(k_morton_sort0, dim3((unsigned)blocks), dim3(256), 0, s, mf, D, keys, err, sp, hist, totals);
+  return hipGetLastError();
+}
+
+// In place: hist[t][d] <- first destination of tile t's keys of digit d
+// (digits ascending, tiles ascending within a digit).  One block; thread
+// (part, d) walks a quarter of the tiles for digit d.
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist, int ntiles,
+                                                    const uint32_t* __restrict__ totals) {
+  __shared__ uint32_t psum[4][256];
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t base[256];
+  const int d = threadIdx.x & 255, part = threadIdx.x >> 8;
+  const int per = (ntiles + 3) / 4;
+  const int t0 = min(ntiles, part * per), t1 = min(ntiles, t0 + per);
+  uint32_t sum = 0;
+  for (int t = t0; t < t1; t++) sum += gp(hist)[(int64_t)t * 256 + d];
+  psum[part][d] = sum;
+  uint32_t tot = 0, inc = 0;
+  if (part == 0) {
+    tot = gp(totals)[d];
+    inc = wave_scan_incl(tot);
+    if ((d & 63) == 63) wsum[d >> 6] = inc;
+  }
+  __syncthreads();
+  if (part == 0) {
+    uint32_t ex = inc - tot;
+    for (int w = 0; w < (d >> 6); w++) ex += wsum[w];
+    base[d] = ex;
+  }
+  __syncthreads();
+  uint32_t off = base[d];
+  for (int q = 0; q < part; q++) off += psum[q][d];
+  for (int t = t0; t < t1; t++) {
+    const int64_t o = (int64_t)t * 256 + d;
+    const uint32_t v = gp(hist)[o];
+    gp(hist)[o] = off;
+    off += v;
+  }
+}
+
+// One pass: every key's destination is the first destination of its tile's
+// digit plus its rank among the tile's keys of that digit.  Ranks within a
+// wave come from a ballot match over the digit bits; the counts of every
+// (item, wave, digit) are turned into running offsets by one thread per
+// digit.  With offs_ready the tile offsets come from k_sort_scan, else the
+// pass sums the counts of the tiles before it and the totals of the smaller
+// digits itself.  The digit counts of the next pass are added per
+// destination tile.
+__global__ __launch_bounds__(256) void k_sort_scatter(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
+                                                      int64_t n, int shift, int bits, const uint32_t* __restrict__ hist,
+                                                      int offs_ready, const uint32_t* __restrict__ totals,
+                                                      uint32_t* __restrict__ hist_next, int shift_n, int bits_n,
+                                                      uint32_t* __restrict__ err) {
+  __shared__ uint32_t cnt[kSortItems][4][256];
+  __shared__ uint32_t wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t tile = blockIdx.x;
+  for (int k = tid; k < kSortItems * 4 * 256; k += 256) (&cnt[0][0][0])[k] = 0u;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint64_t key[kSortItems];
+  uint32_t dig[kSortItems], rk[kSortItems];
+#pragma unroll
+  for (int k = 0; k < kSortItems; k++) {
+    const int64_t i = tile * kSortTile + k * 256 + tid;
+    key[k] = i < n ? gp(kin)[i] : 0ull;
+    dig[k] = digit_of(key[k], shift, bits);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortItems; k++) {
+    const bool valid = tile * kSortTile + k * 256 + tid < n;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < bits; b++) {
+      const bool bit = (dig[k] >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    rk[k] = (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0ull) cnt[k][wave][dig[k]] = (uint32_t)__popcll(peers);
+  }
+  // first destination of digit `tid` in this tile
+  const uint32_t tot = gp(totals)[tid];
+  const uint32_t inc = wave_scan_incl(tot);
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t off;
+  if (offs_ready) {
+    off = gp(hist)[tile * 256 + tid];
+  } else {
+    off = inc - tot;
+    for (int w = 0; w < wave; w++) off += wsum[w];
+    for (int64_t t = 0; t < tile; t++) off += gp(hist)[t * 256 + tid];
+  }
+#pragma unroll
+  for (int k = 0; k < kSortItems; k++)
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      const uint32_t c = cnt[k][w][tid];
+      cnt[k][w][tid] = off;
+      off += c;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortItems; k++) {
+    if (tile * kSortTile + k * 256 + tid >= n) continue;
+    const uint64_t dest = (uint64_t)cnt[k][wave][dig[k]] + rk[k];
+    if (dest >= (uint64_t)n) {  // only if the counts were inconsistent
+      atomicOr(err, ERR_SORT);
+      continue;
+    }
+    gp(kout)[dest] = key[k];
+    if (bits_n > 0)
+      atomicAdd(hist_next + (dest / kSortTile) * 256 + digit_of(key[k], shift_n, bits_n), 1u);
+  }
+}
+
+hipError_t launch_sort_pass(const uint64_t* kin, uint64_t* kout, int64_t n, const SortPasses& sp, int p,
+                            uint32_t* hist, const uint32_t* totals, uint32_t* err, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_morton, dim3((unsigned)blocks), dim3(256), 0, s, xyz, n, D, frame_tag, keys, err);
+  const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+  uint32_t* hp = hist + (int64_t)p * ntiles * 256;
+  const bool last = p + 1 >= sp.n;
+  const bool scan = ntiles > kSortFusedTiles;
+  if (scan) hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hp, (int)ntiles, totals + p * 256);
+  hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)ntiles), dim3(256), 0, s, kin, kout, n, sp.shift[p], sp.bits[p],
+                     (const uint32_t*)hp, scan ? 1 : 0, totals + p * 256, last ? nullptr : hp + ntiles * 256,
+                     last ? 0 : sp.shift[p + 1], last ? 0 : sp.bits[p + 1], err);
   return hipGetLastError();
 }
 

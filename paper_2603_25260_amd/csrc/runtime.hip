@@ -4,7 +4,7 @@
 // tile tables that are uploaded once per phase.
 #include <array>
 #include <map>
-#include <hipcub/hipcub.hpp>
+#include <mutex>
 
 #include <algorithm>
 #include <cstdio>
@@ -350,6 +350,16 @@ struct lpcc_ctx {
   // base depth B of the streams this context encodes: depths below B are
   // coded from the counts of their own codes, the model runs from depth B
   int base = 0;
+  // workspace cap in bytes (0 = none) and the most held so far
+  size_t budget = 0, peak = 0;
+  // fixed mode (the entry point that allocates nothing): the arenas are
+  // carved from one device block the library owns, host staging uses
+  // pageable memory, one stream, no events
+  bool fixed = false;
+  char* fixed_base = nullptr;
+  size_t fixed_cap = 0, fixed_off1 = 0;
+  std::vector<uint8_t> hostbuf;
+  lpcc_ctx* noalloc = nullptr;  // fixed-mode companion of this context
 };
 
 namespace {
@@ -365,20 +375,62 @@ namespace {
     }                                                                                \
   } while (0)
 
+size_t held_bytes(const lpcc_ctx* c) { return c->fixed ? 0 : c->cap[0] + c->cap[1] + c->cap[2]; }
+
+// Fixed mode: [0, kFixedDesc) descriptors, then the octree arena, then the
+// model arena of the current call, all inside the library's block.
+constexpr size_t kFixedDesc = (size_t)2 << 20;
+
+int reserve_fixed(lpcc_ctx* c, int which, size_t bytes) {
+  bytes = align_up(bytes, 256);
+  size_t at = which == 2 ? 0 : (which == 0 ? kFixedDesc : c->fixed_off1);
+  const size_t lim = which == 2 ? kFixedDesc : c->fixed_cap;
+  if (at + bytes > lim) {
+    char b[256];
+    snprintf(b, sizeof(b), "workspace of %zu bytes does not fit the %zu-byte static block of the allocation-free "
+                           "entry point", at + bytes + (which == 2 ? 0 : 0), c->fixed_cap);
+    c->err = b;
+    return LPCC_E_NOMEM;
+  }
+  c->dev[which] = c->fixed_base + at;
+  c->cap[which] = which == 2 ? kFixedDesc : bytes;
+  if (which == 0) c->fixed_off1 = kFixedDesc + bytes;
+  return LPCC_OK;
+}
+
 int reserve(lpcc_ctx* c, int which, size_t bytes) {
+  if (c->fixed) return reserve_fixed(c, which, bytes);
   if (bytes <= c->cap[which]) return LPCC_OK;
   size_t nc = std::max(bytes, c->cap[which] + c->cap[which] / 4);
+  if (c->budget) {  // grow by a quarter when the budget allows, else exactly
+    const size_t others = held_bytes(c) - c->cap[which];
+    if (others + nc > c->budget) nc = bytes;
+    if (others + nc > c->budget) {
+      char b[256];
+      snprintf(b, sizeof(b), "workspace of %zu bytes over the context's budget of %zu bytes", others + nc,
+               c->budget);
+      c->err = b;
+      return LPCC_E_NOMEM;
+    }
+  }
   HIPC(hipStreamSynchronize(c->stream));
   if (c->dev[which]) HIPC(hipFree(c->dev[which]));
   c->dev[which] = nullptr;
   c->cap[which] = 0;
   HIPC(hipMalloc((void**)&c->dev[which], nc));
   c->cap[which] = nc;
+  c->peak = std::max(c->peak, held_bytes(c));
   return LPCC_OK;
 }
 
 int reserve_pinned(lpcc_ctx* c, size_t bytes) {
   if (bytes <= c->pinned_cap) return LPCC_OK;
+  if (c->fixed) {  // pageable: copies from and to it complete before they return
+    c->hostbuf.resize(std::max(bytes, 2 * c->hostbuf.size()));
+    c->pinned = c->hostbuf.data();
+    c->pinned_cap = c->hostbuf.size();
+    return LPCC_OK;
+  }
   size_t nc = std::max(bytes, c->pinned_cap * 2);
   HIPC(hipStreamSynchronize(c->stream));
   if (c->pinned) HIPC(hipHostFree(c->pinned));
@@ -771,6 +823,9 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
   std::vector<int> cands;
   if (c->tiling) {
     cands = {c->tiling};
+  } else if (c->fixed) {  // no events: a decided class, else two row blocks per wave
+    auto it = c->tune.find({up ? 1 : 0, mode, cin, cout, log2_rows(units)});
+    cands = {it != c->tune.end() && it->second.best ? it->second.best : 2};
   } else {
     rec = &c->tune[{up ? 1 : 0, mode, cin, cout, log2_rows(units)}];
     if (rec->best) cands = {rec->best};
@@ -882,6 +937,7 @@ void plan_shallow(Batch& b, const lpcc_model* m, const Levels& lv, const Frames&
 // runtime's blocking wait, so the calling thread keeps its core and the host
 // code after the wait does not start on a core woken from sleep.
 hipError_t stream_wait(lpcc_ctx* c, hipStream_t s) {
+  if (c->fixed) return hipStreamSynchronize(s);
   if (!c->poll_ev && hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     c->poll_ev = nullptr;
@@ -1074,6 +1130,74 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
   });
 }
 
+// Octree workspace of a call: staged coordinates, keys and the sort's
+// digit counts, the level kernels' tile counts, and per depth the node keys,
+// codes and first-child rows.  The words from `err` to the end of the sort
+// counts are cleared by one fill.
+struct OctreeShape {
+  int nf = 0, D = 0, base = 0;
+  int64_t ntot = 0;
+  bool need_stage = false;
+  std::vector<int64_t> ub;  // [D+1] upper bounds of the node counts
+};
+struct OctreeBufs {
+  int32_t* xyz_stage = nullptr;
+  uint64_t *kin = nullptr, *kout = nullptr;
+  uint32_t *hist = nullptr, *foff = nullptr, *err = nullptr, *totals = nullptr, *bhist = nullptr;
+  uint32_t *stot = nullptr, *shist = nullptr;
+  char *zero_lo = nullptr, *zero_hi = nullptr;
+  SortPasses sp;
+  int64_t ntiles = 0, sntiles = 0;
+};
+constexpr int kLevelTile = 256;  // one element per thread: many blocks even for one frame
+
+int frame_bits(int nf) {
+  int b = 0;
+  while ((1ll << b) < nf) b++;
+  return b;
+}
+
+void carve_octree(Arena& A, const OctreeShape& S, Levels& lv, OctreeBufs& o) {
+  const int D = S.D;
+  o.sp = sort_passes(3 * D + frame_bits(S.nf));
+  o.ntiles = (S.ntot + kLevelTile - 1) / kLevelTile;
+  o.sntiles = (S.ntot + kSortTile - 1) / kSortTile;
+  const size_t nbh = (size_t)S.nf * S.base * 256;
+  if (S.need_stage) o.xyz_stage = A.take<int32_t>((size_t)S.ntot * 3);
+  o.kin = A.take<uint64_t>(S.ntot);
+  o.kout = A.take<uint64_t>(S.ntot);
+  o.hist = A.take<uint32_t>((size_t)std::max<int64_t>(o.ntiles, 1) * (D + 1));
+  o.foff = A.take<uint32_t>((size_t)S.nf * (D + 1));
+  // zero-initialised block: error words (one per frame, one for the sort),
+  // totals, base counts, code arrays, sort counts
+  o.err = A.take<uint32_t>(S.nf + 1);
+  o.zero_lo = (char*)o.err;
+  o.totals = A.take<uint32_t>(D + 1);
+  o.bhist = nbh ? A.take<uint32_t>(nbh) : nullptr;
+  for (int d = 0; d <= D; d++) lv.code[d] = A.take<uint8_t>(align_up(S.ub[d], 4) + 4);
+  o.stot = A.take<uint32_t>((size_t)o.sp.n * 256);
+  o.shist = A.take<uint32_t>((size_t)o.sp.n * std::max<int64_t>(o.sntiles, 1) * 256);
+  o.zero_hi = (char*)(o.shist + (size_t)o.sp.n * std::max<int64_t>(o.sntiles, 1) * 256);
+  for (int d = 0; d <= D; d++) {
+    lv.key[d] = A.take<uint64_t>(S.ub[d]);
+    lv.cstart[d] = A.take<int32_t>(S.ub[d] + 1);
+  }
+}
+
+OctreeShape octree_shape(int nf, const int64_t* n, int D, int base, bool need_stage) {
+  OctreeShape S;
+  S.nf = nf;
+  S.D = D;
+  S.base = base;
+  S.need_stage = need_stage;
+  S.ub.assign(D + 1, 0);
+  for (int f = 0; f < nf; f++) {
+    S.ntot += n[f];
+    for (int d = 0; d <= D; d++) S.ub[d] += d >= 21 ? n[f] : std::min<int64_t>(n[f], 1ll << (3 * d));
+  }
+  return S;
+}
+
 // Octree of all frames: Morton keys, radix sort, level arrays.  Fills
 // `fr` (after a synchronisation) and the level pointers.
 int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n,
@@ -1081,87 +1205,62 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
                  std::vector<uint32_t>* base_hist = nullptr) {
   const int D = m->D;
   hipStream_t st = c->stream;
-  int64_t ntot = 0;
   std::vector<int64_t> start(nf + 1, 0);
-  for (int f = 0; f < nf; f++) {
-    start[f] = ntot;
-    ntot += n[f];
-  }
-  start[nf] = ntot;
-  int fbits = 0;
-  while ((1ll << fbits) < nf) fbits++;
-  if (3 * D + fbits > 64) {
+  for (int f = 0; f < nf; f++) start[f + 1] = start[f] + n[f];
+  const int64_t ntot = start[nf];
+  if (3 * D + frame_bits(nf) > 64) {
     c->err = "too many frames for this depth";
     return LPCC_E_INVAL;
   }
-  const int end_bit = 3 * D + fbits;
-  size_t sort_tmp = 0;
-  HIPC(hipcub::DeviceRadixSort::SortKeys(nullptr, sort_tmp, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                         (int)std::max<int64_t>(ntot, 1), 0, std::max(end_bit, 1), st));
-  const int tile = 256;  // one element per thread: many blocks even for one frame
-  const int64_t ntiles = (ntot + tile - 1) / tile;
-  // upper bounds of the node count per depth
-  std::vector<int64_t> ub(D + 1, 0);
-  for (int f = 0; f < nf; f++)
-    for (int d = 0; d <= D; d++) {
-      int64_t cap = d >= 21 ? n[f] : std::min<int64_t>(n[f], 1ll << (3 * d));
-      ub[d] += cap;
-    }
   bool need_stage = false;
   for (int f = 0; f < nf; f++)
     if (n[f] > 0 && !is_device_ptr(xyz[f])) need_stage = true;
-
-  int32_t* xyz_stage = nullptr;
-  uint64_t *kin = nullptr, *kout = nullptr;
-  void* tmp = nullptr;
-  uint32_t *err = nullptr, *hist = nullptr, *totals = nullptr, *foff = nullptr, *bhist = nullptr;
-  char *zero_lo = nullptr, *zero_hi = nullptr;
+  const OctreeShape S = octree_shape(nf, n, D, base, need_stage);
   const size_t nbh = (size_t)nf * base * 256;  // code counts of the base depths
-  auto carve = [&](Arena& A) {
-    if (need_stage) xyz_stage = A.take<int32_t>((size_t)ntot * 3);
-    kin = A.take<uint64_t>(ntot);
-    kout = A.take<uint64_t>(ntot);
-    tmp = A.take<char>(sort_tmp);
-    hist = A.take<uint32_t>((size_t)std::max<int64_t>(ntiles, 1) * (D + 1));
-    foff = A.take<uint32_t>((size_t)nf * (D + 1));
-    // zero-initialised block: error words, totals and all code arrays
-    err = A.take<uint32_t>(nf);
-    zero_lo = (char*)err;
-    totals = A.take<uint32_t>(D + 1);
-    if (nbh) bhist = A.take<uint32_t>(nbh);
-    for (int d = 0; d <= D; d++) lv.code[d] = A.take<uint8_t>(align_up(ub[d], 4) + 4);
-    zero_hi = (char*)(lv.code[D] + align_up(ub[D], 4) + 4);
-    for (int d = 0; d <= D; d++) {
-      lv.key[d] = A.take<uint64_t>(ub[d]);
-      lv.cstart[d] = A.take<int32_t>(ub[d] + 1);
-    }
-  };
+  OctreeBufs o;
   Arena meas;
-  meas.measuring = true;
-  carve(meas);
+  carve_octree(meas, S, lv, o);
   int s = reserve(c, 0, meas.off + 4096);
   if (s) return s;
   Arena A;
   A.base = c->dev[0];
   A.cap = c->cap[0];
-  carve(A);
+  carve_octree(A, S, lv, o);
+  uint32_t *err = o.err, *hist = o.hist, *totals = o.totals, *foff = o.foff, *bhist = o.bhist;
 
   HIPC(launch_fill_u32(foff, (int64_t)nf * (D + 1), 0xFFFFFFFFu, st));
-  HIPC(launch_fill_u32((uint32_t*)zero_lo, (int64_t)(align_up((size_t)(zero_hi - zero_lo), 4) / 4), 0, st));
+  HIPC(launch_fill_u32((uint32_t*)o.zero_lo, (int64_t)(align_up((size_t)(o.zero_hi - o.zero_lo), 4) / 4), 0, st));
+  // coordinates on the device (host frames staged), then the keys of up to
+  // kMortonGroup frames per launch with the first pass's digit counts
+  std::vector<const int32_t*> src(nf, nullptr);
   for (int f = 0; f < nf; f++) {
     if (n[f] <= 0) continue;
-    const int32_t* src = xyz[f];
-    if (!is_device_ptr(src)) {
-      HIPC(hipMemcpyAsync(xyz_stage + 3 * start[f], src, (size_t)n[f] * 12, hipMemcpyHostToDevice, st));
-      src = xyz_stage + 3 * start[f];
+    src[f] = xyz[f];
+    if (!is_device_ptr(src[f])) {
+      HIPC(hipMemcpyAsync(o.xyz_stage + 3 * start[f], xyz[f], (size_t)n[f] * 12, hipMemcpyHostToDevice, st));
+      src[f] = o.xyz_stage + 3 * start[f];
     }
-    HIPC(launch_morton(src, n[f], D, (uint64_t)f << (3 * D), kin + start[f], err + f, st));
   }
+  for (int f0 = 0; f0 < nf; f0 += kMortonGroup) {
+    MortonFrames mf;
+    memset(&mf, 0, sizeof(mf));
+    mf.nf = std::min(kMortonGroup, nf - f0);
+    mf.f0 = f0;
+    for (int g = 0; g <= mf.nf; g++) mf.start[g] = start[f0 + g];
+    for (int g = 0; g < mf.nf; g++) mf.xyz[g] = src[f0 + g];
+    HIPC(launch_morton_sort0(mf, D, o.kin, err, o.sp, o.shist, o.stot, st));
+  }
+  uint64_t* sorted = o.kin;
   if (ntot > 0) {
-    size_t tb = sort_tmp;
-    HIPC(hipcub::DeviceRadixSort::SortKeys(tmp, tb, kin, kout, (int)ntot, 0, end_bit, st));
-    HIPC(launch_level_hist(kout, ntot, D, tile, hist, st));
-    HIPC(launch_level_scan(hist, (int)ntiles, D, totals, st));
+    uint64_t *a = o.kin, *b = o.kout;
+    for (int p = 0; p < o.sp.n; p++) {
+      HIPC(launch_sort_pass(a, b, ntot, o.sp, p, o.shist, o.stot, err + nf, st));
+      std::swap(a, b);
+    }
+    sorted = a;
+    const int tile = kLevelTile;
+    HIPC(launch_level_hist(sorted, ntot, D, tile, hist, st));
+    HIPC(launch_level_scan(hist, (int)o.ntiles, D, totals, st));
     LevelOut lo;
     memset(&lo, 0, sizeof(lo));
     for (int d = 0; d <= D; d++) {
@@ -1170,7 +1269,7 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
       lo.cstart[d] = lv.cstart[d];
     }
     lo.frame_off = foff;
-    HIPC(launch_level_write(kout, ntot, D, tile, hist, totals, lo, st));
+    HIPC(launch_level_write(sorted, ntot, D, tile, hist, totals, lo, st));
     if (nbh) {
       // code counts per (frame, base depth); the node counts are still on
       // the device, so the range covers the upper bounds and the kernel
@@ -1183,9 +1282,8 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
       for (int d = 0; d < base; d++) {
         bl.key[d] = lv.key[d];
         bl.code[d] = lv.code[d];
-        bl.start[d + 1] = bl.start[d] + ub[d];
+        bl.start[d + 1] = bl.start[d] + S.ub[d];
       }
-      HIPC(launch_fill_u32(bhist, (int64_t)nbh, 0, st));
       HIPC(launch_base_hist(bl, bhist, st));
     }
   }
@@ -1202,6 +1300,10 @@ int build_octree(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const*
   HIPC(stream_wait(c, st));
   const uint32_t* h_foff = (const uint32_t*)h8;
   const uint32_t* h_err = (const uint32_t*)(h8 + ((const char*)err - rb0));
+  if (h_err[nf] & ERR_SORT) {
+    c->err = "radix sort produced an impossible rank";
+    return LPCC_E_DEVICE;
+  }
   const uint32_t* h_tot = (const uint32_t*)(h8 + ((const char*)totals - rb0));
   if (base_hist) {
     base_hist->assign(nbh, 0u);
@@ -1244,6 +1346,143 @@ struct OutSpec {
   const size_t* cap;
   size_t* out_len;
 };
+
+// Header bytes of the base tables per frame: B, then per depth m and m
+// (code, count) pairs of the codes present.
+std::vector<size_t> base_table_bytes(const std::vector<uint32_t>& bhist, int nf, int nb) {
+  std::vector<size_t> t(nf, 0);
+  for (int f = 0; f < nf && nb > 0; f++) {
+    t[f] = 1;
+    for (int d = 0; d < nb; d++) {
+      t[f] += 1;
+      for (int k = 1; k < 256; k++) t[f] += bhist.empty() || bhist[((size_t)f * nb + d) * 256 + k] ? 5 : 0;
+    }
+  }
+  return t;
+}
+
+// Chunk table, coder scratch and per-frame output staging of an encode call
+struct EncLayout {
+  std::vector<Chunk> chunks;
+  std::vector<int> chunk_frame;
+  int64_t scratch_bytes = 0;
+  std::vector<size_t> stage_off;
+  size_t stage_bytes = 0;
+  std::vector<int64_t> dbase;  // [D+1] first node of every depth in the per-call node arrays
+};
+
+EncLayout enc_layout(const Frames& fr, int D, int cl, bool probe, const std::vector<size_t>& tbytes) {
+  EncLayout L;
+  const int nf = fr.nf;
+  L.dbase.assign(D + 1, 0);
+  for (int d = 0; d < D; d++) L.dbase[d + 1] = L.dbase[d] + fr.tot[d];
+  L.stage_off.assign(nf, 0);
+  if (probe) return L;
+  size_t nch_all = 0;
+  for (int f = 0; f < nf; f++)
+    for (int d = 0; d < D; d++) nch_all += (size_t)nchunks_of(fr.N[f][d], cl);
+  L.chunks.reserve(nch_all);
+  L.chunk_frame.reserve(nch_all);
+  for (int f = 0; f < nf; f++)
+    for (int d = 0; d < D; d++) {
+      const int64_t Nfd = fr.N[f][d];
+      for (int64_t k = 0; k < nchunks_of(Nfd, cl); k++) {
+        Chunk ch;
+        ch.node0 = L.dbase[d] + fr.off[f][d] + (k << cl);
+        ch.count = (int32_t)std::min<int64_t>(1ll << cl, Nfd - (k << cl));
+        ch.pad_ = 0;
+        ch.scratch = L.scratch_bytes;
+        L.scratch_bytes += align_up(2 * (size_t)ch.count + 16, 16);
+        L.chunks.push_back(ch);
+        L.chunk_frame.push_back(f);
+      }
+    }
+  // per-frame output staging (host outputs and frames that fail): header
+  // bound + the frame's chunk scratch bound
+  std::vector<size_t> fbytes(nf, 16 + 4 * (size_t)D);
+  for (int f = 0; f < nf; f++) fbytes[f] += tbytes[f];
+  for (size_t k = 0; k < L.chunks.size(); k++)
+    fbytes[L.chunk_frame[k]] += 2 + align_up(2 * (size_t)L.chunks[k].count + 16, 16);
+  for (int f = 0; f < nf; f++) {
+    L.stage_off[f] = L.stage_bytes;
+    L.stage_bytes += align_up(fbytes[f], 256);
+  }
+  return L;
+}
+
+struct EncBufs {
+  uint32_t* sf = nullptr;
+  int32_t* cdf_stage = nullptr;
+  uint8_t* scratch = nullptr;
+  uint32_t* lens = nullptr;
+  uint8_t* stage = nullptr;
+};
+
+void carve_encode(Arena& A, const lpcc_model* m, const Frames& fr, int last, const std::vector<bool>& wanted, int nb,
+                  int probe_level, bool cdf_dev, const EncLayout& L, ModelBufs& B, EncBufs& o) {
+  carve_model(A, m, fr, last, wanted, B, nb);
+  if (probe_level < 0) {
+    o.sf = A.take<uint32_t>(L.dbase[m->D]);
+    o.scratch = A.take<uint8_t>(L.scratch_bytes);
+    o.lens = A.take<uint32_t>(L.chunks.size());
+    o.stage = A.take<uint8_t>(L.stage_bytes);
+  } else if (!cdf_dev) {
+    o.cdf_stage = A.take<int32_t>((size_t)fr.tot[probe_level] * 256);
+  }
+}
+
+// Descriptor bytes a call may upload: segment and tile tables, chunk tables
+// and headers stay far below this bound.
+size_t desc_bound(const Frames& fr, size_t nch) {
+  int64_t rows = 0;
+  for (int64_t t : fr.tot) rows += t;
+  return ((size_t)1 << 20) + 16 * (size_t)rows + 64 * nch;
+}
+
+// Frames whose node counts are the upper bounds of an encode of n[f] points
+Frames bound_frames(int nf, const int64_t* n, int D) {
+  Frames fr;
+  fr.nf = nf;
+  fr.tot.assign(D + 1, 0);
+  fr.N.assign(nf, std::vector<int64_t>(D + 1, 0));
+  fr.off.assign(nf, std::vector<int64_t>(D + 1, 0));
+  for (int f = 0; f < nf; f++)
+    for (int d = 0; d <= D; d++) {
+      fr.N[f][d] = d >= 21 ? n[f] : std::min<int64_t>(n[f], 1ll << (3 * d));
+      fr.off[f][d] = fr.tot[d];
+      fr.tot[d] += fr.N[f][d];
+    }
+  return fr;
+}
+
+}  // namespace
+
+// Upper bounds of the three arenas an encode of these frames needs (the
+// node count of every depth at its largest: min(points, 8^d); every depth
+// modelled, which needs the most).
+void lpcc::encode_workspace_bound(const lpcc_model* m, int nf, const int64_t* n, int cl, bool host_in,
+                                  size_t out[3]) {
+  const int D = m->D, nb = 0;
+  const OctreeShape S = octree_shape(nf, n, D, nb, host_in);
+  Levels lv;
+  OctreeBufs o;
+  Arena a0;
+  carve_octree(a0, S, lv, o);
+  const Frames fr = bound_frames(nf, n, D);
+  std::vector<uint32_t> none;
+  const EncLayout EL = enc_layout(fr, D, cl, false, base_table_bytes(none, nf, nb));
+  std::vector<bool> wanted(D, true);
+  for (int d = 0; d < nb && d < D; d++) wanted[d] = false;
+  ModelBufs B;
+  EncBufs eb;
+  Arena a1;
+  carve_encode(a1, m, fr, D - 1, wanted, nb, -1, false, EL, B, eb);
+  out[0] = a0.off + 4096;
+  out[1] = a1.off + 4096;
+  out[2] = desc_bound(fr, EL.chunks.size());
+}
+
+namespace {
 
 int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* xyz, const int64_t* n, int cl,
                 OutSpec os, int* status, int probe_level, int32_t* cdf_out, int64_t cdf_cap, int64_t* n_nodes) {
@@ -1291,81 +1530,28 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
     }
   }
   // ---- model phase buffers
-  ModelBufs B;
-  uint32_t* sf = nullptr;
-  int32_t* cdf_stage = nullptr;
-  uint8_t* scratch = nullptr;
-  uint32_t* lens = nullptr;
-  std::vector<int64_t> dbase(D + 1, 0);
-  for (int d = 0; d < D; d++) dbase[d + 1] = dbase[d] + fr.tot[d];
-  // chunk table (encode only)
-  std::vector<Chunk> chunks;
-  std::vector<int> chunk_frame;
-  int64_t scratch_bytes = 0;
-  if (!probe) {
-    size_t nch_all = 0;
-    for (int f = 0; f < nf; f++)
-      for (int d = 0; d < D; d++) nch_all += (size_t)nchunks_of(fr.N[f][d], cl);
-    chunks.reserve(nch_all);
-    chunk_frame.reserve(nch_all);
-    for (int f = 0; f < nf; f++)
-      for (int d = 0; d < D; d++) {
-        const int64_t Nfd = fr.N[f][d];
-        for (int64_t k = 0; k < nchunks_of(Nfd, cl); k++) {
-          Chunk ch;
-          ch.node0 = dbase[d] + fr.off[f][d] + (k << cl);
-          ch.count = (int32_t)std::min<int64_t>(1ll << cl, Nfd - (k << cl));
-          ch.pad_ = 0;
-          ch.scratch = scratch_bytes;
-          scratch_bytes += align_up(2 * (size_t)ch.count + 16, 16);
-          chunks.push_back(ch);
-          chunk_frame.push_back(f);
-        }
-      }
-  }
+  std::vector<size_t> tbytes = base_table_bytes(bhist, nf, nb);
+  const EncLayout EL = enc_layout(fr, D, cl, probe, tbytes);
+  const std::vector<Chunk>& chunks = EL.chunks;
+  const std::vector<int>& chunk_frame = EL.chunk_frame;
+  const std::vector<int64_t>& dbase = EL.dbase;
+  const std::vector<size_t>& stage_off = EL.stage_off;
   const bool cdf_dev = probe && is_device_ptr(cdf_out);
-  // per-frame output staging (host outputs and frames that fail): header
-  // bound + the frame's chunk scratch bound
-  std::vector<size_t> stage_off(nf, 0);
-  size_t stage_bytes = 0;
-  // header bytes of the base tables per frame: B, then per depth m and m pairs
-  std::vector<size_t> tbytes(nf, 0);
-  for (int f = 0; f < nf && nb > 0; f++) {
-    tbytes[f] = 1;
-    for (int d = 0; d < nb; d++) {
-      tbytes[f] += 1;
-      for (int k = 1; k < 256; k++) tbytes[f] += bhist[((size_t)f * nb + d) * 256 + k] ? 5 : 0;
-    }
-  }
-  if (!probe) {
-    std::vector<size_t> fbytes(nf, 16 + 4 * (size_t)D);
-    for (int f = 0; f < nf; f++) fbytes[f] += tbytes[f];
-    for (size_t k = 0; k < chunks.size(); k++) fbytes[chunk_frame[k]] += 2 + align_up(2 * (size_t)chunks[k].count + 16, 16);
-    for (int f = 0; f < nf; f++) {
-      stage_off[f] = stage_bytes;
-      stage_bytes += align_up(fbytes[f], 256);
-    }
-  }
-  uint8_t* stage = nullptr;
-  auto carve = [&](Arena& A) {
-    carve_model(A, m, fr, last, wanted, B, nb);
-    if (!probe) {
-      sf = A.take<uint32_t>(dbase[D]);
-      scratch = A.take<uint8_t>(scratch_bytes);
-      lens = A.take<uint32_t>(chunks.size());
-      stage = A.take<uint8_t>(stage_bytes);
-    } else if (!cdf_dev) {
-      cdf_stage = A.take<int32_t>((size_t)fr.tot[probe_level] * 256);
-    }
-  };
+  ModelBufs B;
+  EncBufs eb;
   Arena meas;
-  carve(meas);
+  carve_encode(meas, m, fr, last, wanted, nb, probe ? probe_level : -1, cdf_dev, EL, B, eb);
   s = reserve(c, 1, meas.off + 4096);
   if (s) return s;
   Arena A;
   A.base = c->dev[1];
   A.cap = c->cap[1];
-  carve(A);
+  carve_encode(A, m, fr, last, wanted, nb, probe ? probe_level : -1, cdf_dev, EL, B, eb);
+  uint32_t* sf = eb.sf;
+  int32_t* cdf_stage = eb.cdf_stage;
+  uint8_t* scratch = eb.scratch;
+  uint32_t* lens = eb.lens;
+  uint8_t* stage = eb.stage;
 
   Batch b;
   b.ctx = c;
@@ -1403,7 +1589,7 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   // codes and runs beside the shallow chain; the predictor of the shallow
   // depths runs beside the deep ResBlock and upsampling.
   c->sync_used = 0;
-  bool two = c->time_family.empty() && !c->graphs;
+  bool two = c->time_family.empty() && !c->graphs && !c->fixed;
   if (two && !c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     c->side = nullptr;
@@ -1813,6 +1999,115 @@ int read_headers(lpcc_ctx* c, int nf, const uint8_t* const* bs, const size_t* le
   return LPCC_OK;
 }
 
+// Decode workspace: per depth keys, codes and first-child rows of all
+// frames, the payloads, the CDF rows of the largest depth, error words,
+// chunk child counts, staged coordinates, and the model buffers.
+struct DecBufs {
+  uint8_t* payload = nullptr;
+  uint16_t* cdf16 = nullptr;
+  uint32_t *err = nullptr, *csum = nullptr;
+  int32_t* xyz_stage = nullptr;
+};
+
+void carve_decode(Arena& A, const lpcc_model* m, const Frames& fr, size_t paybytes, size_t maxch, bool host_out,
+                  int nb, Levels& lv, ModelBufs& B, DecBufs& o) {
+  const int D = m->D;
+  int64_t maxN = 0;
+  for (int d = 0; d <= D; d++) maxN = std::max(maxN, fr.tot[d]);
+  std::vector<bool> wanted(D, true);
+  for (int d = 0; d < nb && d < D; d++) wanted[d] = false;
+  for (int d = 0; d <= D; d++) {
+    lv.key[d] = A.take<uint64_t>(fr.tot[d]);
+    lv.code[d] = A.take<uint8_t>(align_up(fr.tot[d], 4) + 4);
+    lv.cstart[d] = A.take<int32_t>(fr.tot[d] + 1);
+  }
+  o.payload = A.take<uint8_t>(paybytes);
+  o.cdf16 = A.take<uint16_t>((size_t)maxN * 256);
+  o.err = A.take<uint32_t>(4);
+  o.csum = A.take<uint32_t>(maxch + 1);
+  if (host_out) o.xyz_stage = A.take<int32_t>((size_t)fr.tot[D] * 3);
+  carve_model(A, m, fr, D - 1, wanted, B, nb);
+}
+
+// Arenas a decode of one stream needs, from its depth counts (`N`, D + 1
+// entries), base depth and chunk size.  A chunk's payload is at most two
+// bytes per symbol (every renormalisation emits at most two) and the flush.
+void decode_workspace(const lpcc_model* m, const int64_t* N, int nb, int cl, size_t out[3]) {
+  const int D = m->D;
+  Frames fr;
+  fr.nf = 1;
+  fr.tot.assign(N, N + D + 1);
+  fr.N.assign(1, fr.tot);
+  fr.off.assign(1, std::vector<int64_t>(D + 1, 0));
+  size_t maxch = 0, nch = 0, pay = 0;
+  for (int d = 0; d < D; d++) {
+    maxch = std::max<size_t>(maxch, (size_t)nchunks_of(N[d], cl));
+    nch += (size_t)nchunks_of(N[d], cl);
+    pay += 2 * (size_t)N[d];
+  }
+  pay += 8 * nch;
+  Levels lv;
+  ModelBufs B;
+  DecBufs db;
+  Arena a;
+  carve_decode(a, m, fr, align_up(pay, 16), maxch, true, nb, lv, B, db);
+  out[0] = 0;
+  out[1] = a.off + 4096;
+  out[2] = desc_bound(fr, nch);
+}
+
+}  // namespace
+
+void lpcc::decode_workspace_bound(const lpcc_model* m, int nf, const int64_t* const* N, const int* cl,
+                                  size_t out[3]) {
+  const int D = m->D;
+  Frames fr;
+  fr.nf = nf;
+  fr.tot.assign(D + 1, 0);
+  fr.N.assign(nf, std::vector<int64_t>(D + 1, 0));
+  fr.off.assign(nf, std::vector<int64_t>(D + 1, 0));
+  std::vector<size_t> dch(D, 0);
+  size_t nch = 0, pay = 0;
+  for (int f = 0; f < nf; f++)
+    for (int d = 0; d <= D; d++) {
+      fr.N[f][d] = N[f][d];
+      fr.off[f][d] = fr.tot[d];
+      fr.tot[d] += N[f][d];
+      if (d < D) {
+        const size_t k = (size_t)nchunks_of(N[f][d], cl[f]);
+        dch[d] += k;
+        nch += k;
+        pay += 2 * (size_t)N[f][d] + 8 * k + 16;
+      }
+    }
+  size_t maxch = 0;
+  for (int d = 0; d < D; d++) maxch = std::max(maxch, dch[d]);
+  Levels lv;
+  ModelBufs B;
+  DecBufs db;
+  Arena a;
+  carve_decode(a, m, fr, align_up(pay, 16), maxch, true, 0, lv, B, db);
+  out[0] = 0;
+  out[1] = a.off + 4096;
+  out[2] = desc_bound(fr, nch);
+}
+
+void lpcc::ctx_caps(const lpcc_ctx* c, size_t caps[3]) {
+  for (int i = 0; i < 3; i++) caps[i] = c->fixed ? 0 : c->cap[i];
+}
+void lpcc::ctx_set_budget(lpcc_ctx* c, size_t budget) { c->budget = budget; }
+void lpcc::ctx_trim(lpcc_ctx* c) {
+  if (c->fixed) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (int i = 0; i < 3; i++) {
+    if (c->dev[i]) (void)hipFree(c->dev[i]);
+    c->dev[i] = nullptr;
+    c->cap[i] = 0;
+  }
+}
+
+namespace {
+
 int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* bs, const size_t* len,
                 int32_t* const* xyz_out, const int64_t* cap, int64_t* n_out, int* status) {
   const int D = m->D, C = m->C, k0 = m->k0;
@@ -1902,43 +2197,27 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   }
   Levels lv;
   ModelBufs B;
-  uint8_t* payload = nullptr;
-  uint16_t* cdf16 = nullptr;
-  uint32_t *err = nullptr, *csum = nullptr;
-  int32_t* xyz_stage = nullptr;
-  int64_t maxN = 0;
   size_t maxch = 0;
   for (int d = 0; d < D; d++) maxch = std::max(maxch, dchunks[d].size());
-  for (int d = 0; d <= D; d++) maxN = std::max(maxN, fr.tot[d]);
-  std::vector<bool> wanted(D, true);
-  for (int d = 0; d < nb; d++) wanted[d] = false;
   std::vector<bool> xdev(nf, false);
   bool any_host_out = false;
   for (int f : live) {
     xdev[f] = is_device_ptr(xyz_out[f]);
     if (!xdev[f]) any_host_out = true;
   }
-  auto carve = [&](Arena& A) {
-    for (int d = 0; d <= D; d++) {
-      lv.key[d] = A.take<uint64_t>(fr.tot[d]);
-      lv.code[d] = A.take<uint8_t>(align_up(fr.tot[d], 4) + 4);
-      lv.cstart[d] = A.take<int32_t>(fr.tot[d] + 1);
-    }
-    payload = A.take<uint8_t>(paybytes);
-    cdf16 = A.take<uint16_t>((size_t)maxN * 256);
-    err = A.take<uint32_t>(4);
-    csum = A.take<uint32_t>(maxch + 1);
-    if (any_host_out) xyz_stage = A.take<int32_t>((size_t)fr.tot[D] * 3);
-    carve_model(A, m, fr, D - 1, wanted, B, nb);
-  };
+  DecBufs db;
   Arena meas;
-  carve(meas);
+  carve_decode(meas, m, fr, paybytes, maxch, any_host_out, nb, lv, B, db);
   int s = reserve(c, 1, meas.off + 4096);
   if (s) return s;
   Arena A;
   A.base = c->dev[1];
   A.cap = c->cap[1];
-  carve(A);
+  carve_decode(A, m, fr, paybytes, maxch, any_host_out, nb, lv, B, db);
+  uint8_t* payload = db.payload;
+  uint16_t* cdf16 = db.cdf16;
+  uint32_t *err = db.err, *csum = db.csum;
+  int32_t* xyz_stage = db.xyz_stage;
   size_t desc_off = 0;
 
   // payloads and roots: one device-resident stream is read in place (its
@@ -1985,7 +2264,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   // table of depth d, and the neighbour table of depth d+1 only the
   // expansion, so both run on a second stream beside the chain.
   c->sync_used = 0;
-  bool two = c->time_family.empty() && !c->graphs;
+  bool two = c->time_family.empty() && !c->graphs && !c->fixed;
   if (two && !c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     c->side = nullptr;
@@ -2249,12 +2528,18 @@ int lpcc_model_info(const lpcc_model* m, int* C, int* D, int* n_deep, uint32_t* 
   return LPCC_OK;
 }
 
-int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out) {
+int lpcc_ctx_create(int device, void* hip_stream, size_t hbm_budget, lpcc_ctx** out) {
   if (!out) return LPCC_E_INVAL;
   *out = nullptr;
   if (hipSetDevice(device) != hipSuccess) return LPCC_E_DEVICE;
   lpcc_ctx* c = new lpcc_ctx();
   c->device = device;
+  c->budget = hbm_budget;
+  // companion of the allocation-free entry point (its block is looked up on
+  // the first such call on the device)
+  c->noalloc = new lpcc_ctx();
+  c->noalloc->device = device;
+  c->noalloc->fixed = true;
   c->stream = (hipStream_t)hip_stream;
   if (!c->stream) {
     if (hipStreamCreate(&c->own_stream) != hipSuccess) {
@@ -2263,6 +2548,7 @@ int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out) {
     }
     c->stream = c->own_stream;
   }
+  c->noalloc->stream = c->stream;
   *out = c;
   return LPCC_OK;
 }
@@ -2270,9 +2556,10 @@ int lpcc_ctx_create(int device, void* hip_stream, lpcc_ctx** out) {
 void lpcc_ctx_free(lpcc_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  for (int i = 0; i < 3; i++)
+  if (c->noalloc) lpcc_ctx_free(c->noalloc);
+  for (int i = 0; i < 3 && !c->fixed; i++)
     if (c->dev[i]) (void)hipFree(c->dev[i]);
-  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->pinned && !c->fixed) (void)hipHostFree(c->pinned);
   for (auto& e : c->ev) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
@@ -2292,13 +2579,43 @@ void lpcc_ctx_free(lpcc_ctx* c) {
 
 const char* lpcc_last_error(const lpcc_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int lpcc_peek_header(const uint8_t* bs, size_t len, int* D, int64_t* n_points) {
+int lpcc_ctx_workspace(const lpcc_ctx* c, size_t* held, size_t* peak) {
+  if (!c) return LPCC_E_INVAL;
+  if (held) *held = held_bytes(c);
+  if (peak) *peak = c->peak;
+  return LPCC_OK;
+}
+
+int lpcc_peek_header(const uint8_t* bs, size_t len, int* D, int64_t* n_points, size_t* max_workspace) {
   if (!bs) return LPCC_E_INVAL;
   if (len < 16 || bs[0] != 'L' || bs[1] != 'P' || bs[2] != 'C' || bs[3] != '1' || (bs[4] != 1 && bs[4] != 2))
     return LPCC_E_CORRUPT;
   if (bs[5] < 1 || bs[5] > kMaxD) return LPCC_E_CORRUPT;
   if (D) *D = bs[5];
   if (n_points) *n_points = rd32(bs + 12);
+  if (max_workspace) {
+    *max_workspace = 0;
+    Header H;  // `len` bytes of a stream of unknown length
+    const int st = parse_header(bs, len, (size_t)1 << 62, H, false);
+    if (st == LPCC_OK && H.n_deep <= H.D - 1) {
+      // the larger of the two schedules at the widest model
+      size_t best = 0;
+      for (int xfp = 0; xfp <= 1; xfp++) {
+        lpcc_model shape;
+        shape.C = 64;
+        shape.D = H.D;
+        shape.n_deep = H.n_deep;
+        shape.k0 = H.D - H.n_deep - 1;
+        shape.xfp = xfp;
+        size_t w[3];
+        decode_workspace(&shape, H.N.data(), H.B, H.cl, w);
+        best = std::max(best, w[0] + w[1] + w[2]);
+      }
+      *max_workspace = best;
+    } else if (st != LPCC_OK && st != LPCC_E_CAPACITY) {
+      return st;
+    }
+  }
   return LPCC_OK;
 }
 

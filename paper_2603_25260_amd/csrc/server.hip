@@ -3,11 +3,16 @@
 //
 // A fixed pool of slots runs concurrently; every slot owns a HIP stream and a
 // context (its own workspace, where a frame's octree and features stay
-// resident while it is processed).  A job is admitted as soon as a slot is
-// free and its estimated device footprint fits in the memory budget next to
-// the jobs already running; a free slot takes the oldest admissible job and
-// up to max_batch - 1 queued jobs of the same model and kind, which then
-// share every launch of the batched pipeline.  Jobs that arrive while
+// resident while it is processed).  Admission is by device memory: the
+// workspace the slots' contexts hold counts as in use, and a job is admitted
+// when the growth of its slot's workspace that it may need (an upper bound
+// computed by the library's own carving code from the job's point count or
+// its stream's depth counts) fits in the budget beside the slots' holdings
+// and the growth granted to running jobs; each context is capped at what it
+// was granted, so the workspace never exceeds the budget.  When a waiting job
+// does not fit, idle slots release their workspace.  A free slot takes the
+// oldest admissible job and up to max_batch - 1 queued jobs of the same model
+// and kind, which then share every launch of the batched pipeline.  Jobs that arrive while
 // others are on the device are admitted into slots as they free up, so work
 // of different requests overlaps on the device.  Results are byte-identical
 // to the isolated calls (the batched calls are).
@@ -34,8 +39,11 @@ struct Pending {
   lpcc_job job;
   uint64_t ticket;
   int64_t t_arrival;
-  int64_t points;  // encode: input points; decode: points in the stream header
-  size_t est;      // estimated device bytes while it runs
+  int64_t points;            // encode: input points; decode: points in the stream header
+  std::vector<int64_t> N;    // decode: node counts of every depth (header)
+  int cl = 8;                // decode: chunk size of the stream
+  bool host_in = false;      // encode: coordinates in host memory (staged)
+  size_t need[3] = {0, 0, 0};  // workspace bound of the job alone (per arena)
 };
 
 }  // namespace
@@ -46,7 +54,11 @@ struct lpcc_server {
   std::vector<int> model_C;
   int max_batch = 1;
   size_t budget = 0;
-  size_t in_use = 0;
+  size_t held = 0;     // workspace the slots' contexts hold (as of their last job)
+  size_t granted = 0;  // growth granted to running jobs
+  size_t peak = 0;     // largest held + granted
+  std::vector<size_t> slot_held;
+  std::vector<bool> slot_busy;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Pending> queue;
@@ -63,10 +75,40 @@ struct lpcc_server {
 
 namespace {
 
-size_t estimate_bytes(int C, int64_t points) {
-  // octree arrays + features + neighbour tables + coder buffers, measured
-  // at roughly (200 + 12 C) bytes per point, plus fixed tables
-  return (size_t)std::max<int64_t>(points, 1) * (size_t)(200 + 12 * C) + ((size_t)8 << 20);
+// Workspace bound of a batch of jobs (per arena: octree, model, descriptors)
+void bound_of(lpcc_server* S, const std::vector<const Pending*>& b, size_t need[3]) {
+  const lpcc_model* m = S->models[b[0]->job.model];
+  if (b[0]->job.kind == 0) {
+    std::vector<int64_t> n;
+    bool host = false;
+    for (auto* p : b) {
+      n.push_back(p->points);
+      host = host || p->host_in;
+    }
+    lpcc::encode_workspace_bound(m, (int)b.size(), n.data(), b[0]->job.chunk_log2, host, need);
+  } else {
+    std::vector<const int64_t*> N;
+    std::vector<int> cl;
+    for (auto* p : b) {
+      N.push_back(p->N.data());
+      cl.push_back(p->cl);
+    }
+    lpcc::decode_workspace_bound(m, (int)b.size(), N.data(), cl.data(), need);
+  }
+}
+
+// Growth of a slot's arenas up to the bound
+size_t growth_of(lpcc_ctx* ctx, const size_t need[3]) {
+  size_t caps[3];
+  lpcc::ctx_caps(ctx, caps);
+  size_t g = 0;
+  for (int a = 0; a < 3; a++) g += need[a] > caps[a] ? need[a] - caps[a] : 0;
+  return g;
+}
+
+bool same_kind(const Pending& a, const Pending& b) {
+  return a.job.kind == b.job.kind && a.job.model == b.job.model &&
+         (a.job.kind == 1 || a.job.chunk_log2 == b.job.chunk_log2);
 }
 
 void worker_main(lpcc_server* S, int slot) {
@@ -74,32 +116,69 @@ void worker_main(lpcc_server* S, int slot) {
   lpcc_ctx* ctx = S->ctxs[slot];
   for (;;) {
     std::vector<Pending> batch;
+    size_t growth = 0;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       for (;;) {
         if (S->stop && S->queue.empty()) return;
-        // oldest job that fits, then same-kind jobs of the same model
-        auto it = S->queue.begin();
-        for (; it != S->queue.end(); ++it)
-          if (S->in_use + it->est <= S->budget || S->running == 0) break;
+        auto fits = [&](size_t g) { return S->held + S->granted + g <= S->budget; };
+        // oldest job whose growth fits; once, idle slots give their
+        // workspace back before the queue is scanned again
+        auto pick = [&]() -> std::deque<Pending>::iterator {
+          for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+            growth = growth_of(ctx, it->need);
+            if (fits(growth)) return it;
+          }
+          return S->queue.end();
+        };
+        auto it = pick();
+        if (it == S->queue.end() && !S->queue.empty()) {
+          bool freed = false;
+          for (size_t k = 0; k < S->ctxs.size(); k++)
+            if (!S->slot_busy[k] && S->slot_held[k] > 0) {
+              lpcc::ctx_trim(S->ctxs[k]);
+              S->held -= S->slot_held[k];
+              S->slot_held[k] = 0;
+              freed = true;
+            }
+          if (freed) it = pick();
+        }
+        if (it == S->queue.end() && !S->queue.empty() && S->granted == 0 && S->running == 0) {
+          // nothing runs and nothing else can free memory: the oldest job
+          // gets what the budget leaves (it fails with LPCC_E_NOMEM if that
+          // is too little)
+          it = S->queue.begin();
+          growth = S->budget > S->held ? S->budget - S->held : 0;
+        }
         if (it != S->queue.end()) {
           batch.push_back(*it);
-          S->in_use += it->est;
-          const Pending head = *it;
           S->queue.erase(it);
+          // same-kind jobs of the same model, while the batch's growth fits
           for (auto jt = S->queue.begin(); jt != S->queue.end() && (int)batch.size() < S->max_batch;) {
-            const bool same = jt->job.kind == head.job.kind && jt->job.model == head.job.model &&
-                              (head.job.kind == 1 || jt->job.chunk_log2 == head.job.chunk_log2);
-            if (same && S->in_use + jt->est <= S->budget) {
-              S->in_use += jt->est;
+            if (!same_kind(*jt, batch[0])) {
+              ++jt;
+              continue;
+            }
+            std::vector<const Pending*> v;
+            for (auto& p : batch) v.push_back(&p);
+            v.push_back(&*jt);
+            size_t need[3];
+            bound_of(S, v, need);
+            const size_t g = growth_of(ctx, need);
+            if (fits(g)) {
+              growth = g;
               batch.push_back(*jt);
               jt = S->queue.erase(jt);
             } else {
               ++jt;
             }
           }
+          S->granted += growth;
+          S->peak = std::max(S->peak, S->held + S->granted);
+          S->slot_busy[slot] = true;
           S->admitted += (int64_t)batch.size();
           S->running += (int64_t)batch.size();
+          lpcc::ctx_set_budget(ctx, S->slot_held[slot] + growth);
           break;
         }
         S->cv_work.wait(lk);
@@ -145,8 +224,15 @@ void worker_main(lpcc_server* S, int slot) {
           if (status[i] == LPCC_OK) status[i] = st;
     }
     const int64_t t_done = now_ns();
+    size_t caps[3];
+    lpcc::ctx_caps(ctx, caps);
     {
       std::lock_guard<std::mutex> lk(S->mu);
+      const size_t now_held = caps[0] + caps[1] + caps[2];
+      S->held = S->held - S->slot_held[slot] + now_held;
+      S->slot_held[slot] = now_held;
+      S->granted -= growth;
+      S->slot_busy[slot] = false;
       for (int i = 0; i < nb; i++) {
         lpcc_done d;
         memset(&d, 0, sizeof(d));
@@ -160,7 +246,6 @@ void worker_main(lpcc_server* S, int slot) {
         d.t_done_ns = t_done;
         d.batch = nb;
         S->done.push_back(d);
-        S->in_use -= batch[i].est;
         S->lat_ms.push_back((double)(t_done - batch[i].t_arrival) / 1e6);
         if (status[i] == LPCC_OK) S->pts_done += batch[i].points;
         if (S->first_arrival < 0 || batch[i].t_arrival < S->first_arrival) S->first_arrival = batch[i].t_arrival;
@@ -205,6 +290,8 @@ int lpcc_server_create(int device, const lpcc_model* const* models, int n_models
     hbm_budget = fr - fr / 8;  // leave headroom for the caller
   }
   S->budget = hbm_budget;
+  S->slot_held.assign(n_slots, 0);
+  S->slot_busy.assign(n_slots, false);
   for (int k = 0; k < n_slots; k++) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -213,7 +300,7 @@ int lpcc_server_create(int device, const lpcc_model* const* models, int n_models
     }
     S->streams.push_back(st);
     lpcc_ctx* c = nullptr;
-    int s = lpcc_ctx_create(device, st, &c);
+    int s = lpcc_ctx_create(device, st, 0, &c);
     if (s) {
       lpcc_server_free(S);
       return s;
@@ -232,30 +319,45 @@ int lpcc_server_submit(lpcc_server* S, const lpcc_job* job, uint64_t* ticket) {
   Pending p;
   p.job = *job;
   p.t_arrival = job->t_arrival_ns > 0 ? job->t_arrival_ns : now_ns();
+  hipPointerAttribute_t a;
+  const bool dev = hipPointerGetAttributes(&a, job->in) == hipSuccess &&
+                   (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged);
+  if (!dev) (void)hipGetLastError();
   if (job->kind == 0) {
     if (job->n_points < 0 || job->chunk_log2 < 4 || job->chunk_log2 > 14) return LPCC_E_INVAL;
     p.points = job->n_points;
+    p.host_in = !dev;
   } else {
-    // points from the stream header (host streams directly, device ones by copy)
-    uint8_t h[16];
-    hipPointerAttribute_t a;
-    bool dev = hipPointerGetAttributes(&a, job->in) == hipSuccess &&
-               (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged);
-    if (!dev) (void)hipGetLastError();
+    // depth counts from the stream header (host streams directly, device
+    // ones by copy): they bound the decode's workspace
+    uint8_t h[16 + 4 * lpcc::kMaxD];
     if (job->in_len < 16) return LPCC_E_CORRUPT;
+    const size_t nh = std::min(job->in_len, sizeof(h));
     if (dev) {
       (void)hipSetDevice(S->device);
-      if (hipMemcpy(h, job->in, 16, hipMemcpyDeviceToHost) != hipSuccess) return LPCC_E_DEVICE;
+      if (hipMemcpy(h, job->in, nh, hipMemcpyDeviceToHost) != hipSuccess) return LPCC_E_DEVICE;
     } else {
-      memcpy(h, job->in, 16);
+      memcpy(h, job->in, nh);
     }
     int D = 0;
     int64_t np = 0;
-    int s = lpcc_peek_header(h, 16, &D, &np);
+    int s = lpcc_peek_header(h, nh, &D, &np, nullptr);
     if (s) return s;
+    int mD = 0;
+    lpcc_model_info(S->models[job->model], nullptr, &mD, nullptr, nullptr);
+    if (D != mD || nh < 16 + 4 * (size_t)D) return LPCC_E_CORRUPT;
     p.points = np;
+    p.cl = h[7];
+    if (p.cl < 4 || p.cl > 14) return LPCC_E_CORRUPT;
+    p.N.assign(D + 1, 0);
+    auto rd = [&](size_t o) {
+      return (int64_t)((uint32_t)h[o] | ((uint32_t)h[o + 1] << 8) | ((uint32_t)h[o + 2] << 16) |
+                       ((uint32_t)h[o + 3] << 24));
+    };
+    p.N[D] = rd(12);
+    for (int d = 0; d < D; d++) p.N[d] = rd(16 + 4 * (size_t)d);
   }
-  p.est = estimate_bytes(S->model_C[job->model], p.points);
+  bound_of(S, {&p}, p.need);
   {
     std::lock_guard<std::mutex> lk(S->mu);
     p.ticket = S->next_ticket++;
@@ -310,8 +412,9 @@ int lpcc_server_stats(lpcc_server* S, lpcc_stats* st) {
   st->admitted = S->admitted;
   st->queued = (int64_t)S->queue.size();
   st->running = S->running;
-  st->bytes_in_use = S->in_use;
+  st->bytes_in_use = S->held + S->granted;
   st->bytes_budget = S->budget;
+  st->bytes_peak = S->peak;
   return LPCC_OK;
 }
 

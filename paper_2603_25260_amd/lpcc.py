@@ -38,7 +38,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("mpts_per_s", ctypes.c_double), ("completed", ctypes.c_int64), ("admitted", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("running", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t),
-                ("bytes_budget", ctypes.c_size_t)]
+                ("bytes_budget", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t)]
 
 
 class LpccError(RuntimeError):
@@ -63,7 +63,9 @@ def lib():
         L.lpcc_model_free.restype = None
         L.lpcc_model_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                       ctypes.POINTER(ctypes.c_uint32)]
-        L.lpcc_ctx_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+        L.lpcc_make_weights.argtypes = [ctypes.c_uint64, i32, i32, i32, i32, vp, sz, ctypes.POINTER(sz)]
+        L.lpcc_ctx_create.argtypes = [i32, vp, sz, ctypes.POINTER(vp)]
+        L.lpcc_ctx_workspace.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.lpcc_ctx_free.argtypes = [vp]
         L.lpcc_ctx_free.restype = None
         L.lpcc_last_error.argtypes = [vp]
@@ -71,7 +73,7 @@ def lib():
         L.lpcc_encode_frame.argtypes = [vp, vp, vp, i64, i32, vp, sz, ctypes.POINTER(sz)]
         L.lpcc_decode_frame.argtypes = [vp, vp, vp, sz, vp, i64, ctypes.POINTER(i64)]
         L.lpcc_level_probs.argtypes = [vp, vp, vp, i64, i32, vp, i64, ctypes.POINTER(i64)]
-        L.lpcc_peek_header.argtypes = [vp, sz, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.lpcc_peek_header.argtypes = [vp, sz, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(sz)]
         L.lpcc_encode_batch.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp, vp, vp]
         L.lpcc_decode_batch.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp]
         L.lpcc_timing_enable.argtypes = [vp, ctypes.c_char_p]
@@ -131,6 +133,30 @@ def requant_bounds(m_pos: int, m_neg: int, r: int, z_out: int):
     return tuple(int(v) for v in out)
 
 
+W_NO_XFP, W_ZERO_POINTS = 1, 2
+
+
+def make_weights(seed: int, C: int, D: int, n_deep: int, *, xfp: bool = True, zero_points: bool = False) -> bytes:
+    """Seeded random-init weight blob, built by the library (host only)."""
+    flags = (0 if xfp else W_NO_XFP) | (W_ZERO_POINTS if zero_points else 0)
+    n = ctypes.c_size_t()
+    st = lib().lpcc_make_weights(seed, C, D, n_deep, flags, None, 0, ctypes.byref(n))
+    if st not in (OK, E_CAPACITY):
+        _check(st)
+    buf = np.zeros(n.value, np.uint8)
+    _check(lib().lpcc_make_weights(seed, C, D, n_deep, flags, buf.ctypes.data, n.value, ctypes.byref(n)))
+    return buf.tobytes()
+
+
+def peek_header(bs):
+    """(D, points, max_workspace) of a host stream (max_workspace is 0 when
+    the given bytes do not reach the depth counts)."""
+    b = np.frombuffer(bytes(bs), np.uint8)
+    D, npts, ws = ctypes.c_int(), ctypes.c_int64(), ctypes.c_size_t()
+    _check(lib().lpcc_peek_header(b.ctypes.data, len(b), ctypes.byref(D), ctypes.byref(npts), ctypes.byref(ws)))
+    return D.value, npts.value, ws.value
+
+
 def _check(st, ctx=None):
     if st != OK:
         msg = ""
@@ -166,10 +192,17 @@ class Context:
     """Device, stream and workspace.  ``stream`` is a hipStream_t handle (int)
     or None; with torch, pass ``torch.cuda.current_stream().cuda_stream``."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, hbm_budget: int = 0):
         h = ctypes.c_void_p()
-        _check(lib().lpcc_ctx_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
+        _check(lib().lpcc_ctx_create(device, ctypes.c_void_p(stream) if stream else None, hbm_budget,
+                                     ctypes.byref(h)))
         self.handle = h
+
+    def workspace(self):
+        """(bytes held now, most bytes held so far) of device workspace."""
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().lpcc_ctx_workspace(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def close(self):
         if self.handle:
@@ -266,7 +299,7 @@ def decode_frame(ctx: Context, model: Model, bs, length=None, out=None):
             npts_v = int(hdr[12:16].view(np.uint32)[0])
         else:
             hb = np.frombuffer(bytes(bs[:16]) if not isinstance(bs, np.ndarray) else bs[:16].tobytes(), np.uint8)
-            st = L.lpcc_peek_header(hb.ctypes.data, 16, ctypes.byref(D), ctypes.byref(npts))
+            st = L.lpcc_peek_header(hb.ctypes.data, 16, ctypes.byref(D), ctypes.byref(npts), None)
             _check(st)
             npts_v = npts.value
         res = np.zeros((max(npts_v, 1), 3), np.int32)

@@ -32,27 +32,15 @@ class Sensor:
     stream_len: list = None
 
 
-def fleet_spec(n_sensors: int, seed: int, depths=(14, 15, 16, 17, 18), beams=(16, 32, 64, 128)):
-    """(beams, D) of every sensor, drawn from ``seed``."""
-    rng = np.random.default_rng(seed)
-    return [(int(rng.choice(beams)), int(rng.choice(depths))) for _ in range(n_sensors)]
-
-
-def model_key(D: int):
-    C = 32 if D <= 16 else 64
-    return C, D
-
-
 def build_fleet(n_sensors=24, seed=5000, frames_per_sensor=2, depths=(14, 15, 16, 17, 18),
                 beams=(16, 32, 64, 128), azimuths=2048):
-    spec = fleet_spec(n_sensors, seed, depths, beams)
-    keys = sorted({model_key(D) for _, D in spec})
+    spec = synth.fleet_spec(n_sensors, seed, depths, beams)
+    keys = sorted({synth.fleet_model(D) for _, D in spec})
     sensors = []
     for i, (b, D) in enumerate(spec):
-        voxel = 163.84 / (2 ** D)
-        scan = synth.ScanSpec(b, synth.ELEV_BY_BEAMS[b], azimuths, 40, 80.0, D, voxel)
-        frames = [synth.make_scan(scan, seed + 1 + 100 * i + k) for k in range(frames_per_sensor)]
-        sensors.append(Sensor(i, b, D, keys.index(model_key(D)), frames))
+        scan = synth.fleet_scan_spec(b, D, azimuths)
+        frames = [synth.make_scan(scan, synth.fleet_frame_seed(seed, i, k)) for k in range(frames_per_sensor)]
+        sensors.append(Sensor(i, b, D, keys.index(synth.fleet_model(D)), frames))
     return keys, sensors
 
 
@@ -76,7 +64,7 @@ def run(duration_s=5.0, n_sensors=24, rate_hz=10.0, seed=5000, slots=4, max_batc
 
     dev = torch.device("cuda:0")
     keys, sensors = build_fleet(n_sensors, seed, frames_per_sensor, depths, beams, azimuths)
-    models = [lpcc.Model(synth.make_weights(1, C, D, 4), 0) for (C, D) in keys]
+    models = [lpcc.Model(synth.make_weights(1, C, D, nd), 0) for (C, D, nd) in keys]
     ctx = lpcc.Context(0)
     # device inputs; streams for decode jobs made by earlier encodes
     for s in sensors:
@@ -139,9 +127,10 @@ def run(duration_s=5.0, n_sensors=24, rate_hz=10.0, seed=5000, slots=4, max_batc
         "server_mpts_s": round(stats["mpts_per_s"], 3),
         "offered_req_s": round(len(trace) / duration_s, 1),
         "wall_s": round(wall, 3),
-        "models": [f"C{C}_D{D}" for (C, D) in keys],
+        "models": [f"C{C}_D{D}" for (C, D, _) in keys],
         "slots": slots, "max_batch": max_batch,
         "budget_bytes": int(stats["bytes_budget"]),
+        "bytes_peak": int(stats["bytes_peak"]),
     }
     if verify:
         mism = 0

@@ -206,6 +206,28 @@ def batch_scan_spec(seed: int, D: int = 14, voxel: float = 0.01) -> ScanSpec:
     return ScanSpec(beams, ELEV_BY_BEAMS[beams], az, boxes, 80.0, D, voxel)
 
 
+def fleet_spec(n_sensors: int, seed: int, depths=(14, 15, 16, 17, 18), beams=(16, 32, 64, 128)):
+    """(beams, D) of every simulated sensor of a serving fleet, drawn from ``seed``."""
+    rng = np.random.default_rng(seed)
+    return [(int(rng.choice(beams)), int(rng.choice(depths))) for _ in range(n_sensors)]
+
+
+def fleet_model(D: int):
+    """(C, D, n_deep) of the model a fleet sensor of depth D uses: C = 32 up
+    to 16 levels, 64 beyond; four re-densified depths."""
+    return (32 if D <= 16 else 64), D, 4
+
+
+def fleet_scan_spec(beams: int, D: int, azimuths: int = 2048) -> ScanSpec:
+    """Scene of one fleet sensor: its beam count, 40 boxes, voxel 163.84 m / 2^D."""
+    return ScanSpec(beams, ELEV_BY_BEAMS[beams], azimuths, 40, 80.0, D, 163.84 / (2 ** D))
+
+
+def fleet_frame_seed(seed: int, sensor: int, k: int) -> int:
+    """Scan seed of frame k of sensor ``sensor`` in the fleet drawn from ``seed``."""
+    return seed + 1 + 100 * sensor + k
+
+
 def _scene(spec: ScanSpec, rng: np.random.Generator):
     """Axis-aligned boxes standing on the ground: (lo[3], hi[3]) arrays."""
     n = spec.boxes

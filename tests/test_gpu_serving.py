@@ -43,6 +43,27 @@ def test_admission_with_small_budget(L):
                     hbm_budget=48 << 20, realtime=False)
     sys.stdout.write(f"{rep}\n")
     assert rep["ok"] == rep["requests"] and rep["mismatches_vs_alone"] == 0
+    assert 0 < rep["bytes_peak"] <= rep["budget_bytes"] == 48 << 20
+
+
+def test_context_budget(L):
+    """A context capped below what a frame needs fails with LPCC_E_NOMEM and
+    stays usable; with room it encodes the same stream, and its workspace
+    never exceeds the cap."""
+    from paper_2603_25260_amd import synth
+    D, C = 10, 16
+    blob = synth.make_weights(3, C, D, 3)
+    m = L.Model(blob, 0)
+    xyz = synth.random_cloud(3000, D, 31)
+    tight = L.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(L.LpccError) as e:
+        L.encode_frame(tight, m, xyz, 8)
+    assert e.value.code == L.E_NOMEM and "budget" in str(e.value)
+    ref = L.encode_frame(L.Context(0), m, xyz, 8)
+    roomy = L.Context(0, hbm_budget=64 << 20)
+    assert L.encode_frame(roomy, m, xyz, 8) == ref == O.encode(blob, xyz, 8)
+    held, peak = roomy.workspace()
+    assert 0 < held <= peak <= 64 << 20
 
 
 def test_served_streams_match_oracle(L):

@@ -52,9 +52,61 @@ def test_header_peek_without_device(lib):
     hdr[20:24] = (2).to_bytes(4, "little")
     hdr[24:28] = (4).to_bytes(4, "little")
     hdr += bytes(2 * 3)
-    D, n = ctypes.c_int(), ctypes.c_int64()
+    D, n, ws = ctypes.c_int(), ctypes.c_int64(), ctypes.c_size_t()
     buf = (ctypes.c_uint8 * len(hdr)).from_buffer_copy(bytes(hdr))
-    assert lib.lpcc_peek_header(buf, ctypes.c_size_t(len(hdr)), ctypes.byref(D), ctypes.byref(n)) == 0
+    assert lib.lpcc_peek_header(buf, ctypes.c_size_t(len(hdr)), ctypes.byref(D), ctypes.byref(n),
+                                ctypes.byref(ws)) == 0
     assert (D.value, n.value) == (3, 5)
+    assert ws.value > 0  # the depth counts are present
+    # 16 bytes: depth and points only, no workspace figure
+    assert lib.lpcc_peek_header(buf, ctypes.c_size_t(16), ctypes.byref(D), ctypes.byref(n), ctypes.byref(ws)) == 0
+    assert (D.value, n.value, ws.value) == (3, 5, 0)
     bad = (ctypes.c_uint8 * 16)(*b"XPC1" + bytes(12))
-    assert lib.lpcc_peek_header(bad, ctypes.c_size_t(16), ctypes.byref(D), ctypes.byref(n)) == -3
+    assert lib.lpcc_peek_header(bad, ctypes.c_size_t(16), ctypes.byref(D), ctypes.byref(n), None) == -3
+
+
+def test_peek_workspace_grows_with_the_frame(lib):
+    """The decode workspace bound of a stream grows with its node counts and
+    covers at least the node arrays and the CDF rows of its largest depth."""
+    def header(D, counts):
+        h = bytearray(16 + 4 * D)
+        h[0:4] = b"LPC1"
+        h[4], h[5], h[6], h[7] = 1, D, 2, 8
+        h[12:16] = counts[D].to_bytes(4, "little")
+        for d in range(D):
+            h[16 + 4 * d:20 + 4 * d] = counts[d].to_bytes(4, "little")
+        return bytes(h)
+    small = [1, 8, 60, 400, 2000, 6000, 9000]
+    big = [1, 8, 64, 500, 4000, 30000, 90000]
+    out = []
+    for counts in (small, big):
+        h = header(6, counts)
+        ws = ctypes.c_size_t()
+        buf = (ctypes.c_uint8 * len(h)).from_buffer_copy(h)
+        assert lib.lpcc_peek_header(buf, ctypes.c_size_t(len(h)), None, None, ctypes.byref(ws)) == 0
+        out.append(ws.value)
+        assert ws.value >= 512 * max(counts[:6]) + 13 * sum(counts)
+    assert out[1] > out[0]
+
+
+@pytest.mark.parametrize("C,D,nd,flags", [(16, 12, 4, 0), (32, 14, 4, 0), (64, 18, 5, 0), (16, 9, 3, 1),
+                                          (32, 10, 4, 2), (16, 7, 0, 3), (64, 6, 5, 0)])
+def test_library_weights_equal_generator(lib, C, D, nd, flags):
+    """lpcc_make_weights (integer-only, in the library) writes the same bytes
+    as the seeded input generator, whose multiplier uses floating point."""
+    from paper_2603_25260_amd import synth
+    want = synth.make_weights(7, C, D, nd, xfp=not (flags & 1), zero_points=bool(flags & 2))
+    n = ctypes.c_size_t()
+    assert lib.lpcc_make_weights(ctypes.c_uint64(7), C, D, nd, flags, None, ctypes.c_size_t(0), ctypes.byref(n)) == -2
+    assert n.value == len(want)
+    buf = (ctypes.c_uint8 * n.value)()
+    assert lib.lpcc_make_weights(ctypes.c_uint64(7), C, D, nd, flags, buf, n, ctypes.byref(n)) == 0
+    assert bytes(buf) == want
+
+
+def test_library_weights_reject_bad_arguments(lib):
+    n = ctypes.c_size_t()
+    for args in ((24, 10, 2, 0), (16, 0, 0, 0), (16, 10, 10, 0), (16, 22, 2, 0), (16, 10, 2, 4)):
+        C, D, nd, fl = args
+        assert lib.lpcc_make_weights(ctypes.c_uint64(1), C, D, nd, fl, None, ctypes.c_size_t(0),
+                                     ctypes.byref(n)) == -1, args
