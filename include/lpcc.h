@@ -137,6 +137,30 @@ int lpcc_encode_frame(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int6
                       uint8_t* out, size_t cap, size_t* out_len);
 
 /*
+ * Allocation-free form of lpcc_encode_frame, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, same bytes out as
+ * lpcc_encode_frame on the same context (its stream, base depth and tiling),
+ * but no call into a device or pinned-host allocator: every intermediate
+ * buffer of the encode is carved from a static block of 256 MiB that the
+ * library holds on each device it runs on (from the first context created on
+ * the device until the process ends), and host read-backs go through a 4 MiB
+ * pageable buffer made with the context.  The caller passes inputs and
+ * outputs as for lpcc_encode_frame (host or device).
+ * Every call on a device shares that device's block, which keeps the last
+ * call's contents (each call clears what it needs cleared itself); calls that
+ * overlapped on one device would race on it, so the library holds a per-device
+ * lock for the whole (synchronous) call and concurrent callers run one after
+ * another.
+ * Errors: as lpcc_encode_frame; LPCC_E_NOMEM when the frame's workspace does
+ * not fit the block or its host staging the buffer (checked before any work
+ * is enqueued for that phase; lpcc_last_error gives the sizes);
+ * LPCC_E_DEVICE when the block's device address could not be looked up.
+ */
+int lpcc_encode_frame_noalloc(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int chunk_log2,
+                              uint8_t* out, size_t cap, size_t* out_len);
+
+/*
  * Decode one frame, depth by depth: the model of every depth reads only the
  * depths decoded before it (Eq. 2), so the decoder rebuilds the same
  * distributions and the geometry progressively (Sec. 3.1, S3.2 child

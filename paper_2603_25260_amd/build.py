@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "liblpcc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["octree.hip", "model.hip", "rc.hip", "runtime.hip", "server.hip", "weights.hip"]
+SOURCES = ["octree.hip", "model.hip", "rc.hip", "runtime.hip", "server.hip", "weights.hip", "noalloc.hip"]
 # -amdgpu-mfma-vgpr-form: MFMA accumulators stay in VGPRs; without it the
 # register allocator shuttles the register-blocked accumulators between AGPRs
 # and VGPRs on every k-step of the gather-GEMM loops.

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -341,5 +342,16 @@ hipError_t launch_base_sf(const BaseLevels& bl, const int32_t* cdf, uint32_t* sf
 // rows16[(f nb + d) 256 ..]
 hipError_t launch_base_rows(const uint64_t* keys, int64_t n, int d, int nb, int nf, const uint16_t* rows16,
                             uint16_t* cdf16, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Static workspace of the allocation-free encode entry point (noalloc.hip)
+// ---------------------------------------------------------------------------
+constexpr size_t kNoallocBytes = (size_t)256 << 20;  // device bytes per device
+constexpr size_t kNoallocHost = (size_t)4 << 20;     // pageable host staging per context
+// device address of the block on `device` (current), looked up once per
+// device; LPCC_E_DEVICE with the reason in *why when the lookup failed
+int scratch_setup(int device, char** base, size_t* cap, std::string* why);
+// held for a whole allocation-free call: calls on one device share its block
+std::mutex& scratch_mutex(int device);
 
 }  // namespace lpcc

@@ -353,12 +353,13 @@ struct lpcc_ctx {
   // workspace cap in bytes (0 = none) and the most held so far
   size_t budget = 0, peak = 0;
   // fixed mode (the entry point that allocates nothing): the arenas are
-  // carved from one device block the library owns, host staging uses
-  // pageable memory, one stream, no events
+  // carved from the library's static device block, host staging is one
+  // pageable buffer sized when the context is created, one stream, no events
   bool fixed = false;
   char* fixed_base = nullptr;
   size_t fixed_cap = 0, fixed_off1 = 0;
-  std::vector<uint8_t> hostbuf;
+  std::unique_ptr<uint8_t[]> hostbuf;
+  std::string fixed_why;        // why the static block is unavailable, if it is
   lpcc_ctx* noalloc = nullptr;  // fixed-mode companion of this context
 };
 
@@ -388,7 +389,7 @@ int reserve_fixed(lpcc_ctx* c, int which, size_t bytes) {
   if (at + bytes > lim) {
     char b[256];
     snprintf(b, sizeof(b), "workspace of %zu bytes does not fit the %zu-byte static block of the allocation-free "
-                           "entry point", at + bytes + (which == 2 ? 0 : 0), c->fixed_cap);
+                           "entry point", at + bytes, which == 2 ? kFixedDesc : c->fixed_cap);
     c->err = b;
     return LPCC_E_NOMEM;
   }
@@ -425,11 +426,12 @@ int reserve(lpcc_ctx* c, int which, size_t bytes) {
 
 int reserve_pinned(lpcc_ctx* c, size_t bytes) {
   if (bytes <= c->pinned_cap) return LPCC_OK;
-  if (c->fixed) {  // pageable: copies from and to it complete before they return
-    c->hostbuf.resize(std::max(bytes, 2 * c->hostbuf.size()));
-    c->pinned = c->hostbuf.data();
-    c->pinned_cap = c->hostbuf.size();
-    return LPCC_OK;
+  if (c->fixed) {  // the pageable buffer of the context never grows
+    char b[256];
+    snprintf(b, sizeof(b), "host staging of %zu bytes exceeds the %zu-byte buffer of the allocation-free entry point",
+             bytes, c->pinned_cap);
+    c->err = b;
+    return LPCC_E_NOMEM;
   }
   size_t nc = std::max(bytes, c->pinned_cap * 2);
   HIPC(hipStreamSynchronize(c->stream));
@@ -2535,11 +2537,18 @@ int lpcc_ctx_create(int device, void* hip_stream, size_t hbm_budget, lpcc_ctx** 
   lpcc_ctx* c = new lpcc_ctx();
   c->device = device;
   c->budget = hbm_budget;
-  // companion of the allocation-free entry point (its block is looked up on
-  // the first such call on the device)
+  // companion of the allocation-free entry point: the device address of the
+  // library's static block (looked up once per device, with `device` current)
+  // and a pageable host staging buffer of fixed size
   c->noalloc = new lpcc_ctx();
   c->noalloc->device = device;
   c->noalloc->fixed = true;
+  if (lpcc::scratch_setup(device, &c->noalloc->fixed_base, &c->noalloc->fixed_cap, &c->noalloc->fixed_why) ==
+      LPCC_OK) {
+    c->noalloc->hostbuf.reset(new uint8_t[lpcc::kNoallocHost]);
+    c->noalloc->pinned = c->noalloc->hostbuf.get();
+    c->noalloc->pinned_cap = lpcc::kNoallocHost;
+  }
   c->stream = (hipStream_t)hip_stream;
   if (!c->stream) {
     if (hipStreamCreate(&c->own_stream) != hipSuccess) {
@@ -2636,6 +2645,31 @@ int lpcc_encode_frame(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int6
   if (!out_len) return LPCC_E_INVAL;
   int st = 0;
   return lpcc_encode_batch(c, m, 1, &xyz, &n, chunk_log2, &out, &cap, out_len, &st);
+}
+
+int lpcc_encode_frame_noalloc(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int chunk_log2,
+                              uint8_t* out, size_t cap, size_t* out_len) {
+  if (!c || !m || !out || !out_len || n < 0 || (n > 0 && !xyz) || n > (1ll << 30)) return LPCC_E_INVAL;
+  if (chunk_log2 < 4 || chunk_log2 > 14) return LPCC_E_INVAL;
+  if (hipSetDevice(c->device) != hipSuccess) return LPCC_E_DEVICE;
+  c->err.clear();
+  lpcc_ctx* z = c->noalloc;
+  if (!z || !z->fixed_base) {
+    c->err = z ? z->fixed_why : std::string("context without an allocation-free companion");
+    return LPCC_E_DEVICE;
+  }
+  // every call on the device carves the same block: one call at a time, held
+  // until the call's work has finished (the call is synchronous)
+  std::lock_guard<std::mutex> g(lpcc::scratch_mutex(c->device));
+  z->stream = c->stream;
+  z->base = c->base;
+  z->tiling = c->tiling;
+  z->err.clear();
+  int st = 0;
+  OutSpec os{&out, &cap, out_len};
+  const int s = encode_impl(z, m, 1, &xyz, &n, chunk_log2, os, &st, -1, nullptr, 0, nullptr);
+  if (s) c->err = z->err;
+  return s;
 }
 
 int lpcc_level_probs(lpcc_ctx* c, const lpcc_model* m, const int32_t* xyz, int64_t n, int level, int32_t* cdf_out,

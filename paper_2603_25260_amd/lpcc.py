@@ -71,6 +71,7 @@ def lib():
         L.lpcc_last_error.argtypes = [vp]
         L.lpcc_last_error.restype = ctypes.c_char_p
         L.lpcc_encode_frame.argtypes = [vp, vp, vp, i64, i32, vp, sz, ctypes.POINTER(sz)]
+        L.lpcc_encode_frame_noalloc.argtypes = [vp, vp, vp, i64, i32, vp, sz, ctypes.POINTER(sz)]
         L.lpcc_decode_frame.argtypes = [vp, vp, vp, sz, vp, i64, ctypes.POINTER(i64)]
         L.lpcc_level_probs.argtypes = [vp, vp, vp, i64, i32, vp, i64, ctypes.POINTER(i64)]
         L.lpcc_peek_header.argtypes = [vp, sz, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(sz)]
@@ -282,6 +283,18 @@ def encode_frame(ctx: Context, model: Model, xyz, chunk_log2: int = 10, out=None
     ln = ctypes.c_size_t()
     cap = out.numel() if _is_torch(out) else out.size
     _check(L.lpcc_encode_frame(ctx.handle, model.handle, p, n, chunk_log2, op, cap, ctypes.byref(ln)), ctx.handle)
+    return ln.value
+
+
+def encode_frame_noalloc(ctx: Context, model: Model, xyz, out, chunk_log2: int = 10) -> int:
+    """Stream of one frame written into ``out`` (uint8, host or device) by the
+    allocation-free entry point (static device workspace); returns its length."""
+    p, keep = _ptr(xyz)
+    op, okeep = _ptr(out)
+    cap = out.numel() if _is_torch(out) else out.size
+    ln = ctypes.c_size_t()
+    _check(lib().lpcc_encode_frame_noalloc(ctx.handle, model.handle, p, _n_points(xyz), chunk_log2, op, cap,
+                                           ctypes.byref(ln)), ctx.handle)
     return ln.value
 
 
