@@ -8,11 +8,14 @@ the server encoded earlier for that sensor).  Inputs and outputs live in
 device memory.  The driver submits each job at its arrival time, collects
 completions, and reports p50 / p99 latency (arrival -> completion) and the
 sustained point rate; with ``verify`` every result is compared with the same
-job run alone through the per-frame calls.
+job run alone through the per-frame calls, and with ``reference`` = (digests,
+expect) every encode result with the sha256 digest of the oracle's stream of
+that frame (keyed "sensor_frame") and every decode result with expect(xyz, D).
 """
 from __future__ import annotations
 
 import dataclasses
+import hashlib
 import time
 
 import numpy as np
@@ -59,7 +62,7 @@ def poisson_trace(n_sensors, rate_hz, duration_s, seed, enc_frac=0.5):
 
 def run(duration_s=5.0, n_sensors=24, rate_hz=10.0, seed=5000, slots=4, max_batch=4, hbm_budget=0,
         chunk_log2=8, frames_per_sensor=2, verify=False, depths=(14, 15, 16, 17, 18), beams=(16, 32, 64, 128),
-        azimuths=2048, realtime=True):
+        azimuths=2048, realtime=True, reference=None):
     import torch
 
     dev = torch.device("cuda:0")
@@ -114,6 +117,12 @@ def run(duration_s=5.0, n_sensors=24, rate_hz=10.0, seed=5000, slots=4, max_batc
     wall = (time.monotonic_ns() - t0) / 1e9
     stats = server.stats()
     lat = np.array([(d["t_done_ns"] - d["t_arrival_ns"]) / 1e6 for d in done])
+    # most jobs on the GPU at one time (start -> done intervals overlapping)
+    ev = sorted([(d["t_start_ns"], 1) for d in done] + [(d["t_done_ns"], -1) for d in done])
+    run_, max_run = 0, 0
+    for _, e in ev:
+        run_ += e
+        max_run = max(max_run, run_)
     pts = sum(d["n_points"] for d in done if d["status"] == 0)
     rep = {
         "requests": len(done),
@@ -122,7 +131,9 @@ def run(duration_s=5.0, n_sensors=24, rate_hz=10.0, seed=5000, slots=4, max_batc
         "decode_jobs": sum(d["kind"] == 1 for d in done),
         "p50_ms": round(float(np.percentile(lat, 50)), 3) if len(lat) else None,
         "p99_ms": round(float(np.percentile(lat, 99)), 3) if len(lat) else None,
+        "failed": {str(c): sum(d["status"] == c for d in done) for c in sorted({d["status"] for d in done}) if c != 0},
         "mean_batch": round(float(np.mean([d["batch"] for d in done])), 2) if done else None,
+        "max_in_flight": max_run,
         "sustained_mpts_s": round(pts / wall / 1e6, 3),
         "server_mpts_s": round(stats["mpts_per_s"], 3),
         "offered_req_s": round(len(trace) / duration_s, 1),
@@ -149,5 +160,24 @@ def run(duration_s=5.0, n_sensors=24, rate_hz=10.0, seed=5000, slots=4, max_batc
                 got = out[:d["out_len"]].cpu().numpy()
                 mism += not np.array_equal(got, ref)
         rep["mismatches_vs_alone"] = int(mism)
+    if reference is not None:
+        digests, expect = reference
+        mism, checked, exp_cache = 0, 0, {}
+        for d in done:
+            si, kind, fi, out = tickets[d["ticket"]]
+            s = sensors[si]
+            if d["status"] != 0:  # refused or failed: reported under "failed"
+                continue
+            checked += 1
+            if kind == 0:
+                want = digests.get(f"{si}_{fi}")
+                got = out[:d["out_len"]].cpu().numpy().tobytes()
+                mism += want is None or (len(got), hashlib.sha256(got).hexdigest()) != (want["bytes"], want["sha256"])
+            else:
+                if (si, fi) not in exp_cache:
+                    exp_cache[(si, fi)] = expect(s.frames[fi], s.D)
+                mism += not np.array_equal(out[:d["out_len"]].cpu().numpy(), exp_cache[(si, fi)])
+        rep["checked"] = checked
+        rep["mismatches"] = int(mism)
     server.close()
     return rep
