@@ -182,8 +182,7 @@ struct PredArg {
 // share one launch, each starting at its own block.
 struct HashJob {
   const uint64_t* keys;    // V_j (frame tag above bit 3j)
-  uint64_t* tkeys;
-  int32_t* tvals;
+  uint64_t* table;         // 16-byte slots {u64 key, i32 row}; empty keys are all ones
   int32_t* kmap;           // [27][kstride]
   int64_t n;
   int64_t kstride;
@@ -255,15 +254,14 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_iota_u64(uint64_t* p, int64_t n, hipStream_t s);  // p[i] = i
 
-hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
-                              uint64_t mask, hipStream_t s);
+hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* table, uint64_t mask, hipStream_t s);
 // All jobs' insertions, then all jobs' neighbour tables (two launches); the
 // block offsets in `jobs` must match the host copy used for the grid sizes.
 constexpr int kHashBlock = 256;
 hipError_t launch_hash_multi(const HashJob* jobs_dev, int njobs, int insert_blocks, int kmap_blocks,
                              hipStream_t s);
-hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* tkeys, const int32_t* tvals,
-                       uint64_t mask, int32_t* kmap, int64_t kstride, hipStream_t s);
+hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* table, uint64_t mask,
+                       int32_t* kmap, int64_t kstride, hipStream_t s);
 
 // GEMM families; `mode` selects the row source
 enum GemmMode { G_CONV = 0, G_DENSE = 1, G_DOWN = 2 };
@@ -272,6 +270,10 @@ hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs_dev, con
                        int ntiles, const GemmArg& one, int rb, hipStream_t s);
 hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
                      int rb, hipStream_t s);
+// the same over the occupied children only; tiles of kUpTile parents
+constexpr int kUpTile = 512;
+hipError_t launch_up_cx(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
+                        hipStream_t s);
 hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, const GemmArg& one,
                       hipStream_t s);
 // single-segment predictor launches up to this many rows take 4 rows per wave
@@ -301,12 +303,12 @@ hipError_t launch_rc_pack_dev(const Chunk* chunks, int nchunks, const int32_t* f
 hipError_t launch_rc_decode_sized(const Chunk* chunks, int nchunks, const uint8_t* payload, const uint16_t* cdf16,
                                   uint8_t* codes, uint32_t* csum, uint32_t* err, size_t max_len, hipStream_t s);
 // Child expansion by decoded chunk (one block per chunk) from the chunks'
-// child counts: keys of V_{d+1}, first-child rows, and, when tkeys is not
+// child counts: keys of V_{d+1}, first-child rows, and, when table is not
 // null, insertion of the children into the hash table of depth d+1.
 hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t* pkeys, const uint8_t* codes,
                                 int64_t n, uint32_t* csum, uint64_t* ckeys, int32_t* cstart,
-                                int64_t n_child_expected, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
-                                uint32_t* err, hipStream_t s);
+                                int64_t n_child_expected, uint64_t* table, uint64_t mask, uint32_t* err,
+                                hipStream_t s);
 hipError_t launch_keys_to_xyz(const uint64_t* keys, int64_t n, int D, int32_t* xyz, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -371,6 +371,236 @@ __global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ seg
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gather-GEMM over the present taps only (kernel-map compaction) for the
+// 3x3x3 convolution and the child convolution.  A wave owns WR = 16 RB
+// output rows.  Every row has a bit mask of its present taps: the presence
+// mask the neighbour-table kernel stores after the 27 tap rows, or for the
+// child convolution the parent's occupancy code.  The OR of the masks over
+// the wave's rows sets the wave's K dimension: its nt taps, ranked by tap
+// index, times CIN channels, in k-steps of 64.  A tap that no row of the
+// wave has costs nothing (no table read, weight load, gather or MFMA); rows
+// without a present tap contribute a zero A fragment.  Only the table rows
+// of the present taps are staged, straight from global memory into LDS.
+// The tap of rank i sits in lane i of a register (read with readlane), and
+// the weights of tap t, channel c are rows k = t CIN + c of the packed
+// layout, so any tap's B fragment is addressed directly.  The sums are exact
+// int32, so the order of the taps does not change the result.
+// ---------------------------------------------------------------------------
+template <int MODE, int CIN, int COUT, int RB>
+__global__ __launch_bounds__(256) void k_gemm_cx(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                                 const GemmArg A) {
+  constexpr int TAPS = Taps<MODE>::n;
+  constexpr int NB = COUT / 16;
+  constexpr int WR = 16 * RB;  // rows per wave
+  static_assert(MODE == G_CONV || MODE == G_DOWN, "tap-compacted modes");
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0 && (CIN & (CIN - 1)) == 0, "widths");
+  static_assert(WR <= 64 && TAPS <= 32, "shape");
+  // Per wave, one LDS region holds first the neighbour rows of the wave's
+  // rows (slot i = the tap of rank i, lane l = row wrow0 + l), then, after
+  // the k-loop, the accumulator stage of the epilogue.
+  constexpr int KMW = MODE == G_CONV ? TAPS * WR : 0;
+  constexpr int RW = KMW > 16 * COUT ? KMW : 16 * COUT;  // words per wave
+  __shared__ __attribute__((aligned(16))) int32_t smem[4 * RW];
+
+  GemmSeg S;
+  LayerDev L;
+  const int tile_row0 = pick_seg(segs, tiles, A, S, L, 4 * WR);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int wrow0 = tile_row0 + wave * WR;
+  int32_t* skm = smem + wave * RW;  // [slot][WR]
+  Stage<COUT>* st = (Stage<COUT>*)(smem + wave * RW);
+
+  // presence masks: the table's (one load per row) or the parents' codes
+  uint32_t pcode[RB];
+  int pcs[RB];
+  uint32_t mine = 0u;
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+    const int row = wrow0 + 16 * rb + r;
+    pcode[rb] = 0u;
+    pcs[rb] = 0;
+    if (MODE == G_DOWN && row < S.rows) {
+      pcode[rb] = gp(S.code)[row] & 0xFFu;
+      pcs[rb] = gp(S.cstart)[row];
+    }
+    mine |= pcode[rb];
+  }
+  const int myrow = wrow0 + lane;
+  if (MODE == G_CONV && lane < WR && myrow < S.rows) mine = (uint32_t)gp(S.kmap)[27 * S.kstride + myrow];
+  uint32_t U = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) U |= (uint32_t)__shfl_xor((int)U, o);
+  U = (uint32_t)__builtin_amdgcn_readfirstlane((int)U);
+  const int nt = __popc(U);
+  // lane i: the tap of rank i (255 past the last); the owner of each set bit
+  // sends its tap to the lane of its rank
+  int tapof;
+  {
+    const bool own = lane < TAPS && ((U >> (lane & 31)) & 1u);
+    const int rk = __popc(U & ((1u << (lane & 31)) - 1u));
+    const int got = __builtin_amdgcn_ds_permute((own ? rk : 63) * 4, lane);
+    tapof = lane < nt ? got : 255;
+  }
+  if (MODE == G_CONV) {
+    // table rows of the present taps, straight into LDS (rows past the end
+    // read the last row; they are never used)
+    const int crow = min(myrow, S.rows - 1);
+    uint32_t rem = U;
+    if (lane < WR) {
+      for (int i = 0; i < nt; i++) {
+        const int t = __builtin_ctz(rem);
+        rem &= rem - 1u;
+        __builtin_amdgcn_global_load_lds((const GAS void*)(gp(S.kmap) + (int64_t)t * S.kstride + crow),
+                                         (__attribute__((address_space(3))) void*)(skm + i * WR), 4, 0, 0);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the staged rows have landed
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  // source row of block rb for the tap of rank `slot` (tap `tap`), or -1
+  auto src_of = [&](int rb, int slot, int tap) -> int {
+    const int row = wrow0 + 16 * rb + r;
+    if (row >= S.rows) return -1;
+    if (MODE == G_CONV) return skm[slot * WR + 16 * rb + r];
+    if (!((pcode[rb] >> tap) & 1u)) return -1;
+    const int cr = pcs[rb] + __popc(pcode[rb] & ((1u << tap) - 1u));
+    return cr < S.child_rows ? cr : -1;  // out of range only for a corrupt stream
+  };
+
+  v4i acc[RB][NB];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) acc[rb][nb] = v4i{0, 0, 0, 0};
+  const GAS v4i* Wp = (const GAS v4i*)L.Wp;
+  constexpr int LC = __builtin_ctz(CIN);
+  constexpr int SPLIT = CIN == 2 * COUT ? COUT : CIN;  // [in | in2] layers have cin = 2 cout
+  // taps per k-step (CIN < 64: lane group g takes slot base + (16 g >> LC))
+  constexpr int SPS = CIN >= 64 ? 1 : 64 / CIN;
+  const GAS int8_t* in1 = gp(S.in);
+  const GAS int8_t* in2 = gp(S.in2);
+  const uint32_t st1 = (uint32_t)S.in_stride, st2 = (uint32_t)S.in2_stride;
+  const int KV = (nt * CIN + 63) >> 6;  // k-steps over the present taps (wave-uniform)
+
+  // Software pipeline over the k-steps, one step of loads in flight behind
+  // the MFMAs.  The loop body is straight-line code: steps past the last
+  // present tap, and rows without the step's tap, load from row 0 and the
+  // first weight fragment and are zeroed after the load.
+  constexpr int PD = 2;
+  v4i abuf[PD][RB], bbuf[PD][NB];
+  auto load_step = [&](int v, v4i (&a)[RB], v4i (&b)[NB]) {
+    const int kk = 64 * v + 16 * g;
+    const int c0 = kk & (CIN - 1);
+    int slot, tap;
+    if (SPS == 1) {
+      slot = min((64 * v) >> LC, 31);
+      tap = __builtin_amdgcn_readlane(tapof, slot);
+    } else {
+      const int base = min(v * SPS, 28);
+      int tk[SPS];
+#pragma unroll
+      for (int k = 0; k < SPS; k++) tk[k] = __builtin_amdgcn_readlane(tapof, base + k);
+      const int k = (16 * g) >> LC;
+      slot = base + k;
+      tap = tk[0];
+#pragma unroll
+      for (int q = 1; q < SPS; q++) tap = k == q ? tk[q] : tap;
+    }
+    const bool tv = tap < TAPS;
+    const int ko = tv ? tap * CIN + c0 : 0;
+    const GAS v4i* w = Wp + (int64_t)(ko >> 6) * NB * 64 + ((ko >> 4) & 3) * 16 + r;
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) {
+      const v4i x = w[nb * 64];
+      b[nb] = tv ? x : v4i{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; rb++) {
+      const int sr = tv ? src_of(rb, slot, tap) : -1;
+      const bool present = sr >= 0;
+      const uint32_t ur = present ? (uint32_t)sr : 0u;
+      const v4i x = c0 < SPLIT ? *(const GAS v4i*)(in1 + (ur * st1 + (uint32_t)c0))
+                               : *(const GAS v4i*)(in2 + (ur * st2 + (uint32_t)(c0 - SPLIT)));
+      a[rb] = present ? x : v4i{0, 0, 0, 0};
+    }
+  };
+#pragma unroll
+  for (int p = 0; p < PD - 1; p++) load_step(p, abuf[p], bbuf[p]);
+  for (int v0 = 0; v0 < KV; v0 += PD) {
+#pragma unroll
+    for (int u = 0; u < PD; u++) {
+      load_step(v0 + u + PD - 1, abuf[(u + PD - 1) % PD], bbuf[(u + PD - 1) % PD]);
+#pragma unroll
+      for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) acc[rb][nb] = mfma16(abuf[u][rb], bbuf[u][nb], acc[rb][nb]);
+    }
+  }
+
+  // epilogue, one row block at a time through the wave's LDS stage, which
+  // reuses the region of the staged neighbour rows (its operands are loaded
+  // only now: registers, not latency, bound the k-loop)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  constexpr int PER = COUT / 4;
+  const int er = lane >> 2, ec = (lane & 3) * PER;
+  int bia[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) bia[q] = gp(L.bias)[ec + q];
+#pragma unroll
+  for (int rb = 0; rb < RB; rb++) {
+    int8_t res[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++) res[q] = 0;
+    if (S.resid != nullptr && wrow0 + 16 * rb + er < S.rows) {
+      ld_bytes<PER>(S.resid + (int64_t)(wrow0 + 16 * rb + er) * S.resid_stride + ec, res);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) st->v[4 * g + i][16 * nb + r] = acc[rb][nb][i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int orow = wrow0 + 16 * rb + er;
+    // presence mask of the epilogue row (zero-point correction over its taps)
+    const uint32_t omask = MODE == G_CONV ? (uint32_t)__shfl((int)mine, (16 * rb + er) & 63) : 0u;
+    if (orow < S.rows) {
+      int zsum[PER];
+#pragma unroll
+      for (int q = 0; q < PER; q++) zsum[q] = 0;
+      if (L.zc != nullptr) {
+        for (int t = 0; t < TAPS; t++) {
+          const int present = MODE == G_CONV ? (int)((omask >> t) & 1u) : (int)(src_row<MODE>(S, orow, t) >= 0);
+          if (!present) continue;
+#pragma unroll
+          for (int q = 0; q < PER; q++) zsum[q] += gp(L.zc)[t * L.npad + ec + q];
+        }
+      }
+      int8_t outv[PER];
+#pragma unroll
+      for (int q = 0; q < PER; q++) {
+        int y = requant_l(st->v[er][ec + q] + bia[q] + zsum[q], L);
+        if (S.resid != nullptr) {
+          y += res[q];
+          y = y < -128 ? -128 : (y > 127 ? 127 : y);
+        }
+        outv[q] = (int8_t)y;
+      }
+      st_bytes<PER>(S.out + (int64_t)orow * S.out_stride + ec, outv);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 template <int MODE>
 static hipError_t launch_gemm_mode(int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
                                    const GemmArg& A, int rb, hipStream_t s) {
@@ -389,12 +619,32 @@ static hipError_t launch_gemm_mode(int cin, int cout, const GemmSeg* segs, const
   return hipErrorInvalidValue;
 }
 
+// the 3x3x3 and child convolutions: (C, C) layers, and (2C, C) for the
+// ResBlock's first convolution on [F | G]
+template <int MODE>
+static hipError_t launch_gemm_cx(int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
+                                 const GemmArg& A, int rb, hipStream_t s) {
+#define LPCC_C(CI, CO)                                                                                    \
+  if (cin == CI && cout == CO) {                                                                          \
+    if (rb == 4)                                                                                          \
+      hipLaunchKernelGGL((k_gemm_cx<MODE, CI, CO, 4>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);    \
+    else if (rb == 2)                                                                                     \
+      hipLaunchKernelGGL((k_gemm_cx<MODE, CI, CO, 2>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);    \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_gemm_cx<MODE, CI, CO, 1>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);    \
+    return hipGetLastError();                                                                             \
+  }
+  LPCC_C(16, 16) LPCC_C(32, 16) LPCC_C(32, 32) LPCC_C(64, 32) LPCC_C(64, 64) LPCC_C(128, 64)
+#undef LPCC_C
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
                        const GemmArg& A, int rb, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (mode == G_CONV) return launch_gemm_mode<G_CONV>(cin, cout, segs, tiles, ntiles, A, rb, s);
+  if (mode == G_CONV) return launch_gemm_cx<G_CONV>(cin, cout, segs, tiles, ntiles, A, rb, s);
   if (mode == G_DENSE) return launch_gemm_mode<G_DENSE>(cin, cout, segs, tiles, ntiles, A, rb, s);
-  if (mode == G_DOWN) return launch_gemm_mode<G_DOWN>(cin, cout, segs, tiles, ntiles, A, rb, s);
+  if (mode == G_DOWN) return launch_gemm_cx<G_DOWN>(cin, cout, segs, tiles, ntiles, A, rb, s);
   return hipErrorInvalidValue;
 }
 
@@ -637,6 +887,164 @@ __global__ __launch_bounds__(256) void k_up_staged(const GemmSeg* __restrict__ s
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
+}
+
+// Upsampling + pruning over the occupied children only.  A block takes
+// kUpParents consecutive parents and compacts them, per child slot o, into a
+// list of the parents that have child o (wave ballot and prefix count, then
+// the per-wave totals: the list keeps parent order).  The lists are cut into
+// groups of 16 entries; a wave computes one group with one MFMA column block
+// per 16 output channels: the weights of slot o as the row operand, the 16
+// parents' inputs [Z | bits(X)] as the columns, so that every lane ends with
+// four consecutive output channels of one child and writes them as one word.
+// Only the last group of each slot is partly empty.  Groups are dealt to the
+// waves in slot order, so a wave keeps a slot's weights across its groups.
+constexpr int kUpParents = kUpTile;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {  // set bits of m below this lane
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                               const GemmArg A) {
+  constexpr int KS = (C + 8 + 63) / 64;
+  constexpr int NBS = C / 16;          // column blocks per child slot
+  constexpr int NBT = 8 * NBS;         // column blocks of the layer
+  constexpr int PPT = kUpParents / 256;  // parents per thread
+  static_assert(C % 16 == 0 && kUpParents % 256 == 0, "shape");
+  __shared__ uint16_t list[8][kUpParents];
+  __shared__ uint8_t pcode[kUpParents];
+  __shared__ uint32_t wtot[8][4 * PPT];
+  __shared__ uint32_t cnt[8];
+  __shared__ uint32_t goff[9];
+
+  GemmSeg S;
+  LayerDev L;
+  const int p0 = pick_seg(segs, tiles, A, S, L, kUpParents);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+
+  // compaction: parent t of the block is thread t % 256, round t / 256
+  uint32_t code[PPT];
+  uint32_t rank[PPT][8];
+#pragma unroll
+  for (int q = 0; q < PPT; q++) {
+    const int t = 256 * q + (int)threadIdx.x;
+    const int p = p0 + t;
+    code[q] = p < S.rows ? (uint32_t)gp(S.code)[p] : 0u;
+    pcode[t] = (uint8_t)code[q];
+#pragma unroll
+    for (int o = 0; o < 8; o++) {
+      const uint64_t m = __ballot((code[q] >> o) & 1u);
+      rank[q][o] = lanes_below(m);
+      if (lane == 0) wtot[o][4 * q + wave] = (uint32_t)__popcll(m);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PPT; q++) {
+    const int t = 256 * q + (int)threadIdx.x;
+#pragma unroll
+    for (int o = 0; o < 8; o++) {
+      if (!((code[q] >> o) & 1u)) continue;
+      uint32_t before = rank[q][o];
+      for (int w = 0; w < 4 * q + wave; w++) before += wtot[o][w];
+      list[o][before] = (uint16_t)t;
+    }
+  }
+  if (threadIdx.x < 8) {  // list lengths
+    uint32_t n = 0;
+    for (int w = 0; w < 4 * PPT; w++) n += wtot[threadIdx.x][w];
+    cnt[threadIdx.x] = n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // first group of every slot (16 entries per group)
+    uint32_t gsum = 0;
+    for (int o = 0; o < 8; o++) {
+      goff[o] = gsum;
+      gsum += (cnt[o] + 15) / 16;
+    }
+    goff[8] = gsum;
+  }
+  __syncthreads();
+
+  const GAS v4i* Wp = (const GAS v4i*)L.Wp;
+  const GAS v4i* Bp = (const GAS v4i*)L.bias;
+  const int G = (int)goff[8];
+  // wave w takes the contiguous groups [G w / 4, G (w + 1) / 4)
+  const int gb = (G * wave) / 4, ge = (G * (wave + 1)) / 4;
+  int cur = -1;
+  v4i wb[KS][NBS], bb[NBS];
+  for (int gi = gb; gi < ge; gi++) {
+    int o = 0;
+#pragma unroll
+    for (int q = 1; q < 8; q++) o += gi >= (int)goff[q] ? 1 : 0;
+    if (o != cur) {  // weights and biases of slot o (wave-uniform)
+      cur = o;
+#pragma unroll
+      for (int s = 0; s < KS; s++)
+#pragma unroll
+        for (int nb = 0; nb < NBS; nb++) wb[s][nb] = Wp[((int64_t)s * NBT + o * NBS + nb) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < NBS; nb++) bb[nb] = Bp[(o * C + 16 * nb + 4 * g) / 4];
+    }
+    const int e = 16 * (gi - (int)goff[o]) + r;  // entry of column r
+    const bool ev = e < (int)cnt[o];
+    const int t = ev ? (int)list[o][e] : 0;
+    const int p = p0 + t;
+    const uint32_t pc = pcode[t];
+    // column operand: k-slice 16 g of the parent's [Z | bits(X)] row
+    v4i a[KS];
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+      const int k0 = 64 * s + 16 * g;
+      a[s] = v4i{0, 0, 0, 0};
+      if (ev && k0 < C) {
+        a[s] = ld16(S.in + (int64_t)p * S.in_stride + k0);
+      } else if (ev && k0 == C) {  // occupancy bits as int8 {0,127}, then zeros
+        uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          if ((pc >> b) & 1u) w0 |= 127u << (8 * b);
+          if ((pc >> (b + 4)) & 1u) w1 |= 127u << (8 * b);
+        }
+        a[s] = v4i{(int)w0, (int)w1, 0, 0};
+      }
+    }
+    const int first = ev ? gp(S.cstart)[p] : 0;
+    v4i acc[NBS];
+#pragma unroll
+    for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; s++)
+#pragma unroll
+      for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(wb[s][nb], a[s], acc[nb]);
+    if (!ev) continue;
+    const int crow = first + __popc(pc & ((1u << o) - 1u));
+    if (crow >= S.child_rows) continue;  // only for a corrupt stream
+    GAS uint32_t* dst = (GAS uint32_t*)(gp(S.out) + (int64_t)crow * S.out_stride + 4 * g);
+#pragma unroll
+    for (int nb = 0; nb < NBS; nb++) {
+      uint32_t packed = 0;
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int y = requant_l(acc[nb][i] + bb[nb][i], L);
+        packed |= ((uint32_t)y & 0xFFu) << (8 * i);
+      }
+      dst[4 * nb] = packed;
+    }
+  }
+}
+
+hipError_t launch_up_cx(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A,
+                        hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (C == 16) hipLaunchKernelGGL((k_up_cx<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else if (C == 32) hipLaunchKernelGGL((k_up_cx<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else if (C == 64) hipLaunchKernelGGL((k_up_cx<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, int rb,

@@ -453,6 +453,7 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
 // row whatever the insertion order.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kEmpty = ~0ull;
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint64_t hmix(uint64_t k) {
   k ^= k >> 33;
@@ -463,69 +464,82 @@ __device__ __forceinline__ uint64_t hmix(uint64_t k) {
   return k;
 }
 
-__device__ __forceinline__ void hash_put(uint64_t k, int32_t row, uint64_t* tkeys, int32_t* tvals, uint64_t mask) {
-  uint64_t slot = hmix(k) & mask;
+__device__ __forceinline__ uint64_t hslot(uint64_t k, uint64_t mask) { return hmix(k) & mask; }
+
+__device__ __forceinline__ void hash_put(uint64_t k, int32_t row, uint64_t* table, uint64_t mask) {
+  uint64_t slot = hslot(k, mask);
   for (uint64_t probe = 0; probe <= mask; probe++) {
     unsigned long long prev = kEmpty;
-    __hip_atomic_compare_exchange_strong((GAS unsigned long long*)&tkeys[slot], &prev, (unsigned long long)k,
+    __hip_atomic_compare_exchange_strong((GAS unsigned long long*)&table[2 * slot], &prev, (unsigned long long)k,
                                          __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (prev == kEmpty || prev == k) {
-      gp(tvals)[slot] = row;
+      ((GAS int32_t*)(table + 2 * slot + 1))[0] = row;
       return;
     }
     slot = (slot + 1) & mask;
   }
 }
 
-__global__ void k_hash_insert(const uint64_t* __restrict__ keys, int64_t n, uint64_t* tkeys, int32_t* tvals,
-                              uint64_t mask) {
+__global__ void k_hash_insert(const uint64_t* __restrict__ keys, int64_t n, uint64_t* table, uint64_t mask) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  hash_put(keys[i], (int32_t)i, tkeys, tvals, mask);
+  hash_put(keys[i], (int32_t)i, table, mask);
 }
 
-hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
-                              hipStream_t s) {
+hipError_t launch_hash_insert(const uint64_t* keys, int64_t n, uint64_t* table, uint64_t mask, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, tkeys, tvals,
-                     mask);
+  hipLaunchKernelGGL(k_hash_insert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, table, mask);
   return hipGetLastError();
 }
 
-// One lane per (node, tap): neighbour (dx,dy,dz) of tap 9(dx+1)+3(dy+1)+(dz+1);
-// kmap[tap * kstride + node] = its row, or -1 when empty / outside [0,2^j)^3.
-__device__ __forceinline__ void kmap_one(const uint64_t* __restrict__ keys, int64_t gid, int j,
-                                         const uint64_t* __restrict__ tkeys, const int32_t* __restrict__ tvals,
-                                         uint64_t mask, int32_t* __restrict__ kmap, int64_t kstride) {
-  int64_t i = gid / 27;
-  int t = (int)(gid - i * 27);
-  uint64_t key = gp(keys)[i];
-  uint64_t low = j > 0 ? (key & ((1ull << (3 * j)) - 1)) : 0;
-  uint64_t tag = key ^ low;
-  int x = (int)compact3(low >> 2) + t / 9 - 1;
-  int y = (int)compact3(low >> 1) + (t / 3) % 3 - 1;
-  int z = (int)compact3(low) + t % 3 - 1;
-  int side = 1 << j;
+// Neighbour table: a wave serves two nodes, lanes 0-26 and 32-58 one tap
+// each: neighbour (dx,dy,dz) of tap 9(dx+1)+3(dy+1)+(dz+1).
+// kmap[tap * kstride + node] = the neighbour's row, or -1 when empty or
+// outside [0,2^j)^3; kmap[27 * kstride + node] = the node's presence mask
+// (bit tap set when that neighbour exists; the node itself is tap 13),
+// gathered from the wave's ballot.  Every lane probes on its own, so the
+// probes of a node are in flight together.
+__device__ __forceinline__ void kmap_pair(const uint64_t* __restrict__ keys, int64_t n, int64_t wv, int j,
+                                          const uint64_t* __restrict__ table, uint64_t mask,
+                                          int32_t* __restrict__ kmap, int64_t kstride) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = 2 * wv + (lane >> 5);
+  const int t = lane & 31;
+  const bool valid = t < 27 && i < n;
   int32_t r = -1;
-  if (x >= 0 && y >= 0 && z >= 0 && x < side && y < side && z < side) {
-    uint64_t q = tag | (spread3((uint32_t)x) << 2) | (spread3((uint32_t)y) << 1) | spread3((uint32_t)z);
-    uint64_t slot = hmix(q) & mask;
-    for (uint64_t probe = 0; probe <= mask; probe++) {
-      uint64_t v = gp(tkeys)[slot];
-      if (v == q) { r = gp(tvals)[slot]; break; }
-      if (v == kEmpty) break;
-      slot = (slot + 1) & mask;
+  if (valid) {
+    const uint64_t key = gp(keys)[i];
+    const uint64_t low = j > 0 ? (key & ((1ull << (3 * j)) - 1)) : 0;
+    const uint64_t tag = key ^ low;
+    const int x = (int)compact3(low >> 2) + t / 9 - 1;
+    const int y = (int)compact3(low >> 1) + (t / 3) % 3 - 1;
+    const int z = (int)compact3(low) + t % 3 - 1;
+    const int side = 1 << j;
+    if (x >= 0 && y >= 0 && z >= 0 && x < side && y < side && z < side) {
+      const uint64_t q = tag | (spread3((uint32_t)x) << 2) | (spread3((uint32_t)y) << 1) | spread3((uint32_t)z);
+      uint64_t slot = hslot(q, mask);
+      for (uint64_t probe = 0; probe <= mask; probe++) {
+        const u64x2 e = ((const GAS u64x2*)table)[slot];
+        if (e.x == q) {
+          r = (int32_t)(uint32_t)e.y;
+          break;
+        }
+        if (e.x == kEmpty) break;
+        slot = (slot + 1) & mask;
+      }
     }
+    gp(kmap)[(int64_t)t * kstride + i] = r;
   }
-  gp(kmap)[(int64_t)t * kstride + i] = r;
+  const uint64_t m = __ballot(r >= 0);
+  if (t == 0 && i < n) gp(kmap)[27 * kstride + i] = (int32_t)(uint32_t)(m >> (lane & 32));
 }
 
-__global__ void k_kmap(const uint64_t* __restrict__ keys, int64_t n, int j, const uint64_t* __restrict__ tkeys,
-                       const int32_t* __restrict__ tvals, uint64_t mask, int32_t* __restrict__ kmap,
-                       int64_t kstride) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n * 27) return;
-  kmap_one(keys, gid, j, tkeys, tvals, mask, kmap, kstride);
+__global__ __launch_bounds__(256) void k_kmap(const uint64_t* __restrict__ keys, int64_t n, int j,
+                                              const uint64_t* __restrict__ table, uint64_t mask,
+                                              int32_t* __restrict__ kmap, int64_t kstride) {
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (2 * wv >= n) return;  // wave-uniform
+  kmap_pair(keys, n, wv, j, table, mask, kmap, kstride);
 }
 
 // Several depths per launch: block b belongs to the last job whose first
@@ -543,14 +557,14 @@ __global__ __launch_bounds__(kHashBlock) void k_hash_insert_multi(const HashJob*
   const HashJob J = jobs[job_of(jobs, njobs, false)];
   const int64_t i = (int64_t)((int)blockIdx.x - J.blk_insert) * kHashBlock + threadIdx.x;
   if (i >= J.n) return;
-  hash_put(gp(J.keys)[i], (int32_t)i, J.tkeys, J.tvals, J.mask);
+  hash_put(gp(J.keys)[i], (int32_t)i, J.table, J.mask);
 }
 
 __global__ __launch_bounds__(kHashBlock) void k_kmap_multi(const HashJob* __restrict__ jobs, int njobs) {
   const HashJob J = jobs[job_of(jobs, njobs, true)];
-  const int64_t gid = (int64_t)((int)blockIdx.x - J.blk_kmap) * kHashBlock + threadIdx.x;
-  if (gid >= J.n * 27) return;
-  kmap_one(J.keys, gid, J.j, J.tkeys, J.tvals, J.mask, J.kmap, J.kstride);
+  const int64_t wv = ((int64_t)((int)blockIdx.x - J.blk_kmap) * kHashBlock + threadIdx.x) >> 6;
+  if (2 * wv >= J.n) return;  // wave-uniform
+  kmap_pair(J.keys, J.n, wv, J.j, J.table, J.mask, J.kmap, J.kstride);
 }
 
 hipError_t launch_hash_multi(const HashJob* jobs_dev, int njobs, int insert_blocks, int kmap_blocks,
@@ -561,12 +575,11 @@ hipError_t launch_hash_multi(const HashJob* jobs_dev, int njobs, int insert_bloc
   return hipGetLastError();
 }
 
-hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* tkeys, const int32_t* tvals,
-                       uint64_t mask, int32_t* kmap, int64_t kstride, hipStream_t s) {
+hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* table, uint64_t mask,
+                       int32_t* kmap, int64_t kstride, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  int64_t tot = n * 27;
-  hipLaunchKernelGGL(k_kmap, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, keys, n, j, tkeys, tvals, mask,
-                     kmap, kstride);
+  hipLaunchKernelGGL(k_kmap, dim3((unsigned)((n + 7) / 8)), dim3(256), 0, s, keys, n, j, table, mask, kmap,
+                     kstride);
   return hipGetLastError();
 }
 
@@ -605,8 +618,8 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
                                                        const uint8_t* __restrict__ codes, int64_t n,
                                                        const uint32_t* __restrict__ csum, int sums_are_offsets,
                                                        uint64_t* __restrict__ ckeys, int32_t* __restrict__ cstart,
-                                                       int64_t expected, uint64_t* tkeys, int32_t* tvals,
-                                                       uint64_t mask, uint32_t* err) {
+                                                       int64_t expected, uint64_t* table, uint64_t mask,
+                                                       uint32_t* err) {
   __shared__ uint32_t wtot[4];
   __shared__ uint32_t run;
   __shared__ uint64_t kids[8 * 256];  // child keys of the current round, in child order
@@ -661,7 +674,7 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
       if ((int64_t)r >= expected) break;
       const uint64_t k = kids[j];
       ckeys[r] = k;
-      if (tkeys != nullptr) hash_put(k, (int32_t)r, tkeys, tvals, mask);
+      if (table != nullptr) hash_put(k, (int32_t)r, table, mask);
     }
     __syncthreads();
     if (threadIdx.x == 0) run = r0 + nk;
@@ -671,8 +684,8 @@ __global__ __launch_bounds__(256) void k_expand_chunks(const Chunk* __restrict__
 
 hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t* pkeys, const uint8_t* codes,
                                 int64_t n, uint32_t* csum, uint64_t* ckeys, int32_t* cstart,
-                                int64_t n_child_expected, uint64_t* tkeys, int32_t* tvals, uint64_t mask,
-                                uint32_t* err, hipStream_t s) {
+                                int64_t n_child_expected, uint64_t* table, uint64_t mask, uint32_t* err,
+                                hipStream_t s) {
   if (nchunks <= 0 || n <= 0) return hipSuccess;
   int offs = 0;
   if (nchunks > kExpandDirect) {
@@ -680,7 +693,7 @@ hipError_t launch_expand_chunks(const Chunk* chunks, int nchunks, const uint64_t
     offs = 1;
   }
   hipLaunchKernelGGL(k_expand_chunks, dim3(nchunks), dim3(256), 0, s, chunks, nchunks, pkeys, codes, n,
-                     (const uint32_t*)csum, offs, ckeys, cstart, n_child_expected, tkeys, tvals, mask, err);
+                     (const uint32_t*)csum, offs, ckeys, cstart, n_child_expected, table, mask, err);
   return hipGetLastError();
 }
 

@@ -664,11 +664,10 @@ struct Levels {
 // Model-phase buffers (depth d arrays are [tot[d]] rows)
 struct ModelBufs {
   int8_t* F[kMaxD + 1] = {};         // features that predict depth d (shallow d and k0)
-  int32_t* kmap[kMaxD + 1] = {};     // [27][tot[j]] for the depths that convolve
-  uint64_t* hkeys[kMaxD + 1] = {};
-  int32_t* hvals[kMaxD + 1] = {};
+  int32_t* kmap[kMaxD + 1] = {};     // [28][tot[j]] for the depths that convolve: 27 taps, masks
+  uint64_t* hkeys[kMaxD + 1] = {};   // hash tables: 16-byte slots {u64 key, i32 row}
   uint64_t hmask[kMaxD + 1] = {};
-  uint64_t* hash_lo = nullptr;        // first word of the contiguous key arrays
+  uint64_t* hash_lo = nullptr;        // first word of the contiguous tables
   size_t hash_words = 0;              // their extent in u64 words
   int8_t *h = nullptr, *S = nullptr;  // shallow ResBlock temporaries
   int8_t* E = nullptr;                // embedded parent codes (schedule without propagation)
@@ -706,14 +705,13 @@ void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, cons
     uint64_t sz = 1;
     while (sz < (uint64_t)std::max<int64_t>(2 * fr.tot[j], 2)) sz <<= 1;
     B.hmask[j] = sz - 1;
-    B.hkeys[j] = A.take<uint64_t>(sz);
+    B.hkeys[j] = A.take<uint64_t>(2 * sz);
     if (!B.hash_lo) B.hash_lo = B.hkeys[j];
-    B.hash_words = (size_t)(B.hkeys[j] + sz - B.hash_lo);
+    B.hash_words = (size_t)(B.hkeys[j] + 2 * sz - B.hash_lo);
   }
   for (int j = 0; j <= kmax; j++) {
     if (!hashed(j)) continue;
-    B.hvals[j] = A.take<int32_t>(B.hmask[j] + 1);
-    B.kmap[j] = A.take<int32_t>((size_t)27 * fr.tot[j]);
+    B.kmap[j] = A.take<int32_t>((size_t)28 * fr.tot[j]);  // 27 taps + the presence masks
   }
   for (int d = k0 + 1; d <= last; d++) {
     if (!wanted[d]) continue;
@@ -754,8 +752,7 @@ void plan_kmaps(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, cons
     HashJob h;
     memset(&h, 0, sizeof(h));
     h.keys = lv.key[j];
-    h.tkeys = B.hkeys[j];
-    h.tvals = B.hvals[j];
+    h.table = B.hkeys[j];
     h.kmap = B.kmap[j];
     h.n = fr.tot[j];
     h.kstride = fr.tot[j];
@@ -764,7 +761,7 @@ void plan_kmaps(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, cons
     h.blk_insert = ib;
     h.blk_kmap = kb;
     ib += (int)((h.n + kHashBlock - 1) / kHashBlock);
-    kb += (int)((27 * h.n + kHashBlock - 1) / kHashBlock);
+    kb += (int)((h.n + 7) / 8);  // neighbour blocks: 8 nodes each (two per wave)
     units += h.n;
     jobs.push_back(h);
   }
@@ -780,11 +777,10 @@ void plan_kmaps(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, cons
 void plan_kmap_only(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, int j, hipStream_t st) {
   const int64_t n = fr.tot[j];
   const uint64_t* hk = B.hkeys[j];
-  const int32_t* hv = B.hvals[j];
   const uint64_t mask = B.hmask[j];
   int32_t* km = B.kmap[j];
   const uint64_t* keys = lv.key[j];
-  b.launch("hash", n, [=](const uint8_t*) { return launch_kmap(keys, n, j, hk, hv, mask, km, n, st); });
+  b.launch("hash", n, [=](const uint8_t*) { return launch_kmap(keys, n, j, hk, mask, km, n, st); });
 }
 
 const LayerDev& hlayer(const lpcc_model* m, const LayerDev* dev) { return m->h_layers[dev - m->d_layers]; }
@@ -814,6 +810,14 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
     const int nt = (int)count_tiles(rows);
     b.launch(f, units, [=](const uint8_t* base) {
       return launch_emb((const GemmSeg*)(base + so), (const Tile*)(base + to), nt, cout, one, st);
+    });
+    return;
+  }
+  if (f == "up") {  // compacted by child slot inside tiles of kUpTile parents (no tile tuning)
+    const size_t to = segs.size() == 1 ? 0 : b.add(make_tiles(rows, kUpTile));
+    const int nt = (int)count_tiles(rows, kUpTile);
+    b.launch(f, units, [=](const uint8_t* base) {
+      return launch_up_cx(cout, (const GemmSeg*)(base + so), (const Tile*)(base + to), nt, one, st);
     });
     return;
   }
@@ -2368,10 +2372,9 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       uint32_t* cs = csum;
       const bool hashed = d + 1 <= k0 && d + 1 >= nb && B.kmap[d + 1];
       uint64_t* tk = hashed ? B.hkeys[d + 1] : nullptr;
-      int32_t* tv = hashed ? B.hvals[d + 1] : nullptr;
       const uint64_t hm = hashed ? B.hmask[d + 1] : 0;
       b.launch("expand", np, [=](const uint8_t* base) {
-        return launch_expand_chunks((const Chunk*)(base + co), nch, pk, codes, np, cs, ck, cst, nc, tk, tv, hm, e1,
+        return launch_expand_chunks((const Chunk*)(base + co), nch, pk, codes, np, cs, ck, cst, nc, tk, hm, e1,
                                     st);
       });
     }
