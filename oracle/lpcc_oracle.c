@@ -437,7 +437,7 @@ static void logits_to_cdf(const int8_t *l, int32_t *cdf)
     for (int i = 0; i < NSYM; i++) cdf[i + 1] = cdf[i] + (int32_t)f[i];
 }
 
-/* Base geometry (Sec. S3.1, last paragraph of the network details: the     */
+/* Base geometry (Sec. S2, "Detailed Model Structure", last paragraph: the  */
 /* levels that are not modelled are coded directly from the frequencies of  */
 /* their symbols).  For a depth d < B the counts n_s of its occupancy codes */
 /* give the frequencies by the same rule as the softmax above, with the     */

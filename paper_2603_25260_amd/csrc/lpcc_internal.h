@@ -135,8 +135,9 @@ struct GemmSeg {
   int64_t in2_stride;
   int32_t split;           // first channel read from in2 (cin when unused)
   int32_t pad_;
-  const int32_t* kmap;     // conv: [27][kstride] source rows (-1 = empty)
+  const int32_t* kmap;     // conv: [28][kstride]: 27 tap rows of source rows (-1 = empty), presence masks
   int64_t kstride;
+  const uint8_t* ccode;    // down: when set, child c reads row ccode[c] of `in` (a table indexed by code)
   const uint8_t* code;     // down/up: occupancy codes of the parents
   const int32_t* cstart;   // down/up: first child row of each parent
   const LayerDev* L;
@@ -274,6 +275,11 @@ hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int 
 constexpr int kUpTile = 512;
 hipError_t launch_up_cx(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
                         hipStream_t s);
+// child convolution (C -> C) over the occupied children only; tiles of
+// kDownTile parents
+constexpr int kDownTile = 128;
+hipError_t launch_down_cx(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
+                          hipStream_t s);
 hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, const GemmArg& one,
                       hipStream_t s);
 // single-segment predictor launches up to this many rows take 4 rows per wave

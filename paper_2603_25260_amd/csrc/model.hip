@@ -974,12 +974,51 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
   const int G = (int)goff[8];
   // wave w takes the contiguous groups [G w / 4, G (w + 1) / 4)
   const int gb = (G * wave) / 4, ge = (G * (wave + 1)) / 4;
-  int cur = -1;
-  v4i wb[KS][NBS], bb[NBS];
-  for (int gi = gb; gi < ge; gi++) {
+  // operands of group gi: its slot, the column's parent, that parent's
+  // input slice and first child (fetched one group ahead of the MFMAs)
+  struct Op {
+    int o, p, first;
+    bool ev;
+    uint32_t pc;
+    v4i a[KS];
+  };
+  auto fetch = [&](int gi, Op& x) {
     int o = 0;
 #pragma unroll
     for (int q = 1; q < 8; q++) o += gi >= (int)goff[q] ? 1 : 0;
+    const int e = 16 * (gi - (int)goff[o]) + r;  // entry of column r
+    x.o = o;
+    x.ev = e < (int)cnt[o];
+    const int t = x.ev ? (int)list[o][e] : 0;
+    x.p = p0 + t;
+    x.pc = pcode[t];
+    // column operand: k-slice 16 g of the parent's [Z | bits(X)] row
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+      const int k0 = 64 * s + 16 * g;
+      x.a[s] = v4i{0, 0, 0, 0};
+      if (x.ev && k0 < C) {
+        x.a[s] = ld16(S.in + (int64_t)x.p * S.in_stride + k0);
+      } else if (x.ev && k0 == C) {  // occupancy bits as int8 {0,127}, then zeros
+        uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+          if ((x.pc >> b) & 1u) w0 |= 127u << (8 * b);
+          if ((x.pc >> (b + 4)) & 1u) w1 |= 127u << (8 * b);
+        }
+        x.a[s] = v4i{(int)w0, (int)w1, 0, 0};
+      }
+    }
+    x.first = x.ev ? gp(S.cstart)[x.p] : 0;
+  };
+  int cur = -1;
+  v4i wb[KS][NBS], bb[NBS];
+  Op nx;
+  if (gb < ge) fetch(gb, nx);
+  for (int gi = gb; gi < ge; gi++) {
+    const Op x = nx;
+    if (gi + 1 < ge) fetch(gi + 1, nx);
+    const int o = x.o;
     if (o != cur) {  // weights and biases of slot o (wave-uniform)
       cur = o;
 #pragma unroll
@@ -989,37 +1028,18 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
 #pragma unroll
       for (int nb = 0; nb < NBS; nb++) bb[nb] = Bp[(o * C + 16 * nb + 4 * g) / 4];
     }
-    const int e = 16 * (gi - (int)goff[o]) + r;  // entry of column r
-    const bool ev = e < (int)cnt[o];
-    const int t = ev ? (int)list[o][e] : 0;
-    const int p = p0 + t;
-    const uint32_t pc = pcode[t];
-    // column operand: k-slice 16 g of the parent's [Z | bits(X)] row
-    v4i a[KS];
-#pragma unroll
-    for (int s = 0; s < KS; s++) {
-      const int k0 = 64 * s + 16 * g;
-      a[s] = v4i{0, 0, 0, 0};
-      if (ev && k0 < C) {
-        a[s] = ld16(S.in + (int64_t)p * S.in_stride + k0);
-      } else if (ev && k0 == C) {  // occupancy bits as int8 {0,127}, then zeros
-        uint32_t w0 = 0, w1 = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-          if ((pc >> b) & 1u) w0 |= 127u << (8 * b);
-          if ((pc >> (b + 4)) & 1u) w1 |= 127u << (8 * b);
-        }
-        a[s] = v4i{(int)w0, (int)w1, 0, 0};
-      }
-    }
-    const int first = ev ? gp(S.cstart)[p] : 0;
+    const bool ev = x.ev;
+    const int p = x.p;
+    const uint32_t pc = x.pc;
+    const int first = x.first;
+    (void)p;
     v4i acc[NBS];
 #pragma unroll
     for (int nb = 0; nb < NBS; nb++) acc[nb] = v4i{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < KS; s++)
 #pragma unroll
-      for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(wb[s][nb], a[s], acc[nb]);
+      for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(wb[s][nb], x.a[s], acc[nb]);
     if (!ev) continue;
     const int crow = first + __popc(pc & ((1u << o) - 1u));
     if (crow >= S.child_rows) continue;  // only for a corrupt stream
@@ -1035,6 +1055,182 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
       dst[4 * nb] = packed;
     }
   }
+}
+
+// Child convolution (the stride-2 step of the re-densification, Eq. 4) over
+// the occupied children only: out[q] = rq(b + sum over children c of q of
+// in[c] W[slot(c)]).  A block takes kDownTile consecutive parents, compacts
+// them per child slot as the upsampling does, and multiplies 16-entry groups
+// of one slot (the slot's weights as the row operand, the 16 children's
+// input rows as the columns).  Each lane then holds four consecutive output
+// channels of one child's contribution and adds them into its parent's
+// int32 accumulator row in LDS (a parent with several children collects one
+// contribution per slot; integer adds, so the order does not matter).  The
+// accumulators are requantised once all groups are done.  With `ccode` set,
+// child c reads row ccode[c] of `in`: the occupancy embedding of depth j
+// depends on the code alone, so the first step reads a 256-row table.
+template <int C>
+__global__ __launch_bounds__(256) void k_down_cx(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+                                                 const GemmArg A) {
+  constexpr int P = kDownTile;
+  constexpr int NB = C / 16;
+  constexpr int KS = (C + 63) / 64;
+  static_assert(C % 16 == 0 && P <= 256 && P % 64 == 0, "shape");
+  __shared__ int32_t accs[P][C + 1];
+  __shared__ uint8_t list[8][P];
+  __shared__ uint8_t pcode[P];
+  __shared__ int32_t pfirst[P];
+  __shared__ uint32_t wtot[8][P / 64];
+  __shared__ uint32_t cnt[8];
+  __shared__ uint32_t goff[9];
+
+  GemmSeg S;
+  LayerDev L;
+  const int q0 = pick_seg(segs, tiles, A, S, L, P);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+
+  for (int k = threadIdx.x; k < P * (C + 1); k += 256) (&accs[0][0])[k] = 0;
+  uint32_t code = 0u, rk[8];
+  if ((int)threadIdx.x < P) {
+    const int q = q0 + (int)threadIdx.x;
+    code = q < S.rows ? ((uint32_t)gp(S.code)[q] & 0xFFu) : 0u;
+    pcode[threadIdx.x] = (uint8_t)code;
+    pfirst[threadIdx.x] = q < S.rows ? gp(S.cstart)[q] : 0;
+#pragma unroll
+    for (int o = 0; o < 8; o++) {
+      const uint64_t m = __ballot((code >> o) & 1u);
+      rk[o] = lanes_below(m);
+      if (lane == 0) wtot[o][wave] = (uint32_t)__popcll(m);
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < P) {
+#pragma unroll
+    for (int o = 0; o < 8; o++) {
+      if (!((code >> o) & 1u)) continue;
+      uint32_t before = rk[o];
+      for (int w = 0; w < wave; w++) before += wtot[o][w];
+      list[o][before] = (uint8_t)threadIdx.x;
+    }
+  }
+  if (threadIdx.x < 8) {
+    uint32_t n = 0;
+    for (int w = 0; w < P / 64; w++) n += wtot[threadIdx.x][w];
+    cnt[threadIdx.x] = n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t gsum = 0;
+    for (int o = 0; o < 8; o++) {
+      goff[o] = gsum;
+      gsum += (cnt[o] + 15) / 16;
+    }
+    goff[8] = gsum;
+  }
+  __syncthreads();
+
+  const GAS v4i* Wp = (const GAS v4i*)L.Wp;
+  const int G = (int)goff[8];
+  const int gb = (G * wave) / 4, ge = (G * (wave + 1)) / 4;
+  // operands of group gi: its slot, the column's parent and child, the
+  // child's input slice (fetched one group ahead of the MFMAs)
+  struct Op {
+    int o, t;
+    bool cv;
+    v4i a[KS];
+  };
+  auto fetch = [&](int gi, Op& x) {
+    int o = 0;
+#pragma unroll
+    for (int q = 1; q < 8; q++) o += gi >= (int)goff[q] ? 1 : 0;
+    const int e = 16 * (gi - (int)goff[o]) + r;  // entry of column r
+    const bool ev = e < (int)cnt[o];
+    const int t = ev ? (int)list[o][e] : 0;
+    const uint32_t pc = pcode[t];
+    const int c = pfirst[t] + __popc(pc & ((1u << o) - 1u));
+    x.o = o;
+    x.t = t;
+    x.cv = ev && c < S.child_rows;  // out of range only for a corrupt stream
+    const int64_t src = !x.cv ? 0 : (S.ccode != nullptr ? (int64_t)gp(S.ccode)[c] : (int64_t)c);
+#pragma unroll
+    for (int s = 0; s < KS; s++) {
+      const int k0 = 64 * s + 16 * g;
+      x.a[s] = v4i{0, 0, 0, 0};
+      if (x.cv && k0 < C) x.a[s] = ld16(S.in + src * S.in_stride + k0);
+    }
+  };
+  int cur = -1;
+  v4i wb[KS][NB];
+  Op nx;
+  if (gb < ge) fetch(gb, nx);
+  for (int gi = gb; gi < ge; gi++) {
+    const Op x = nx;
+    if (gi + 1 < ge) fetch(gi + 1, nx);
+    const int o = x.o;
+    if (o != cur) {  // the slot's weights: rows k = o C + c of the packed layout
+      cur = o;
+#pragma unroll
+      for (int s = 0; s < KS; s++) {
+        const bool kv = 64 * s + 16 * g < C;
+        const int ko = kv ? o * C + 64 * s + 16 * g : 0;
+        const GAS v4i* w = Wp + (int64_t)(ko >> 6) * NB * 64 + ((ko >> 4) & 3) * 16 + r;
+#pragma unroll
+        for (int nb = 0; nb < NB; nb++) {
+          const v4i y = w[kv ? nb * 64 : 0];
+          wb[s][nb] = kv ? y : v4i{0, 0, 0, 0};
+        }
+      }
+    }
+    const int t = x.t;
+    const bool cv = x.cv;
+    v4i acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++) acc[nb] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; s++)
+#pragma unroll
+      for (int nb = 0; nb < NB; nb++) acc[nb] = mfma16(wb[s][nb], x.a[s], acc[nb]);
+    if (!cv) continue;
+#pragma unroll
+    for (int nb = 0; nb < NB; nb++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) atomicAdd(&accs[t][16 * nb + 4 * g + i], acc[nb][i]);
+  }
+  __syncthreads();
+
+  // requantise: thread (row, 4-channel group), rows in steps of 256 / (C / 4)
+  constexpr int LPR = C / 4;
+  const int c4 = (threadIdx.x % LPR) * 4;
+  int bia[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) bia[q] = gp(L.bias)[c4 + q];
+  for (int t = threadIdx.x / LPR; t < P; t += 256 / LPR) {
+    const int q = q0 + t;
+    if (q >= S.rows) break;
+    const uint32_t pc = pcode[t];
+    uint32_t packed = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      int a = accs[t][c4 + k] + bia[k];
+      if (L.zc != nullptr) {
+        for (int o = 0; o < 8; o++)
+          if ((pc >> o) & 1u) a += gp(L.zc)[o * L.npad + c4 + k];
+      }
+      packed |= ((uint32_t)requant_l(a, L) & 0xFFu) << (8 * k);
+    }
+    *(GAS uint32_t*)(gp(S.out) + (int64_t)q * S.out_stride + c4) = packed;
+  }
+}
+
+hipError_t launch_down_cx(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A,
+                          hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (C == 16) hipLaunchKernelGGL((k_down_cx<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else if (C == 32) hipLaunchKernelGGL((k_down_cx<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else if (C == 64) hipLaunchKernelGGL((k_down_cx<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_up_cx(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A,
@@ -1092,7 +1288,7 @@ __global__ __launch_bounds__(256) void k_emb(const GemmSeg* __restrict__ segs, c
 #pragma unroll
   for (int k = 0; k < 16; k++) {
     const int row = tile_row0 + (threadIdx.x >> cs) + k * rstep;
-    code[k] = (k < nrow && row < S.rows) ? gp(S.code)[row] : 0u;
+    code[k] = (k < nrow && row < S.rows) ? (S.code != nullptr ? (uint32_t)gp(S.code)[row] : (uint32_t)row) : 0u;
   }
 #pragma unroll
   for (int k = 0; k < 16; k++) {

@@ -715,7 +715,9 @@ void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, cons
   }
   for (int d = k0 + 1; d <= last; d++) {
     if (!wanted[d]) continue;
-    for (int j = d - 1; j > k0; j--) B.G[d][j] = A.take<int8_t>((size_t)fr.tot[j] * C);
+    // the embedding of depth d-1 depends on the code alone: a 256-row table
+    // when a child convolution reads it, rows of depth k0 otherwise
+    for (int j = d - 1; j > k0; j--) B.G[d][j] = A.take<int8_t>((size_t)(j == d - 1 ? 256 : fr.tot[j]) * C);
     B.Gk[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
     B.dh[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
     B.ds[d] = A.take<int8_t>((size_t)fr.tot[k0] * C);
@@ -810,6 +812,14 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
     const int nt = (int)count_tiles(rows);
     b.launch(f, units, [=](const uint8_t* base) {
       return launch_emb((const GemmSeg*)(base + so), (const Tile*)(base + to), nt, cout, one, st);
+    });
+    return;
+  }
+  if (f == "down") {  // compacted by child slot inside tiles of kDownTile parents (no tile tuning)
+    const size_t to = segs.size() == 1 ? 0 : b.add(make_tiles(rows, kDownTile));
+    const int nt = (int)count_tiles(rows, kDownTile);
+    b.launch(f, units, [=](const uint8_t* base) {
+      return launch_down_cx(cout, (const GemmSeg*)(base + so), (const Tile*)(base + to), nt, one, st);
     });
     return;
   }
@@ -988,12 +998,13 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
     std::vector<GemmSeg> v;
     for (int d : dset) {
       GemmSeg s = seg0();
-      s.code = lv.code[d - 1];
+      const bool table = d - 1 > k0;  // every code's embedding (code = row)
+      s.code = table ? nullptr : lv.code[d - 1];
       s.L = dlayer(m, d, 0);
       auto o = Gout(d, d - 1);
       s.out = o.first;
       s.out_stride = o.second;
-      s.rows = (int)fr.tot[d - 1];
+      s.rows = table ? 256 : (int)fr.tot[d - 1];
       v.push_back(s);
     }
     plan_gemm(b, m, "emb", 0, 8, C, v, st);
@@ -1009,6 +1020,7 @@ void plan_deep(Batch& b, const lpcc_model* m, const Levels& lv, const Frames& fr
       GemmSeg s = seg0();
       s.in = B.G[d][j];
       s.in_stride = C;
+      if (j == d - 1) s.ccode = lv.code[j];  // the embedding table, indexed by the child's code
       s.code = lv.code[j - 1];
       s.cstart = lv.cstart[j - 1];
       s.L = dlayer(m, d, t);
