@@ -234,8 +234,9 @@ struct MortonFrames {
 // counts of pass 0 and the digit totals of every pass
 hipError_t launch_morton_sort0(const MortonFrames& mf, int D, uint64_t* keys, uint32_t* err, const SortPasses& sp,
                                uint32_t* hist, uint32_t* totals, hipStream_t s);
-// pass p: kin -> kout, stable on the pass's digit; adds the per-tile digit
-// counts of pass p+1 (of kout) into hist; ERR_SORT in *err on an impossible rank
+// pass p: kin -> kout, stable on the pass's digit (for p > 0 the pass first
+// counts its digits per tile of kin into hist); ERR_SORT in *err on an
+// impossible rank
 hipError_t launch_sort_pass(const uint64_t* kin, uint64_t* kout, int64_t n, const SortPasses& sp, int p,
                             uint32_t* hist, const uint32_t* totals, uint32_t* err, hipStream_t s);
 // Octree build over sorted keys (frame id in bits >= 3D).

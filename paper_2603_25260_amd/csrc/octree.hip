@@ -114,34 +114,33 @@ hipError_t launch_morton_sort0(const MortonFrames& mf, int D, uint64_t* keys, ui
 }
 
 // In place: hist[t][d] <- first destination of tile t's keys of digit d
-// (digits ascending, tiles ascending within a digit).  One block; thread
-// (part, d) walks a quarter of the tiles for digit d.
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist, int ntiles,
-                                                    const uint32_t* __restrict__ totals) {
-  __shared__ uint32_t psum[4][256];
+// (digits ascending, tiles ascending within a digit).  Block d scans digit
+// d over the tiles: each thread sums a run of tiles, the 256 run sums are
+// scanned in the block, and the runs are rewritten as running offsets
+// starting from the digit's base (the keys of all smaller digits).
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t* __restrict__ hist, int ntiles,
+                                                   const uint32_t* __restrict__ totals) {
   __shared__ uint32_t wsum[4];
-  __shared__ uint32_t base[256];
-  const int d = threadIdx.x & 255, part = threadIdx.x >> 8;
-  const int per = (ntiles + 3) / 4;
-  const int t0 = min(ntiles, part * per), t1 = min(ntiles, t0 + per);
+  __shared__ uint32_t base;
+  const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // base of digit d: the sum of the totals of the smaller digits
+  const uint32_t tv = tid < d ? gp(totals)[tid] : 0u;
+  const uint32_t bi = wave_scan_incl(tv);
+  if (lane == 63) wsum[wave] = bi;
+  __syncthreads();
+  if (tid == 0) base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();
+  const uint32_t b0 = base;
+  __syncthreads();
+  const int per = (ntiles + 255) / 256;
+  const int t0 = min(ntiles, tid * per), t1 = min(ntiles, t0 + per);
   uint32_t sum = 0;
   for (int t = t0; t < t1; t++) sum += gp(hist)[(int64_t)t * 256 + d];
-  psum[part][d] = sum;
-  uint32_t tot = 0, inc = 0;
-  if (part == 0) {
-    tot = gp(totals)[d];
-    inc = wave_scan_incl(tot);
-    if ((d & 63) == 63) wsum[d >> 6] = inc;
-  }
+  const uint32_t inc = wave_scan_incl(sum);
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
-  if (part == 0) {
-    uint32_t ex = inc - tot;
-    for (int w = 0; w < (d >> 6); w++) ex += wsum[w];
-    base[d] = ex;
-  }
-  __syncthreads();
-  uint32_t off = base[d];
-  for (int q = 0; q < part; q++) off += psum[q][d];
+  uint32_t off = b0 + inc - sum;
+  for (int w = 0; w < wave; w++) off += wsum[w];
   for (int t = t0; t < t1; t++) {
     const int64_t o = (int64_t)t * 256 + d;
     const uint32_t v = gp(hist)[o];
@@ -150,18 +149,33 @@ __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t* __restrict__ hist,
   }
 }
 
+// Digit counts of one pass per tile of kSortTile keys (LDS histogram, one
+// store per bin).
+__global__ __launch_bounds__(256) void k_sort_count(const uint64_t* __restrict__ kin, int64_t n, int shift, int bits,
+                                                    uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t tile = blockIdx.x;
+#pragma unroll
+  for (int k = 0; k < kSortItems; k++) {
+    const int64_t i = tile * kSortTile + k * 256 + threadIdx.x;
+    if (i < n) atomicAdd(&h[digit_of(gp(kin)[i], shift, bits)], 1u);
+  }
+  __syncthreads();
+  gp(hist)[tile * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
 // One pass: every key's destination is the first destination of its tile's
 // digit plus its rank among the tile's keys of that digit.  Ranks within a
 // wave come from a ballot match over the digit bits; the counts of every
 // (item, wave, digit) are turned into running offsets by one thread per
 // digit.  With offs_ready the tile offsets come from k_sort_scan, else the
 // pass sums the counts of the tiles before it and the totals of the smaller
-// digits itself.  The digit counts of the next pass are added per
-// destination tile.
+// digits itself.
 __global__ __launch_bounds__(256) void k_sort_scatter(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
                                                       int64_t n, int shift, int bits, const uint32_t* __restrict__ hist,
                                                       int offs_ready, const uint32_t* __restrict__ totals,
-                                                      uint32_t* __restrict__ hist_next, int shift_n, int bits_n,
                                                       uint32_t* __restrict__ err) {
   __shared__ uint32_t cnt[kSortItems][4][256];
   __shared__ uint32_t wsum[4];
@@ -221,8 +235,6 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint64_t* __restrict
       continue;
     }
     gp(kout)[dest] = key[k];
-    if (bits_n > 0)
-      atomicAdd(hist_next + (dest / kSortTile) * 256 + digit_of(key[k], shift_n, bits_n), 1u);
   }
 }
 
@@ -231,12 +243,14 @@ hipError_t launch_sort_pass(const uint64_t* kin, uint64_t* kout, int64_t n, cons
   if (n <= 0) return hipSuccess;
   const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
   uint32_t* hp = hist + (int64_t)p * ntiles * 256;
-  const bool last = p + 1 >= sp.n;
   const bool scan = ntiles > kSortFusedTiles;
-  if (scan) hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hp, (int)ntiles, totals + p * 256);
+  // pass 0's per-tile counts come with the keys; later passes count the
+  // order the previous pass left
+  if (p > 0)
+    hipLaunchKernelGGL(k_sort_count, dim3((unsigned)ntiles), dim3(256), 0, s, kin, n, sp.shift[p], sp.bits[p], hp);
+  if (scan) hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hp, (int)ntiles, totals + p * 256);
   hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)ntiles), dim3(256), 0, s, kin, kout, n, sp.shift[p], sp.bits[p],
-                     (const uint32_t*)hp, scan ? 1 : 0, totals + p * 256, last ? nullptr : hp + ntiles * 256,
-                     last ? 0 : sp.shift[p + 1], last ? 0 : sp.bits[p + 1], err);
+                     (const uint32_t*)hp, scan ? 1 : 0, totals + p * 256, err);
   return hipGetLastError();
 }
 
