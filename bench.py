@@ -28,8 +28,8 @@ The same JSON line carries, each checked the same way:
   against MI355X peaks; ``roofline_families`` gives every family;
 * ``cpu_baseline``: the CPU oracle on slices of the same frames, one worker
   process per host core of this process's CPU set (at most 16);
-* schedule variants, base depths, range-coder chunk sizes and graph mode on
-  the 64-beam frames.
+* schedule variants, base depths, range-coder chunk sizes, graph mode and
+  level-aware parameter sharing on the 64-beam frames.
 """
 from __future__ import annotations
 
@@ -366,6 +366,7 @@ def main():
         res["schedules"] = _bench_schedules(lpcc, synth, torch, ctx, f2, d2, dbs, dout)
         res["base_geometry"] = _bench_base(lpcc, torch, m2, f2, d2, dbs, dout, c2.scan.D - c2.n_deep - 1)
         res["chunk_sizes"] = _bench_chunks(lpcc, torch, ctx, m2, f2, d2, dbs, dout)
+        res["parameter_sharing"] = _bench_shared(lpcc, synth, torch, ctx, f2, d2, dbs, dout)
     if not args.no_serve:
         res["served"] = _served(args.serve_seconds, digests)
     if not args.no_cpu:
@@ -603,6 +604,35 @@ def _bench_chunks(lpcc, torch, ctx, model, frames, dxyz, dbs, dout):
         out.append({"chunk_log2": c, "mpts_s": round(pts / wall / 1e6, 3),
                     "ms_per_frame": round(wall / len(frames) * 1e3, 3),
                     "bytes_per_point": round(sum(lens) / pts, 4)})
+    return out
+
+
+def _bench_shared(lpcc, synth, torch, ctx, frames, dxyz, dbs, dout):
+    """Level-aware parameter sharing: blob sizes of the per-depth and the
+    shared models (64-beam C = 32 and 128-beam C = 64 workloads), and the
+    64-beam frames encoded and decoded with each."""
+    out = {}
+    for name in ("cfg2", "cfg4"):
+        c = synth.CONFIGS[name]
+        out[f"blob_bytes_{name}"] = {
+            "per_depth": len(synth.make_weights(c.weight_seed, c.C, c.scan.D, c.n_deep)),
+            "shared": len(synth.make_weights(c.weight_seed, c.C, c.scan.D, c.n_deep, shared=True))}
+    c = synth.CONFIGS["cfg2"]
+    for label, sh in (("per_depth", False), ("shared", True)):
+        m = lpcc.Model(synth.make_weights(c.weight_seed, c.C, c.scan.D, c.n_deep, shared=sh), 0)
+        for k in range(len(frames)):
+            n = lpcc.encode_frame(ctx, m, dxyz[k], CHUNK, out=dbs)
+            lpcc.decode_frame(ctx, m, dbs, length=n, out=dout)
+        reps = 3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for k in range(len(frames)):
+                n = lpcc.encode_frame(ctx, m, dxyz[k], CHUNK, out=dbs)
+                lpcc.decode_frame(ctx, m, dbs, length=n, out=dout)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        out[f"{label}_mpts_s_64beam"] = round(sum(len(f) for f in frames) / wall / 1e6, 3)
     return out
 
 

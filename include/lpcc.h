@@ -74,26 +74,38 @@ typedef struct lpcc_ctx lpcc_ctx;     /* device, stream, workspace of one caller
  *                (0 <= n_deep <= D - 1; the dense fusion depth is D - n_deep - 1)
  *   flags        LPCC_W_NO_XFP: the ablation schedule without cross-scale
  *                propagation (blob version 2); LPCC_W_ZERO_POINTS: activation
- *                zero points in [-8, 8] on every layer (Eq. 13-14)
+ *                zero points in [-8, 8] on every layer (Eq. 13-14);
+ *                LPCC_W_SHARED: level-aware parameter sharing (the future work
+ *                named in the last paragraph of Sec. S2): the layers of one
+ *                role share one weight tensor across depths (the predictor's
+ *                two layers at every depth; per kind the shallow depths
+ *                d <= k0 and the deep depths apart), every layer keeps its own
+ *                bias and requantisation (version flag 0x100)
  *   blob, cap    output buffer (host); may be NULL with cap = 0 to query
  *   len          bytes of the blob (also with LPCC_E_CAPACITY)
  * Layout: u32 "LPCW", u32 version, u32 C, u32 D, u32 n_deep, u32 n_layers,
  * u64 seed; per layer u32 kind, depth, j, taps, cin, cout, i32 m_pos, m_neg,
- * u32 r, i32 z_in, z_out, i32 bias[cout], i8 W[taps][cin][cout], zero
- * padding to 4 bytes.  W = (u >> 33) mod 255 - 127, bias = (u >> 33) mod 8193
+ * u32 r, i32 z_in, z_out, [shared: u32 owner, the index of the layer whose
+ * weights it uses], i32 bias[cout], i8 W[taps][cin][cout] (shared: only in
+ * the owner's record), zero padding to 4 bytes.  The draws do not depend on
+ * sharing: a shared blob is the unshared one with every layer's weights
+ * replaced by its owner's.  W = (u >> 33) mod 255 - 127, bias = (u >> 33) mod 8193
  * - 4096, r = 24, m_pos = floor(2^24 / (73.6 sqrt(taps cin))) (3/4 of it for
  * the logit layer), m_neg = 0 (ReLU), m_pos (identity) or m_pos / 4 (PReLU).
  * Errors: LPCC_E_INVAL (bad argument), LPCC_E_CAPACITY (cap < len).
  */
 #define LPCC_W_NO_XFP 1
 #define LPCC_W_ZERO_POINTS 2
+#define LPCC_W_SHARED 4
 int lpcc_make_weights(uint64_t seed, int C, int D, int n_deep, int flags, void* blob, size_t cap, size_t* len);
 
 /*
- * Weight blob -> device model (the per-depth layers of Sec. S2; parameters are
- * not shared between depths).  The blob is parsed, validated (layer order,
- * shapes, |bias| < 2^24, 0 <= m < 2^31, 0 <= r <= 62, zero points in int8) and
- * copied to `device`; the caller keeps ownership of `blob`.
+ * Weight blob -> device model (the per-depth layers of Sec. S2).  The blob is
+ * parsed, validated (layer order, shapes, |bias| < 2^24, 0 <= m < 2^31,
+ * 0 <= r <= 62, zero points in int8; in a shared blob every owner index
+ * points at an earlier or the same layer of equal shape that owns its
+ * weights) and copied to `device`, each shared weight tensor once; the caller
+ * keeps ownership of `blob`.
  * Errors: LPCC_E_INVAL (null), LPCC_E_MODEL (bad blob), LPCC_E_DEVICE / NOMEM.
  */
 int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out);

@@ -181,6 +181,7 @@ typedef struct {
     int r, z_in, z_out;
     const int32_t *bias;
     const int8_t *W;  /* [taps][cin][cout] */
+    int own;          /* the weights are stored in this layer's record */
 } layer_t;
 
 typedef struct {
@@ -234,8 +235,14 @@ static void model_free(model_t *M) { free(M->L); M->L = NULL; }
 static int model_parse(const uint8_t *b, size_t len, model_t *M)
 {
     memset(M, 0, sizeof(*M));
-    if (!b || len < 32 || rd32(b) != 0x5743504Cu || (rd32(b + 4) != 1 && rd32(b + 4) != 2)) return ORC_E_MODEL;
-    M->xfp = rd32(b + 4) == 1;
+    if (!b || len < 32 || rd32(b) != 0x5743504Cu) return ORC_E_MODEL;
+    uint32_t ver = rd32(b + 4);
+    if (((ver & 0xFFu) != 1 && (ver & 0xFFu) != 2) || (ver & ~0x1FFu)) return ORC_E_MODEL;
+    /* version flag 0x100: level-aware parameter sharing (the future work of  */
+    /* Sec. S2, last paragraph; reading in the design notes): each record     */
+    /* names the layer whose weights it uses, and only that layer stores them */
+    int shared = (ver & 0x100u) != 0;
+    M->xfp = (ver & 0xFFu) == 1;
     M->C = (int)rd32(b + 8); M->D = (int)rd32(b + 12); M->n_deep = (int)rd32(b + 16);
     M->n_layers = (int)rd32(b + 20);
     if (M->C < 1 || M->C > 256 || M->D < 1 || M->D > MAXD || M->n_deep < 0 || M->n_deep > M->D - 1)
@@ -262,7 +269,14 @@ static int model_parse(const uint8_t *b, size_t len, model_t *M)
             if (L->m_pos < 0 || L->m_neg < 0 || L->r < 0 || L->r > 62 || L->z_in < -128 || L->z_in > 127 ||
                 L->z_out < -128 || L->z_out > 127) goto bad;
             off += 44;
-            size_t nb = (size_t)L->cout * 4, nw = (size_t)L->taps * L->cin * L->cout;
+            int owner = li;
+            if (shared) {
+                if (off + 4 > len) goto bad;
+                owner = (int)rd32(b + off);
+                off += 4;
+                if (owner < 0 || owner > li) goto bad;
+            }
+            size_t nb = (size_t)L->cout * 4, nw = owner == li ? (size_t)L->taps * L->cin * L->cout : 0;
             if (off + nb + nw > len) goto bad;
             L->bias = (const int32_t *)(b + off);
             for (int o = 0; o < L->cout; o++) {
@@ -270,7 +284,15 @@ static int model_parse(const uint8_t *b, size_t len, model_t *M)
                 if (v <= -(1 << 24) || v >= (1 << 24)) goto bad;
             }
             off += nb;
-            L->W = (const int8_t *)(b + off);
+            if (owner == li) {
+                L->W = (const int8_t *)(b + off);
+                L->own = 1;
+            } else {
+                /* the weights of an earlier layer of the same shape that owns them */
+                const layer_t *O = &M->L[owner];
+                if (!O->own || O->taps != L->taps || O->cin != L->cin || O->cout != L->cout) goto bad;
+                L->W = O->W;
+            }
             off += nw;
             off = (off + 3) & ~(size_t)3;
         }

@@ -24,7 +24,8 @@ struct HostLayer {
   int kind, depth, j, taps, cin, cout;
   int32_t m_pos, m_neg, r, z_in, z_out;
   std::vector<int32_t> bias;
-  std::vector<int8_t> W;  // [taps][cin][cout]
+  std::vector<int8_t> W;  // [taps][cin][cout] (a copy of the owner's when shared)
+  int owner = 0;          // index of the layer whose weights these are (itself unless shared)
 };
 
 struct lpcc_model {
@@ -97,8 +98,12 @@ void softmax_table(int32_t* E) {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int parse_blob(const uint8_t* b, size_t len, lpcc_model* m) {
-  if (len < 32 || rd32(b) != 0x5743504Cu || (rd32(b + 4) != 1 && rd32(b + 4) != 2)) return LPCC_E_MODEL;
-  m->xfp = rd32(b + 4) == 1;
+  if (len < 32 || rd32(b) != 0x5743504Cu) return LPCC_E_MODEL;
+  const uint32_t ver = rd32(b + 4);
+  if ((ver & 0xFFu) != 1 && (ver & 0xFFu) != 2) return LPCC_E_MODEL;
+  if (ver & ~0x1FFu) return LPCC_E_MODEL;
+  const bool shared = (ver & 0x100u) != 0;  // level-aware parameter sharing: owner index per record
+  m->xfp = (ver & 0xFFu) == 1;
   m->C = (int)rd32(b + 8);
   m->D = (int)rd32(b + 12);
   m->n_deep = (int)rd32(b + 16);
@@ -132,7 +137,19 @@ int parse_blob(const uint8_t* b, size_t len, lpcc_model* m) {
           L.z_out > 127)
         return LPCC_E_MODEL;
       off += 44;
-      const size_t nb = (size_t)L.cout * 4, nw = (size_t)L.taps * L.cin * L.cout;
+      const int idx = (int)m->host.size();
+      L.owner = idx;
+      if (shared) {
+        if (off + 4 > len) return LPCC_E_MODEL;
+        L.owner = (int)rd32(b + off);
+        off += 4;
+        if (L.owner < 0 || L.owner > idx) return LPCC_E_MODEL;
+        if (L.owner < idx) {
+          const HostLayer& O = m->host[L.owner];
+          if (O.owner != L.owner || O.taps != L.taps || O.cin != L.cin || O.cout != L.cout) return LPCC_E_MODEL;
+        }
+      }
+      const size_t nb = (size_t)L.cout * 4, nw = L.owner == idx ? (size_t)L.taps * L.cin * L.cout : 0;
       if (off + nb + nw > len) return LPCC_E_MODEL;
       L.bias.resize(L.cout);
       for (int o = 0; o < L.cout; o++) {
@@ -140,7 +157,8 @@ int parse_blob(const uint8_t* b, size_t len, lpcc_model* m) {
         if (L.bias[o] <= -(1 << 24) || L.bias[o] >= (1 << 24)) return LPCC_E_MODEL;
       }
       off += nb;
-      L.W.assign((const int8_t*)(b + off), (const int8_t*)(b + off + nw));
+      if (L.owner == idx) L.W.assign((const int8_t*)(b + off), (const int8_t*)(b + off + nw));
+      else L.W = m->host[L.owner].W;
       off = align_up(off + nw, 4);
       m->host.push_back(std::move(L));
     }
@@ -2477,9 +2495,11 @@ int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out) 
   // one device block: per layer packed W, raw W, bias, zc; then the table
   std::vector<LayerImage> im;
   size_t bytes = 0;
-  for (auto& L : m->host) {
+  for (size_t i = 0; i < m->host.size(); i++) {
+    const HostLayer& L = m->host[i];
     im.push_back(build_image(L));
-    bytes += align_up(im.back().packed.size(), 256) + align_up(L.W.size(), 256) +
+    const bool own = L.owner == (int)i;  // shared weights are placed once, with their owner
+    bytes += (own ? align_up(im.back().packed.size(), 256) + align_up(L.W.size(), 256) : 0) +
              align_up(im.back().bias.size() * 4, 256) + align_up(im.back().zc.size() * 4, 256);
   }
   bytes += 1024 + align_up(m->host.size() * sizeof(LayerDev), 256);
@@ -2498,8 +2518,13 @@ int lpcc_model_load(const void* blob, size_t len, int device, lpcc_model** out) 
     const HostLayer& L = m->host[i];
     LayerDev& D = ld[i];
     memset(&D, 0, sizeof(D));
-    D.Wp = (const int8_t*)put(im[i].packed.data(), im[i].packed.size());
-    D.Wr = (const int8_t*)put(L.W.data(), L.W.size());
+    if (L.owner == (int)i) {
+      D.Wp = (const int8_t*)put(im[i].packed.data(), im[i].packed.size());
+      D.Wr = (const int8_t*)put(L.W.data(), L.W.size());
+    } else {
+      D.Wp = ld[L.owner].Wp;
+      D.Wr = ld[L.owner].Wr;
+    }
     D.bias = (const int32_t*)put(im[i].bias.data(), im[i].bias.size() * 4);
     D.zc = im[i].zc.empty() ? nullptr : (const int32_t*)put(im[i].zc.data(), im[i].zc.size() * 4);
     const RqBounds rq = requant_bounds(L.m_pos, L.m_neg, L.r, L.z_out);

@@ -69,6 +69,25 @@ std::vector<Rec> plan(int C, int D, int n_deep, bool xfp) {
   return v;
 }
 
+// Level-aware parameter sharing: the layer whose weights each layer uses.
+// One role per kind for the shallow depths (d <= k0) and one for the deep
+// depths, one per predictor layer for all depths; the first layer of a role
+// in blob order owns the weights.
+std::vector<int> owners(const std::vector<Rec>& layers, int k0) {
+  std::vector<int> own(layers.size());
+  std::vector<std::pair<int, int>> roles;  // (role key, owner)
+  for (size_t i = 0; i < layers.size(); i++) {
+    const Rec& L = layers[i];
+    const int key = (L.kind == lpcc::K_FC1 || L.kind == lpcc::K_FC2) ? 2 * L.kind : 2 * L.kind + (L.depth > k0 ? 1 : 0);
+    int o = (int)i;
+    for (auto& r : roles)
+      if (r.first == key) o = r.second;
+    if (o == (int)i) roles.push_back({key, (int)i});
+    own[i] = o;
+  }
+  return own;
+}
+
 void put32(std::vector<uint8_t>& b, uint32_t v) {
   for (int k = 0; k < 4; k++) b.push_back((uint8_t)(v >> (8 * k)));
 }
@@ -78,13 +97,15 @@ void put32(std::vector<uint8_t>& b, uint32_t v) {
 extern "C" int lpcc_make_weights(uint64_t seed, int C, int D, int n_deep, int flags, void* blob, size_t cap,
                                  size_t* len) {
   if (!len || !(C == 16 || C == 32 || C == 64) || D < 1 || D > lpcc::kMaxD || n_deep < 0 || n_deep > D - 1 ||
-      (flags & ~(LPCC_W_NO_XFP | LPCC_W_ZERO_POINTS)))
+      (flags & ~(LPCC_W_NO_XFP | LPCC_W_ZERO_POINTS | LPCC_W_SHARED)))
     return LPCC_E_INVAL;
   const bool xfp = !(flags & LPCC_W_NO_XFP), zp = (flags & LPCC_W_ZERO_POINTS) != 0;
+  const bool shared = (flags & LPCC_W_SHARED) != 0;
   const std::vector<Rec> layers = plan(C, D, n_deep, xfp);
+  const std::vector<int> own = owners(layers, D - n_deep - 1);
   std::vector<uint8_t> b;
   put32(b, kBlobMagic);
-  put32(b, xfp ? 1u : 2u);
+  put32(b, (xfp ? 1u : 2u) | (shared ? 0x100u : 0u));
   put32(b, (uint32_t)C);
   put32(b, (uint32_t)D);
   put32(b, (uint32_t)n_deep);
@@ -92,7 +113,8 @@ extern "C" int lpcc_make_weights(uint64_t seed, int C, int D, int n_deep, int fl
   put32(b, (uint32_t)seed);
   put32(b, (uint32_t)(seed >> 32));
   uint64_t ctr = 0;
-  for (const Rec& L : layers) {
+  for (size_t li = 0; li < layers.size(); li++) {
+    const Rec& L = layers[li];
     const int64_t nW = (int64_t)L.taps * L.cin * L.cout;
     // draws ctr+1 .. ctr+nW+cout+2: weights, biases, two zero points
     const uint64_t first = ctr;
@@ -112,8 +134,10 @@ extern "C" int lpcc_make_weights(uint64_t seed, int C, int D, int n_deep, int fl
     put32(b, 24u);
     put32(b, (uint32_t)z_in);
     put32(b, (uint32_t)z_out);
+    if (shared) put32(b, (uint32_t)own[li]);
     for (int o = 0; o < L.cout; o++) put32(b, (uint32_t)(int32_t)(hi(nW + o) % 8193 - 4096));
-    for (int64_t i = 0; i < nW; i++) b.push_back((uint8_t)(int8_t)(hi(i) % 255 - 127));
+    if (!shared || own[li] == (int)li)
+      for (int64_t i = 0; i < nW; i++) b.push_back((uint8_t)(int8_t)(hi(i) % 255 - 127));
     while (b.size() % 4) b.push_back(0);
   }
   *len = b.size();

@@ -134,12 +134,13 @@ def requant_bounds(m_pos: int, m_neg: int, r: int, z_out: int):
     return tuple(int(v) for v in out)
 
 
-W_NO_XFP, W_ZERO_POINTS = 1, 2
+W_NO_XFP, W_ZERO_POINTS, W_SHARED = 1, 2, 4
 
 
-def make_weights(seed: int, C: int, D: int, n_deep: int, *, xfp: bool = True, zero_points: bool = False) -> bytes:
+def make_weights(seed: int, C: int, D: int, n_deep: int, *, xfp: bool = True, zero_points: bool = False,
+                 shared: bool = False) -> bytes:
     """Seeded random-init weight blob, built by the library (host only)."""
-    flags = (0 if xfp else W_NO_XFP) | (W_ZERO_POINTS if zero_points else 0)
+    flags = (0 if xfp else W_NO_XFP) | (W_ZERO_POINTS if zero_points else 0) | (W_SHARED if shared else 0)
     n = ctypes.c_size_t()
     st = lib().lpcc_make_weights(seed, C, D, n_deep, flags, None, 0, ctypes.byref(n))
     if st not in (OK, E_CAPACITY):

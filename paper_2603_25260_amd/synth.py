@@ -22,7 +22,9 @@ The blob layout (little-endian) is::
     n_layers records:
       u32 kind, u32 depth, u32 j, u32 taps, u32 cin, u32 cout,
       i32 m_pos, i32 m_neg, u32 r, i32 z_in, i32 z_out,
-      i32 bias[cout], i8 W[taps][cin][cout], zero padding to 4 bytes
+      [version flag 0x100 (shared weights): u32 owner],
+      i32 bias[cout], i8 W[taps][cin][cout] (only when the layer owns its
+      weights), zero padding to 4 bytes
 
 Layer kinds and their order per coded depth d (k0 = D - n_deep - 1):
 
@@ -108,9 +110,30 @@ def splitmix64(seed: int, start: int, n: int) -> np.ndarray:
     return z
 
 
+SHARED = 0x100  # version flag: layers may take their weights from an earlier layer
+
+
+def weight_owners(C: int, D: int, n_deep: int, xfp: bool = True):
+    """Level-aware parameter sharing: for every layer of the plan, the index
+    of the layer whose weights it uses.  Layers of one role share one weight
+    tensor across depths: the predictor's two layers at every depth, and per
+    kind the layers of the shallow depths (d <= k0) and those of the deep
+    depths (d > k0) apart (their inputs differ: [S | bits] vs [Z | bits],
+    F vs [F_k0 | G]).  The first layer of a role in blob order owns the
+    weights; every layer keeps its own bias and requantisation, which is what
+    makes a shared block level-aware (a one-hot level input through a linear
+    layer is exactly a per-level bias)."""
+    k0 = D - n_deep - 1
+    owner, first = [], {}
+    for i, (kind, depth, j, taps, cin, cout) in enumerate(layer_plan(C, D, n_deep, xfp)):
+        role = (kind,) if kind in (FC1, FC2) else (kind, depth > k0)
+        owner.append(first.setdefault(role, i))
+    return owner
+
+
 def make_weights(seed: int, C: int, D: int, n_deep: int, *,
                  zero_points: bool = False, gain: float = 1.0,
-                 shift: int = 24, xfp: bool = True) -> bytes:
+                 shift: int = 24, xfp: bool = True, shared: bool = False) -> bytes:
     """Random-init integer weight blob for channel width C and D levels.
 
     W ~ uniform integers in [-127, 127]; bias uniform in [-4096, 4096];
@@ -119,12 +142,19 @@ def make_weights(seed: int, C: int, D: int, n_deep: int, *,
     m_neg = 0, identity layers m_neg = m_pos, PReLU layers (slope 64/256)
     m_neg = (m_pos * 64) >> 8.  With ``zero_points`` every layer also gets
     input/output zero points in [-8, 8] (to exercise that part of Eq. 13-14).
+    With ``shared`` the blob shares weights across depths (``weight_owners``;
+    version flag SHARED): each record carries a u32 owner index after z_out
+    and holds weights only when it owns them.  The draws are the same as for
+    the unshared blob, so a shared blob equals the unshared one with every
+    layer's weights replaced by its owner's.
     """
     plan = layer_plan(C, D, n_deep, xfp)
+    owner = weight_owners(C, D, n_deep, xfp) if shared else list(range(len(plan)))
     out = bytearray()
-    out += struct.pack("<6IQ", BLOB_MAGIC, 1 if xfp else 2, C, D, n_deep, len(plan), seed)
+    out += struct.pack("<6IQ", BLOB_MAGIC, (1 if xfp else 2) | (SHARED if shared else 0), C, D, n_deep, len(plan),
+                       seed)
     ctr = 0
-    for (kind, depth, j, taps, cin, cout) in plan:
+    for li, (kind, depth, j, taps, cin, cout) in enumerate(plan):
         nW = taps * cin * cout
         u = splitmix64(seed, ctr, nW + cout + 2)
         ctr += nW + cout + 2
@@ -144,8 +174,11 @@ def make_weights(seed: int, C: int, D: int, n_deep: int, *,
             z_in = z_out = 0
         out += struct.pack("<6I2iI2i", kind, depth, j, taps, cin, cout,
                            m_pos, m_neg, shift, z_in, z_out)
+        if shared:
+            out += struct.pack("<I", owner[li])
         out += b.tobytes()
-        out += W.tobytes()
+        if owner[li] == li:
+            out += W.tobytes()
         while len(out) % 4:
             out += b"\0"
     return bytes(out)

@@ -12,18 +12,28 @@ from paper_2603_25260_amd import synth
 
 
 def parse_blob(blob):
+    version = struct.unpack_from("<I", blob, 4)[0]
+    shared = bool(version & 0x100)  # records name the layer whose weights they use
     C, D, n_deep, n_layers = struct.unpack_from("<4I", blob, 8)
     off = 32
-    layers = {}
-    for _ in range(n_layers):
+    layers, order = {}, []
+    for li in range(n_layers):
         kind, depth, j, taps, cin, cout, m_pos, m_neg, r, z_in, z_out = struct.unpack_from("<6I2iI2i", blob, off)
         off += 44
+        owner = li
+        if shared:
+            owner = struct.unpack_from("<I", blob, off)[0]
+            off += 4
         b = np.frombuffer(blob, np.int32, cout, off).astype(np.int64)
         off += 4 * cout
-        W = np.frombuffer(blob, np.int8, taps * cin * cout, off).reshape(taps, cin, cout).astype(np.int64)
-        off += taps * cin * cout
+        if owner == li:
+            W = np.frombuffer(blob, np.int8, taps * cin * cout, off).reshape(taps, cin, cout).astype(np.int64)
+            off += taps * cin * cout
+        else:
+            W = layers[order[owner]]["W"]
         off = (off + 3) & ~3
         layers[(kind, depth, j)] = dict(W=W, b=b, m_pos=m_pos, m_neg=m_neg, r=r, z_in=z_in, z_out=z_out)
+        order.append((kind, depth, j))
     return C, D, n_deep, layers
 
 

@@ -106,7 +106,7 @@ def test_library_weights_equal_generator(lib, C, D, nd, flags):
 
 def test_library_weights_reject_bad_arguments(lib):
     n = ctypes.c_size_t()
-    for args in ((24, 10, 2, 0), (16, 0, 0, 0), (16, 10, 10, 0), (16, 22, 2, 0), (16, 10, 2, 4)):
+    for args in ((24, 10, 2, 0), (16, 0, 0, 0), (16, 10, 10, 0), (16, 22, 2, 0), (16, 10, 2, 8)):
         C, D, nd, fl = args
         assert lib.lpcc_make_weights(ctypes.c_uint64(1), C, D, nd, fl, None, ctypes.c_size_t(0),
                                      ctypes.byref(n)) == -1, args
