@@ -60,6 +60,14 @@ __device__ __forceinline__ int requant_l24(int acc, const LayerDev& L) {
   return min(max(p + L.z_out, -128), 127);
 }
 
+// The same for identity layers (m_pos = m_neg, checked on the host): no
+// sign-dependent multiplier.
+__device__ __forceinline__ int requant_id24(int acc, const LayerDev& L) {
+  const int a = min(max(acc, L.a_lo), L.a_hi);
+  const int p = (__mul24(a, L.m_pos) + (int)L.rnd) >> L.r;
+  return min(max(p + L.z_out, -128), 127);
+}
+
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Every device array is global memory.  Pointers that arrive inside
@@ -176,7 +184,7 @@ struct PredArg {
   PredSeg seg;
   LayerDev fc1, fc2;
   int32_t one;
-  int32_t rq24;  // every segment's logit layer has rq24 set
+  int32_t rq24;  // every segment's logit layer has rq24 set (2: and is an identity layer)
 };
 
 // Coordinate hash and 3x3x3 neighbour table of one depth j; several depths

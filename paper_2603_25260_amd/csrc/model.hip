@@ -1315,29 +1315,33 @@ hipError_t launch_emb(const GemmSeg* segs, const Tile* tiles, int ntiles, int C,
 //   f_i = 1 + floor(E_i * 65281 / S), the remainder 65536 - sum f goes to the
 //   lowest index holding M;  cdf[s] = sum_{i<s} f_i.
 // Division: for E <= 2^15 and 2^15 <= S < 2^23, floor(E * 65281 / S) is
-// q' or q'+1 with q' = (E * K) >> 22 and K = floor(65281 * 2^22 / S): the
-// two quotients differ by less than E / 2^22 < 1.  K < 2^23 and E < 2^16, so
-// every product is a full-rate 24-bit multiply; K comes from a shift-subtract
-// long division once per node.  Integer-only.
+// q' or q'+1 with q' = (E * K) >> 16 and K = floor(65281 * 2^16 / S) < 2^17:
+// E * K / 2^16 is at most E / 2^16 <= 1/2 below E * 65281 / S.  E * K < 2^32,
+// so q' is one full-rate 24-bit multiply and a shift, and the remainder
+// E * 65281 - q' S (in [0, 2S)) decides the +1.  K comes from a 32-bit
+// shift-subtract long division once per node.  Integer-only.
 // A wave handles 16 nodes; lane l owns rows 4(l/16)+i and columns 16b + l%16.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t recip_k(uint32_t S) {  // floor(65281 * 2^22 / S), 2^15 <= S < 2^23
-  uint64_t rem = 65281ull << 22;
+__device__ __forceinline__ uint32_t recip_k(uint32_t S) {  // floor(65281 * 2^16 / S), 2^15 <= S < 2^23
+  uint32_t rem = 65281u << 16;  // < 2^32
   uint32_t q = 0;
 #pragma unroll
-  for (int b = 22; b >= 0; b--) {
-    const uint64_t t = (uint64_t)S << b;
-    if (rem >= t) { rem -= t; q |= 1u << b; }
+  for (int b = 16; b >= 0; b--) {
+    // rem >= S 2^b  <=>  floor(rem / 2^b) >= S; then S 2^b <= rem fits 32 bits
+    if ((rem >> b) >= S) {
+      rem -= S << b;
+      q |= 1u << b;
+    }
   }
   return q;
 }
 
-// E < 2^16 (a 16-bit table entry), K < 2^23 (masked by the caller), S < 2^23.
-// The quotient is at most 65281, so q' fits 16 bits; the masks only tell the
-// instruction selector that 24-bit multiplies suffice.
+// E <= 2^15 (a table entry), K < 2^17 (masked by the caller), S < 2^23.
+// The quotient is at most 65281; the masks only tell the instruction
+// selector that 24-bit multiplies suffice.
 __device__ __forceinline__ uint32_t div_freq(uint32_t E, uint32_t S, uint32_t K) {  // floor(E * 65281 / S)
-  const uint32_t q = (uint32_t)(((uint64_t)E * (uint64_t)K) >> 22);
-  const uint32_t rem = __umul24(E, 65281u) - __umul24(q & 0xFFFFu, S & 0xFFFFFFu);  // in [0, 2S)
+  const uint32_t q = __umul24(E & 0xFFFFu, K & 0x1FFFFu) >> 16;
+  const uint32_t rem = __umul24(E & 0xFFFFu, 65281u) - __umul24(q, S & 0xFFFFFFu);  // in [0, 2S)
   return rem >= S ? q + 1 : q;
 }
 
@@ -1455,7 +1459,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
 #pragma unroll
     for (int i = 0; i < NI; i++) {
       const int a = acc[i] + b2[b];
-      lg[i][b] = 16 * b + r < kNSym ? (RQ24 ? requant_l24(a, L2) : requant_l(a, L2)) : -1000;
+      lg[i][b] = 16 * b + r < kNSym ? (RQ24 == 2 ? requant_id24(a, L2) : (RQ24 ? requant_l24(a, L2) : requant_l(a, L2))) : -1000;
     }
   }
 
@@ -1499,7 +1503,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   for (int i = 0; i < NI; i++) {
     const int nrow = row0 + node_of(g, i);
     const uint32_t S_ = Sr[i];
-    const uint32_t K_ = inv[i] & 0x7FFFFFu;
+    const uint32_t K_ = inv[i] & 0x1FFFFu;
     int f[16];
     int fsum = 0;
 #pragma unroll
@@ -1595,12 +1599,12 @@ hipError_t launch_predict(int C, int mode, const PredSeg* segs, const Tile* tile
   const int grid = small ? (A.seg.rows + 15) / 16 : ntiles;
 #define LPCC_P(CC, MM)                                                                                   \
   if (C == CC && mode == MM) {                                                                           \
-    if (small && A.rq24)                                                                                 \
-      hipLaunchKernelGGL((k_predict<CC, MM, 1, 1>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
+    if (small && A.rq24 == 2)                                                                            \
+      hipLaunchKernelGGL((k_predict<CC, MM, 1, 2>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
     else if (small)                                                                                      \
       hipLaunchKernelGGL((k_predict<CC, MM, 1, 0>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
-    else if (A.rq24)                                                                                     \
-      hipLaunchKernelGGL((k_predict<CC, MM, 4, 1>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
+    else if (A.rq24 == 2)                                                                                \
+      hipLaunchKernelGGL((k_predict<CC, MM, 4, 2>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
     else                                                                                                 \
       hipLaunchKernelGGL((k_predict<CC, MM, 4, 0>), dim3(grid), dim3(256), 0, s, segs, tiles, lut, A);   \
     return hipGetLastError();                                                                            \

@@ -1148,8 +1148,14 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
   if (nt == 0) return;
   PredArg one;
   memset(&one, 0, sizeof(one));
-  one.rq24 = 1;
-  for (auto& s : segs) one.rq24 &= hlayer(m, s.fc2).rq24;
+  // the logit layers' requantisation: a 24-bit multiply-add for identity
+  // layers (2), else the general form (0)
+  bool fits = true;
+  for (auto& s : segs) {
+    const LayerDev& F = hlayer(m, s.fc2);
+    fits = fits && F.rq24 && F.m_pos == F.m_neg;
+  }
+  one.rq24 = fits ? 2 : 0;
   size_t so = 0, to = 0;
   if (segs.size() == 1) {
     one.seg = segs[0];
