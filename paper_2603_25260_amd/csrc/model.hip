@@ -19,25 +19,36 @@ namespace lpcc {
 
 __device__ __forceinline__ v4i ld16(const int8_t* p) { return *(const GAS v4i*)p; }
 
-// N int8 values (N a multiple of 4, 4-byte aligned) as 32-bit words
+// N int8 values (N a multiple of 4; p aligned to 4 N bytes up to 16) as one
+// vector access of N/4 32-bit words
+template <int N>
+struct Words;
+template <>
+struct Words<4> { typedef int T __attribute__((ext_vector_type(1))); };
+template <>
+struct Words<8> { typedef int T __attribute__((ext_vector_type(2))); };
+template <>
+struct Words<16> { typedef int T __attribute__((ext_vector_type(4))); };
+
 template <int N>
 __device__ __forceinline__ void ld_bytes(const int8_t* p, int8_t (&v)[N]) {
+  const typename Words<N>::T x = *(const GAS typename Words<N>::T*)p;
 #pragma unroll
-  for (int w = 0; w < N / 4; w++) {
-    const uint32_t x = ((const GAS uint32_t*)p)[w];
+  for (int w = 0; w < N / 4; w++)
 #pragma unroll
-    for (int b = 0; b < 4; b++) v[4 * w + b] = (int8_t)(x >> (8 * b));
-  }
+    for (int b = 0; b < 4; b++) v[4 * w + b] = (int8_t)((uint32_t)x[w] >> (8 * b));
 }
 template <int N>
 __device__ __forceinline__ void st_bytes(int8_t* p, const int8_t (&v)[N]) {
+  typename Words<N>::T x;
 #pragma unroll
   for (int w = 0; w < N / 4; w++) {
-    uint32_t x = 0;
+    uint32_t y = 0;
 #pragma unroll
-    for (int b = 0; b < 4; b++) x |= ((uint32_t)(uint8_t)v[4 * w + b]) << (8 * b);
-    ((GAS uint32_t*)p)[w] = x;
+    for (int b = 0; b < 4; b++) y |= ((uint32_t)(uint8_t)v[4 * w + b]) << (8 * b);
+    x[w] = (int)y;
   }
+  *(GAS typename Words<N>::T*)p = x;
 }
 
 // Epilogue: one wave's 16 x COUT int32 tile staged in LDS, then every lane
@@ -918,6 +929,8 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
   __shared__ uint32_t wtot[8][4 * PPT];
   __shared__ uint32_t cnt[8];
   __shared__ uint32_t goff[9];
+  __shared__ uint32_t ost[4][16][C / 4 + 4];  // output stage of every wave (16 rows)
+  __shared__ int32_t ocrow[4][16];
 
   GemmSeg S;
   LayerDev L;
@@ -1040,10 +1053,12 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
     for (int s = 0; s < KS; s++)
 #pragma unroll
       for (int nb = 0; nb < NBS; nb++) acc[nb] = mfma16(wb[s][nb], x.a[s], acc[nb]);
-    if (!ev) continue;
-    const int crow = first + __popc(pc & ((1u << o) - 1u));
-    if (crow >= S.child_rows) continue;  // only for a corrupt stream
-    GAS uint32_t* dst = (GAS uint32_t*)(gp(S.out) + (int64_t)crow * S.out_stride + 4 * g);
+    // the group's 16 child rows go through the wave's LDS stage, so that
+    // every row leaves as whole 16-byte stores (lane (r, g) holds channels
+    // 16 nb + 4 g .. + 3 of column r)
+    int crow = ev ? first + __popc(pc & ((1u << o) - 1u)) : -1;
+    if (crow >= S.child_rows) crow = -1;  // only for a corrupt stream
+    if (g == 0) ocrow[wave][r] = crow;
 #pragma unroll
     for (int nb = 0; nb < NBS; nb++) {
       uint32_t packed = 0;
@@ -1052,8 +1067,23 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
         const int y = requant_l(acc[nb][i] + bb[nb][i], L);
         packed |= ((uint32_t)y & 0xFFu) << (8 * i);
       }
-      dst[4 * nb] = packed;
+      ost[wave][r][4 * nb + g] = packed;
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < 16 * NBS) {
+      const int row = lane / NBS, part = lane % NBS;
+      const int cr = ocrow[wave][row];
+      if (cr >= 0) {
+        const uint32_t* w = &ost[wave][row][4 * part];
+        *(GAS v4i*)(gp(S.out) + (int64_t)cr * S.out_stride + 16 * part) =
+            v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
