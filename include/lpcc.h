@@ -293,21 +293,28 @@ int lpcc_timing_enable(lpcc_ctx* c, const char* name);
 int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* units);
 
 /*
- * Tile shapes of the gather-GEMM and up-convolution kernels (the indexed
- * linear transforms of the sparse convolutions, Sec. 3.3, and the
- * upsampling of Eq. 6).  A wave computes
- * rb blocks of 16 rows (rb = 1, 2 or 4); larger rb re-uses every weight
- * fragment across more rows and suits large launches, rb = 1 has the
- * shortest per-wave chain and suits small ones.  rb = 0 (the default)
- * autotunes: the first launch of every (kernel, widths, log2 rows) class on
- * this context runs each candidate, timed with HIP events on the context's
- * stream, and later launches of the class use the fastest.  Every choice
- * computes identical outputs.  Returns LPCC_E_INVAL for other values.
+ * Kernel variants of the gather-GEMM, child-convolution and upsampling
+ * launches (the indexed linear transforms of the sparse convolutions,
+ * Sec. 3.3, the stride-2 steps of Eq. 4 and the upsampling of Eq. 6).  Each
+ * kind has a compacted variant, which works only on the present taps of a
+ * wave's rows or the occupied children of a block's parents (wave ballot
+ * and prefix count), and a dense one over every tap or child slot (absent
+ * ones contribute zeros); a wave computes rb blocks of 16 rows.  rb = 0 (the
+ * default) autotunes: the first launch of every (kernel, widths, log2 rows)
+ * class on this context runs each candidate, timed with HIP events on the
+ * context's stream, and later launches of the class use the fastest.  rb =
+ * 1, 2 or 4 fixes the compacted variants (that many row blocks per wave for
+ * the gather-GEMMs), 11, 12 or 14 the dense variants with rb - 10 row blocks
+ * per wave.  Every choice computes identical outputs.  Returns LPCC_E_INVAL
+ * for other values.
  *
  * lpcc_ctx_tuning reports the table: 6 ints per class (kind 0 gemm / 1 up,
- * mode, cin, cout, log2 rows, chosen rb or 0 while undecided) into out
+ * mode, cin, cout, log2 rows, chosen variant or 0 while undecided) into out
  * (host, 6 * cap ints), the number of classes into *n; LPCC_E_CAPACITY when
- * cap is too small (the first cap rows are written).
+ * cap is too small (the first cap rows are written).  Variant codes: rb (1,
+ * 2, 4) and 10 + rb for the gather-GEMMs, 101/102 (compacted, 64/128 parents
+ * per block) and 110 + rb for the child convolution, 201/202 (compacted,
+ * 128/512 parents per block) and 210 + rb for the upsampling.
  */
 int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb);
 

@@ -278,17 +278,22 @@ enum GemmMode { G_CONV = 0, G_DENSE = 1, G_DOWN = 2 };
 // rb: 16-row blocks per wave (1, 2 or 4); tiles then cover 64 * rb rows
 hipError_t launch_gemm(int mode, int cin, int cout, const GemmSeg* segs_dev, const Tile* tiles_dev,
                        int ntiles, const GemmArg& one, int rb, hipStream_t s);
+// the same over every tap (absent neighbours and child slots contribute
+// zeros): the dense variant the autotuner weighs against the compacted one
+hipError_t launch_gemm_dense(int mode, int cin, int cout, const GemmSeg* segs_dev, const Tile* tiles_dev,
+                             int ntiles, const GemmArg& one, int rb, hipStream_t s);
 hipError_t launch_up(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
                      int rb, hipStream_t s);
-// the same over the occupied children only; tiles of kUpTile parents
-constexpr int kUpTile = 512;
+// the same over the occupied children only; tiles of P = 128 or 512 parents
 hipError_t launch_up_cx(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
-                        hipStream_t s);
-// child convolution (C -> C) over the occupied children only; tiles of
-// kDownTile parents
-constexpr int kDownTile = 128;
+                        int P, hipStream_t s);
+// child convolution (C -> C) over the occupied children only; tiles of P = 64
+// or 128 parents
 hipError_t launch_down_cx(int C, const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, const GemmArg& one,
-                          hipStream_t s);
+                          int P, hipStream_t s);
+// tile of the compacted child-slot kernels: the large one once a launch has
+// this many of its blocks, else the small one (more blocks in flight)
+constexpr int kSlotTileBlocks = 512;
 hipError_t launch_emb(const GemmSeg* segs_dev, const Tile* tiles_dev, int ntiles, int C, const GemmArg& one,
                       hipStream_t s);
 // single-segment predictor launches up to this many rows take 4 rows per wave

@@ -81,7 +81,8 @@ __device__ __forceinline__ int src_row(const GemmSeg& S, int row, int tap) {
   uint32_t code = gp(S.code)[row];
   if (!((code >> tap) & 1u)) return -1;
   const int cr = gp(S.cstart)[row] + __popc(code & ((1u << tap) - 1u));
-  return cr < S.child_rows ? cr : -1;  // out of range only for a corrupt stream
+  if (cr >= S.child_rows) return -1;  // only for a corrupt stream
+  return S.ccode != nullptr ? (int)gp(S.ccode)[cr] : cr;  // the embedding table is indexed by the child's code
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD
@@ -289,7 +290,8 @@ __global__ __launch_bounds__(256) void k_gemm_rb(const GemmSeg* __restrict__ seg
     if (MODE == G_DENSE) return row;
     if (!((pcode[rb] >> tap) & 1u)) return -1;
     const int cr = pcs[rb] + __popc(pcode[rb] & ((1u << tap) - 1u));
-    return cr < S.child_rows ? cr : -1;
+    if (cr >= S.child_rows) return -1;
+    return S.ccode != nullptr ? (int)gp(S.ccode)[cr] : cr;  // the embedding table is indexed by the child's code
   };
 
   v4i acc[RB][NB];
@@ -480,7 +482,8 @@ __global__ __launch_bounds__(256) void k_gemm_cx(const GemmSeg* __restrict__ seg
     if (MODE == G_CONV) return skm[slot * WR + 16 * rb + r];
     if (!((pcode[rb] >> tap) & 1u)) return -1;
     const int cr = pcs[rb] + __popc(pcode[rb] & ((1u << tap) - 1u));
-    return cr < S.child_rows ? cr : -1;  // out of range only for a corrupt stream
+    if (cr >= S.child_rows) return -1;  // only for a corrupt stream
+    return S.ccode != nullptr ? (int)gp(S.ccode)[cr] : cr;  // the embedding table is indexed by the child's code
   };
 
   v4i acc[RB][NB];
@@ -647,6 +650,15 @@ static hipError_t launch_gemm_cx(int cin, int cout, const GemmSeg* segs, const T
   }
   LPCC_C(16, 16) LPCC_C(32, 16) LPCC_C(32, 32) LPCC_C(64, 32) LPCC_C(64, 64) LPCC_C(128, 64)
 #undef LPCC_C
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_dense(int mode, int cin, int cout, const GemmSeg* segs, const Tile* tiles, int ntiles,
+                             const GemmArg& A, int rb, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (mode == G_CONV) return launch_gemm_mode<G_CONV>(cin, cout, segs, tiles, ntiles, A, rb, s);
+  if (mode == G_DENSE) return launch_gemm_mode<G_DENSE>(cin, cout, segs, tiles, ntiles, A, rb, s);
+  if (mode == G_DOWN) return launch_gemm_mode<G_DOWN>(cin, cout, segs, tiles, ntiles, A, rb, s);
   return hipErrorInvalidValue;
 }
 
@@ -900,8 +912,8 @@ __global__ __launch_bounds__(256) void k_up_staged(const GemmSeg* __restrict__ s
   }
 }
 
-// Upsampling + pruning over the occupied children only.  A block takes
-// kUpParents consecutive parents and compacts them, per child slot o, into a
+// Upsampling + pruning over the occupied children only.  A block takes P
+// (128 or 512) consecutive parents and compacts them, per child slot o, into a
 // list of the parents that have child o (wave ballot and prefix count, then
 // the per-wave totals: the list keeps parent order).  The lists are cut into
 // groups of 16 entries; a wave computes one group with one MFMA column block
@@ -910,22 +922,21 @@ __global__ __launch_bounds__(256) void k_up_staged(const GemmSeg* __restrict__ s
 // four consecutive output channels of one child and writes them as one word.
 // Only the last group of each slot is partly empty.  Groups are dealt to the
 // waves in slot order, so a wave keeps a slot's weights across its groups.
-constexpr int kUpParents = kUpTile;
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {  // set bits of m below this lane
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-template <int C>
+template <int C, int P>
 __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
                                                const GemmArg A) {
   constexpr int KS = (C + 8 + 63) / 64;
   constexpr int NBS = C / 16;          // column blocks per child slot
   constexpr int NBT = 8 * NBS;         // column blocks of the layer
-  constexpr int PPT = kUpParents / 256;  // parents per thread
-  static_assert(C % 16 == 0 && kUpParents % 256 == 0, "shape");
-  __shared__ uint16_t list[8][kUpParents];
-  __shared__ uint8_t pcode[kUpParents];
+  constexpr int PPT = P >= 256 ? P / 256 : 1;  // parents per thread
+  static_assert(C % 16 == 0 && (P % 256 == 0 || P == 128), "shape");
+  __shared__ uint16_t list[8][P];
+  __shared__ uint8_t pcode[P];
   __shared__ uint32_t wtot[8][4 * PPT];
   __shared__ uint32_t cnt[8];
   __shared__ uint32_t goff[9];
@@ -934,7 +945,7 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
 
   GemmSeg S;
   LayerDev L;
-  const int p0 = pick_seg(segs, tiles, A, S, L, kUpParents);
+  const int p0 = pick_seg(segs, tiles, A, S, L, P);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
 
@@ -945,8 +956,8 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
   for (int q = 0; q < PPT; q++) {
     const int t = 256 * q + (int)threadIdx.x;
     const int p = p0 + t;
-    code[q] = p < S.rows ? (uint32_t)gp(S.code)[p] : 0u;
-    pcode[t] = (uint8_t)code[q];
+    code[q] = t < P && p < S.rows ? (uint32_t)gp(S.code)[p] : 0u;
+    if (t < P) pcode[t] = (uint8_t)code[q];
 #pragma unroll
     for (int o = 0; o < 8; o++) {
       const uint64_t m = __ballot((code[q] >> o) & 1u);
@@ -1089,7 +1100,7 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
 
 // Child convolution (the stride-2 step of the re-densification, Eq. 4) over
 // the occupied children only: out[q] = rq(b + sum over children c of q of
-// in[c] W[slot(c)]).  A block takes kDownTile consecutive parents, compacts
+// in[c] W[slot(c)]).  A block takes P (64 or 128) consecutive parents, compacts
 // them per child slot as the upsampling does, and multiplies 16-entry groups
 // of one slot (the slot's weights as the row operand, the 16 children's
 // input rows as the columns).  Each lane then holds four consecutive output
@@ -1099,10 +1110,9 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
 // accumulators are requantised once all groups are done.  With `ccode` set,
 // child c reads row ccode[c] of `in`: the occupancy embedding of depth j
 // depends on the code alone, so the first step reads a 256-row table.
-template <int C>
+template <int C, int P>
 __global__ __launch_bounds__(256) void k_down_cx(const GemmSeg* __restrict__ segs, const Tile* __restrict__ tiles,
                                                  const GemmArg A) {
-  constexpr int P = kDownTile;
   constexpr int NB = C / 16;
   constexpr int KS = (C + 63) / 64;
   static_assert(C % 16 == 0 && P <= 256 && P % 64 == 0, "shape");
@@ -1253,24 +1263,30 @@ __global__ __launch_bounds__(256) void k_down_cx(const GemmSeg* __restrict__ seg
   }
 }
 
-hipError_t launch_down_cx(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A,
+hipError_t launch_down_cx(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, int P,
                           hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (C == 16) hipLaunchKernelGGL((k_down_cx<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else if (C == 32) hipLaunchKernelGGL((k_down_cx<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else if (C == 64) hipLaunchKernelGGL((k_down_cx<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+#define LPCC_D(CC, PP)                                                                                 \
+  if (C == CC && P == PP) {                                                                            \
+    hipLaunchKernelGGL((k_down_cx<CC, PP>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);            \
+    return hipGetLastError();                                                                          \
+  }
+  LPCC_D(16, 64) LPCC_D(16, 128) LPCC_D(32, 64) LPCC_D(32, 128) LPCC_D(64, 64) LPCC_D(64, 128)
+#undef LPCC_D
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_up_cx(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A,
+hipError_t launch_up_cx(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, int P,
                         hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (C == 16) hipLaunchKernelGGL((k_up_cx<16>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else if (C == 32) hipLaunchKernelGGL((k_up_cx<32>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else if (C == 64) hipLaunchKernelGGL((k_up_cx<64>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+#define LPCC_U(CC, PP)                                                                                 \
+  if (C == CC && P == PP) {                                                                            \
+    hipLaunchKernelGGL((k_up_cx<CC, PP>), dim3(ntiles), dim3(256), 0, s, segs, tiles, A);              \
+    return hipGetLastError();                                                                          \
+  }
+  LPCC_U(16, 128) LPCC_U(16, 512) LPCC_U(32, 128) LPCC_U(32, 512) LPCC_U(64, 128) LPCC_U(64, 512)
+#undef LPCC_U
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_up(int C, const GemmSeg* segs, const Tile* tiles, int ntiles, const GemmArg& A, int rb,

@@ -172,10 +172,13 @@ __global__ __launch_bounds__(256) void k_sort_count(const uint64_t* __restrict__
 // (item, wave, digit) are turned into running offsets by one thread per
 // digit.  With offs_ready the tile offsets come from k_sort_scan, else the
 // pass sums the counts of the tiles before it and the totals of the smaller
-// digits itself.
+// digits itself; such small sorts also add the next pass's digit counts per
+// destination tile here (few tiles: few contended counters), larger ones
+// count them in a pass of their own.
 __global__ __launch_bounds__(256) void k_sort_scatter(const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
                                                       int64_t n, int shift, int bits, const uint32_t* __restrict__ hist,
                                                       int offs_ready, const uint32_t* __restrict__ totals,
+                                                      uint32_t* __restrict__ hist_next, int shift_n, int bits_n,
                                                       uint32_t* __restrict__ err) {
   __shared__ uint32_t cnt[kSortItems][4][256];
   __shared__ uint32_t wsum[4];
@@ -235,6 +238,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const uint64_t* __restrict
       continue;
     }
     gp(kout)[dest] = key[k];
+    if (hist_next != nullptr)
+      atomicAdd(hist_next + (dest / kSortTile) * 256 + digit_of(key[k], shift_n, bits_n), 1u);
   }
 }
 
@@ -244,13 +249,17 @@ hipError_t launch_sort_pass(const uint64_t* kin, uint64_t* kout, int64_t n, cons
   const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
   uint32_t* hp = hist + (int64_t)p * ntiles * 256;
   const bool scan = ntiles > kSortFusedTiles;
-  // pass 0's per-tile counts come with the keys; later passes count the
-  // order the previous pass left
-  if (p > 0)
+  const bool last = p + 1 >= sp.n;
+  // pass 0's per-tile counts come with the keys; a large sort counts every
+  // later pass over the order the previous pass left, a small one had them
+  // added by the previous pass
+  if (p > 0 && scan)
     hipLaunchKernelGGL(k_sort_count, dim3((unsigned)ntiles), dim3(256), 0, s, kin, n, sp.shift[p], sp.bits[p], hp);
   if (scan) hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hp, (int)ntiles, totals + p * 256);
+  uint32_t* next = (!scan && !last) ? hp + ntiles * 256 : nullptr;
   hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)ntiles), dim3(256), 0, s, kin, kout, n, sp.shift[p], sp.bits[p],
-                     (const uint32_t*)hp, scan ? 1 : 0, totals + p * 256, err);
+                     (const uint32_t*)hp, scan ? 1 : 0, totals + p * 256, next, last ? 0 : sp.shift[p + 1],
+                     last ? 0 : sp.bits[p + 1], err);
   return hipGetLastError();
 }
 

@@ -336,12 +336,16 @@ struct lpcc_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   size_t ev_used = 0;
   int64_t time_units = 0;
-  // tile autotuner: rows per wave (16 x rb) of the GEMM-type launches, per
-  // (kernel, widths, log2 rows); tiling = 0 tunes, 1/2/4 fixes rb
+  // kernel autotuner of the GEMM-type launches, per (kernel, widths, log2
+  // rows): the variant (compacted over present taps / occupied children, or
+  // dense) and its tile; tiling = 0 tunes, 1/2/4 fixes the compacted
+  // variants' row blocks, 11/12/14 the dense variants'
   struct TuneRec {
     int best = 0;
-    double ms[3] = {0, 0, 0};
-    int n[3] = {0, 0, 0};
+    int ncand = 0;
+    int cand[8] = {};
+    double ms[8] = {};
+    int n[8] = {};
   };
   std::map<std::array<int, 5>, TuneRec> tune;
   struct Pending {
@@ -603,8 +607,50 @@ int64_t count_tiles(const std::vector<int64_t>& rows, int rows_per_tile = 64) {
   return n;
 }
 
-// ---- tile autotuner ----
-constexpr int kTileRB[3] = {1, 2, 4};
+// ---- kernel autotuner ----
+// Variant codes: for the 3x3x3 and other GEMM launches rb (1, 2, 4: the
+// compacted gather-GEMM, or the dense one for layers without taps) or
+// 10 + rb (the dense gather-GEMM over all taps); for the child convolution
+// 100 + 1/2 (compacted, tiles of 64 / 128 parents) or 110 + rb (dense); for
+// the upsampling 200 + 1/2 (compacted, tiles of 128 / 512 parents) or
+// 210 + rb (all child slots of every parent).
+struct Variant {
+  int code, tile_rows;
+};
+std::vector<Variant> variants(bool up, int mode) {
+  if (up) return {{201, 128}, {202, 512}, {211, 64}, {212, 128}, {214, 256}};
+  if (mode == G_DOWN) return {{101, 64}, {102, 128}, {111, 64}, {112, 128}, {114, 256}};
+  if (mode == G_CONV) return {{1, 64}, {2, 128}, {4, 256}, {11, 64}, {12, 128}, {14, 256}};
+  return {{1, 64}, {2, 128}, {4, 256}};
+}
+// the variant a fixed tiling selects
+Variant fixed_variant(bool up, int mode, int tiling, int64_t rows) {
+  const bool dense = tiling > 10;
+  const int rb = tiling % 10;
+  if (up) {
+    if (dense) return {210 + rb, 64 * rb};
+    return count_tiles({rows}, 512) >= kSlotTileBlocks ? Variant{202, 512} : Variant{201, 128};
+  }
+  if (mode == G_DOWN) {
+    if (dense) return {110 + rb, 64 * rb};
+    return count_tiles({rows}, 128) >= kSlotTileBlocks ? Variant{102, 128} : Variant{101, 64};
+  }
+  if (mode == G_CONV) return {tiling, 64 * rb};
+  return {rb, 64 * rb};
+}
+hipError_t launch_variant(int code, bool up, int mode, int cin, int cout, const GemmSeg* S, const Tile* T, int nt,
+                          const GemmArg& one, hipStream_t st) {
+  if (up) {
+    if (code < 210) return launch_up_cx(cout, S, T, nt, one, code == 201 ? 128 : 512, st);
+    return launch_up(cout, S, T, nt, one, code - 210, st);
+  }
+  if (mode == G_DOWN) {
+    if (code < 110) return launch_down_cx(cout, S, T, nt, one, code == 101 ? 64 : 128, st);
+    return launch_gemm_dense(mode, cin, cout, S, T, nt, one, code - 110, st);
+  }
+  if (code > 10) return launch_gemm_dense(mode, cin, cout, S, T, nt, one, code - 10, st);
+  return launch_gemm(mode, cin, cout, S, T, nt, one, code, st);
+}
 
 hipError_t tune_event(lpcc_ctx* c, hipEvent_t* e) {
   if (!c->ev_free.empty()) {
@@ -640,8 +686,8 @@ void resolve_tuning(lpcc_ctx* c) {
     if (r.best) continue;
     int bi = -1;
     double bv = 0;
-    bool all = true;
-    for (int k = 0; k < 3; k++) {
+    bool all = r.ncand > 0;
+    for (int k = 0; k < r.ncand; k++) {
       if (r.n[k] == 0) {
         all = false;
         break;
@@ -649,7 +695,7 @@ void resolve_tuning(lpcc_ctx* c) {
       const double v = r.ms[k] / r.n[k];
       if (bi < 0 || v < bv) bi = k, bv = v;
     }
-    if (all) r.best = kTileRB[bi];
+    if (all) r.best = r.cand[bi];
   }
 }
 
@@ -833,43 +879,38 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
     });
     return;
   }
-  if (f == "down") {  // compacted by child slot inside tiles of kDownTile parents (no tile tuning)
-    const size_t to = segs.size() == 1 ? 0 : b.add(make_tiles(rows, kDownTile));
-    const int nt = (int)count_tiles(rows, kDownTile);
-    b.launch(f, units, [=](const uint8_t* base) {
-      return launch_down_cx(cout, (const GemmSeg*)(base + so), (const Tile*)(base + to), nt, one, st);
-    });
-    return;
-  }
-  if (f == "up") {  // compacted by child slot inside tiles of kUpTile parents (no tile tuning)
-    const size_t to = segs.size() == 1 ? 0 : b.add(make_tiles(rows, kUpTile));
-    const int nt = (int)count_tiles(rows, kUpTile);
-    b.launch(f, units, [=](const uint8_t* base) {
-      return launch_up_cx(cout, (const GemmSeg*)(base + so), (const Tile*)(base + to), nt, one, st);
-    });
-    return;
-  }
-  // rows per wave: the tuned choice of this size class, a fixed one, or all
+  // the variant: the tuned choice of this size class, a fixed one, or all
   // candidates timed (identical outputs: every candidate writes the same rows)
   lpcc_ctx* c = b.ctx;
   const bool up = f == "up";
   lpcc_ctx::TuneRec* rec = nullptr;
-  std::vector<int> cands;
+  const std::vector<Variant> all = variants(up, mode);
+  std::vector<Variant> cands;
+  auto of_code = [&](int code) {
+    for (const Variant& v : all)
+      if (v.code == code) return v;
+    return all[0];
+  };
   if (c->tiling) {
-    cands = {c->tiling};
-  } else if (c->fixed) {  // no events: a decided class, else two row blocks per wave
+    cands = {fixed_variant(up, mode, c->tiling, units)};
+  } else if (c->fixed) {  // no events: a decided class, else the compacted variant
     auto it = c->tune.find({up ? 1 : 0, mode, cin, cout, log2_rows(units)});
-    cands = {it != c->tune.end() && it->second.best ? it->second.best : 2};
+    cands = {it != c->tune.end() && it->second.best ? of_code(it->second.best) : fixed_variant(up, mode, 2, units)};
   } else {
     rec = &c->tune[{up ? 1 : 0, mode, cin, cout, log2_rows(units)}];
-    if (rec->best) cands = {rec->best};
-    else cands = {kTileRB[0], kTileRB[1], kTileRB[2]};
+    if (rec->best) {
+      cands = {of_code(rec->best)};
+    } else {
+      cands = all;
+      rec->ncand = (int)all.size();
+      for (size_t k = 0; k < all.size(); k++) rec->cand[k] = all[k].code;
+    }
   }
-  std::vector<std::pair<int, size_t>> plan;  // (rb, tile offset)
+  std::vector<std::pair<int, size_t>> plan;  // (variant code, tile offset)
   std::vector<int> ntiles;
-  for (int rb : cands) {
-    plan.push_back({rb, segs.size() == 1 ? 0 : b.add(make_tiles(rows, 64 * rb))});
-    ntiles.push_back((int)count_tiles(rows, 64 * rb));
+  for (const Variant& v : cands) {
+    plan.push_back({v.code, segs.size() == 1 ? 0 : b.add(make_tiles(rows, v.tile_rows))});
+    ntiles.push_back((int)count_tiles(rows, v.tile_rows));
   }
   const bool timed = rec != nullptr && cands.size() > 1;
   if (timed) b.has_events = true;
@@ -877,10 +918,7 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
     const GemmSeg* S = (const GemmSeg*)(base + so);
     for (size_t k = 0; k < plan.size(); k++) {
       const Tile* T = (const Tile*)(base + plan[k].second);
-      auto go = [&]() {
-        return up ? launch_up(cout, S, T, ntiles[k], one, plan[k].first, st)
-                  : launch_gemm(mode, cin, cout, S, T, ntiles[k], one, plan[k].first, st);
-      };
+      auto go = [&]() { return launch_variant(plan[k].first, up, mode, cin, cout, S, T, ntiles[k], one, st); };
       if (!timed) {
         hipError_t e = go();
         if (e != hipSuccess) return e;
@@ -895,7 +933,7 @@ void plan_gemm(Batch& b, const lpcc_model* m, const char* fam, int mode, int cin
       if (e == hipSuccess) e = hipEventRecord(ez, st);
       if (e != hipSuccess) return e;
       int ci = 0;
-      while (kTileRB[ci] != plan[k].first) ci++;
+      while (rec->cand[ci] != plan[k].first) ci++;
       c->pending.push_back({rec, ci, ea, ez});
     }
     return hipSuccess;
@@ -2785,7 +2823,7 @@ int lpcc_ctx_graph_stats(lpcc_ctx* c, int64_t* instantiated, int64_t* updated) {
 }
 
 int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb) {
-  if (!c || !(rb == 0 || rb == 1 || rb == 2 || rb == 4)) return LPCC_E_INVAL;
+  if (!c || !(rb == 0 || rb == 1 || rb == 2 || rb == 4 || rb == 11 || rb == 12 || rb == 14)) return LPCC_E_INVAL;
   c->tiling = rb;
   return LPCC_OK;
 }

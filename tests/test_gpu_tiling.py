@@ -1,6 +1,8 @@
-"""Tile shapes of the gather-GEMM and up-convolution kernels: every fixed
-choice of 16-row blocks per wave (1, 2, 4) and the autotuned one give the
-oracle's CDF rows and bitstreams byte for byte."""
+"""Kernel variants of the gather-GEMM, child-convolution and upsampling
+launches: the compacted variants (present taps / occupied children only)
+with every fixed choice of 16-row blocks per wave (1, 2, 4), the dense
+variants over every tap and child slot (11, 12, 14), and the autotuned
+choice give the oracle's CDF rows and bitstreams byte for byte."""
 import numpy as np
 import pytest
 
@@ -36,7 +38,7 @@ def test_fixed_tilings_match_oracle(L, C, D, n_deep, npts, zp):
     p_deep, p_sh = O.level_probs(blob, xyz, d_deep), O.level_probs(blob, xyz, d_shallow)
     m = L.Model(blob, 0)
     dx = torch.from_numpy(xyz).cuda()
-    for rb in (1, 2, 4):
+    for rb in (1, 2, 4, 11, 12, 14):
         ctx = L.Context(0)
         ctx.set_tiling(rb)
         print("C", C, "zp", zp, "rb", rb, flush=True)
@@ -63,7 +65,8 @@ def test_autotuned_tiling_decides_and_matches(L):
         assert len(dec) == len(np.unique(xyz, axis=0))
     table = ctx.tuning()
     assert table, "no tuned classes"
-    assert all(t["rb"] in (1, 2, 4) for t in table), table
+    valid = {1, 2, 4, 11, 12, 14, 101, 102, 111, 112, 114, 201, 202, 211, 212, 214}
+    assert all(t["rb"] in valid for t in table), table
 
 
 def test_bad_tiling_rejected(L):
