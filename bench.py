@@ -187,7 +187,38 @@ FAMILY_BOUND = {"conv": "hbm", "down": "hbm", "skip": "hbm", "emb": "hbm", "up":
                 "rc_encode": "hbm", "rc_decode": "hbm"}
 
 
-def roofline_of(fam, work, launches, ms):
+# HBM bytes per headline step and family, (read, write), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE over the steps after the warm-up step, scaled by
+# what the same counters read for a 256 MiB device copy (fetch x2, write x1).
+# They hold for the library sources whose digest is TRAFFIC_SOURCES; any other
+# source tree reports traffic null.
+TRAFFIC_SOURCES = "4ac1d3bcce96c877"
+FAMILY_TRAFFIC = {
+    "conv": (5803468254, 2248017152),
+    "down": (1584537167, 2081497216),
+    "skip": (1708499899, 853240960),
+    "emb": (3487286, 170779264),
+    "up": (4577782316, 4400884372),
+    "predict": (1692934449, 6584371178),
+    "rc_encode": (65128064, 16356444),
+    "rc_decode": (8107890476, 25174298),
+    "hash": (14530627786, 2447233452),
+    "expand": (138530343, 566879436),
+    "pack": (32347860, 15933280),
+}
+
+
+def library_sources_digest():
+    """sha256[:16] of the library's sources, concatenated in name order."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2603_25260_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def roofline_of(fam, work, launches, ms, traffic_ok=False):
     bound = FAMILY_BOUND[fam]
     s = ms / 1e3
     if bound == "alu":
@@ -199,6 +230,13 @@ def roofline_of(fam, work, launches, ms):
            "avg_launch_ms": round(ms / max(launches, 1), 5), "total_ms": round(ms, 3),
            "algorithmic_bytes": work["bytes"], "algorithmic_int8_macs": work["macs"],
            "algorithmic_int_ops": work["ops"]}
+    if traffic_ok and fam in FAMILY_TRAFFIC and launches:
+        rd, wr = FAMILY_TRAFFIC[fam]
+        out["traffic"] = int((rd + wr) / launches)
+        out["traffic_read"] = int(rd / launches)
+        out["traffic_write"] = int(wr / launches)
+        out["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        out["algorithmic_bytes_per_launch"] = int(work["bytes"] / launches)
     if work["macs"]:
         out["int8_mfma_frac"] = round(2 * work["macs"] / s / 1e12 / MFMA_I8_PEAK_TOPS, 5)
     return out
@@ -332,7 +370,10 @@ def main():
     ctx.timing_enable("")
     res["kernel_ms_per_step"] = {f: round(v[1], 3) for f, v in fam_t.items()}
     res["launches_per_step"] = {f: v[0] for f, v in fam_t.items()}
-    fams = {f: roofline_of(f, work[f], *fam_t[f]) for f in work if fam_t[f][0] > 0}
+    src = library_sources_digest()
+    res["library_sources"] = src
+    fams = {f: roofline_of(f, work[f], *fam_t[f], traffic_ok=(src == TRAFFIC_SOURCES))
+            for f in work if fam_t[f][0] > 0}
     dom = max(fams, key=lambda f: fams[f]["total_ms"])
     res["roofline"] = fams[dom]
     res["roofline_families"] = fams

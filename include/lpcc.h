@@ -353,6 +353,24 @@ int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n);
 int lpcc_ctx_set_base_depth(lpcc_ctx* c, int base);
 
 /*
+ * How the 3x3x3 neighbour tables of the convolved depths are built (Sec. 3.3
+ * runs the sparse convolutions over such tables, built from a coordinate
+ * hash).  Both modes give the same tables, entry for entry, hence the same
+ * streams and decodes.
+ *   mode 0 (default): a coordinate hash (open addressing, linear probing,
+ *     2^k >= 2N slots of {u64 key, i32 row}) only at the first convolved
+ *     depth; every later depth derives its table from its parent depth's
+ *     table, occupancy codes and first-child rows (the neighbour at offset
+ *     delta of the child in slot o of parent p is child slot (o + delta)
+ *     mod 2 of the parent-level cell p + floor((o + delta) / 2), per axis).
+ *   mode 1: a coordinate hash and 27 probes per node at every convolved
+ *     depth.
+ * Applies to the calls made on this context after it returns.  LPCC_E_INVAL
+ * for another mode or a null context.
+ */
+int lpcc_ctx_set_kmap_mode(lpcc_ctx* c, int mode);
+
+/*
  * The integer exponent table of the softmax (Eq. 15; the table covers the
  * non-positive domain, Sec. 3.3 "Integer softmax") as the library builds
  * it: out[i] = round(2^15 e^{-i/16}), i = 0..255, computed on the host with

@@ -68,6 +68,14 @@ __device__ __forceinline__ int requant_id24(int acc, const LayerDev& L) {
   return min(max(p + L.z_out, -128), 127);
 }
 
+// The same for identity layers whose zero point is folded into the rounding
+// term, rndz = rnd + z_out 2^r (a m + rndz inside int32 on [a_lo, a_hi],
+// checked on the host): floor((x + z 2^r) / 2^r) = floor(x / 2^r) + z.
+__device__ __forceinline__ int requant_idz24(int acc, const LayerDev& L, int rndz) {
+  const int a = min(max(acc, L.a_lo), L.a_hi);
+  return min(max((__mul24(a, L.m_pos) + rndz) >> L.r, -128), 127);
+}
+
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // Every device array is global memory.  Pointers that arrive inside
@@ -184,7 +192,8 @@ struct PredArg {
   PredSeg seg;
   LayerDev fc1, fc2;
   int32_t one;
-  int32_t rq24;  // every segment's logit layer has rq24 set (2: and is an identity layer)
+  int32_t rq24;  // 2: every segment's logit layer is an identity layer with rq24 set whose
+                 // zero point folds into the rounding term (requant_idz24); else 0
 };
 
 // Coordinate hash and 3x3x3 neighbour table of one depth j; several depths
@@ -272,6 +281,11 @@ hipError_t launch_hash_multi(const HashJob* jobs_dev, int njobs, int insert_bloc
                              hipStream_t s);
 hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* table, uint64_t mask,
                        int32_t* kmap, int64_t kstride, hipStream_t s);
+// Neighbour table of a depth (n rows, stride n) from the parents' table
+// (np rows, stride np), their codes and first-child rows (with the sentinel
+// pcstart[np]); no hash table
+hipError_t launch_kmap_tree(const int32_t* pkmap, int64_t np, const uint8_t* pcode, const int32_t* pcstart,
+                            int32_t* kmap, int64_t n, hipStream_t s);
 
 // GEMM families; `mode` selects the row source
 enum GemmMode { G_CONV = 0, G_DENSE = 1, G_DOWN = 2 };

@@ -1382,13 +1382,16 @@ __device__ __forceinline__ uint32_t recip_k(uint32_t S) {  // floor(65281 * 2^16
   return q;
 }
 
-// E <= 2^15 (a table entry), K < 2^17 (masked by the caller), S < 2^23.
-// The quotient is at most 65281; the masks only tell the instruction
-// selector that 24-bit multiplies suffice.
-__device__ __forceinline__ uint32_t div_freq(uint32_t E, uint32_t S, uint32_t K) {  // floor(E * 65281 / S)
+// f = 1 + floor(E * 65281 / S) for E <= 2^15 (a table entry), K < 2^17
+// (masked by the caller), S < 2^23.  With q' = (E K) >> 16 the remainder
+// E 65281 - q' S lies in [0, 2S), so the floor is q' + 1 exactly when
+// (q' + 1) S <= E 65281; both sides stay below 2^32 (q' S <= E 65281 <
+// 2^31, plus S < 2^23), and (q' + 1) S is one 24-bit multiply-add.  The
+// masks only tell the instruction selector that 24-bit operands suffice.
+__device__ __forceinline__ uint32_t freq_of(uint32_t E, uint32_t S, uint32_t K) {
   const uint32_t q = __umul24(E & 0xFFFFu, K & 0x1FFFFu) >> 16;
-  const uint32_t rem = __umul24(E & 0xFFFFu, 65281u) - __umul24(q, S & 0xFFFFFFu);  // in [0, 2S)
-  return rem >= S ? q + 1 : q;
+  const uint32_t up = __umul24(q, S & 0xFFFFFFu) + S;
+  return q + 1u + (up <= __umul24(E & 0xFFFFu, 65281u) ? 1u : 0u);
 }
 
 // reductions over the 16 lanes of a DPP row (rotations by 8, 4, 2, 1 leave the
@@ -1434,7 +1437,8 @@ enum { P_ENCODE = 0, P_CDF16 = 1, P_CDF32 = 2 };
 // small launches (4 nodes per wave at MFMA rows 0, 4, 8, 12: a quarter of the
 // per-lane softmax work, so short launches finish sooner).
 template <int C, int MODE, int NI, int RQ24>
-__global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ segs, const Tile* __restrict__ tiles,
+// at most 128 VGPRs: four waves per SIMD
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_predict(const PredSeg* __restrict__ segs, const Tile* __restrict__ tiles,
                                                  const int32_t* __restrict__ lut_g, const PredArg A) {
   static_assert(NI == 4 || NI == 1, "NI");
   // node (within the wave) of output group g, row i, and the MFMA row of a node
@@ -1497,7 +1501,11 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
   __syncthreads();  // hs of this wave, and the exponent table written by all waves
   v4i h = *(const v4i*)&hs[wave][r][16 * g];
 
-  // fc2: 16 column blocks of 16 logits
+  // fc2: 16 column blocks of 16 logits.  RQ24 = 2: an identity layer whose
+  // a m + rnd + z_out 2^r stays inside int32 on [a_lo, a_hi] (checked on the
+  // host), so the zero point rides in the rounding term: floor((x + z 2^r) /
+  // 2^r) = floor(x / 2^r) + z
+  const int rndz = RQ24 == 2 ? (int)L2.rnd + (int)((uint32_t)L2.z_out << L2.r) : 0;
   int lg[NI][16];
 #pragma unroll
   for (int b = 0; b < 16; b++) {
@@ -1505,7 +1513,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
 #pragma unroll
     for (int i = 0; i < NI; i++) {
       const int a = acc[i] + b2[b];
-      lg[i][b] = 16 * b + r < kNSym ? (RQ24 == 2 ? requant_id24(a, L2) : (RQ24 ? requant_l24(a, L2) : requant_l(a, L2))) : -1000;
+      lg[i][b] = 16 * b + r < kNSym ? (RQ24 == 2 ? requant_idz24(a, L2, rndz) : requant_l(a, L2)) : -1000;
     }
   }
 
@@ -1523,9 +1531,12 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
     const int M = key >> 8;
     arg[i] = 255 - (key & 255);
     int sum = 0;
+    // entry M - l of the table at byte 2M - 2l from its start (one 24-bit
+    // multiply-add per entry)
+    const uint8_t* lb = (const uint8_t*)lut + 2 * M;
 #pragma unroll
     for (int b = 0; b < 16; b++) {
-      const int e = (16 * b + r < kNSym) ? lut[M - lg[i][b]] : 0;
+      const int e = (16 * b + r < kNSym) ? *(const uint16_t*)(lb + __mul24(lg[i][b], -2)) : 0;
       lg[i][b] = e;
       sum += e;
     }
@@ -1552,28 +1563,34 @@ __global__ __launch_bounds__(256) void k_predict(const PredSeg* __restrict__ seg
     const uint32_t K_ = inv[i] & 0x1FFFFu;
     int f[16];
     int fsum = 0;
-#pragma unroll
-    for (int b = 0; b < 16; b++) {
-      f[b] = (16 * b + r < kNSym) ? 1 + (int)div_freq((uint32_t)lg[i][b], S_, K_) : 0;
-      fsum += f[b];
-    }
-    // the remainder R goes to entry arg, added once per node below
-    const int R = 65536 - red16_sum(fsum);
-    rem[i] = R;
-
     if (MODE == P_ENCODE) {
+      // start = sum of f over the columns below the symbol: this lane's
+      // columns 16b + r < sym are a prefix of b, so the lane's share is its
+      // running sum at the last such b; the symbol's own f sits in the one
+      // lane and block with 16b + r = sym
       const int sym = nrow < S.rows ? (int)gp(S.code)[nrow] - 1 : 0;
+      const int lim = sym - r;
       int st_ = 0, fr = 0;
 #pragma unroll
       for (int b = 0; b < 16; b++) {
-        const int col = 16 * b + r;
-        st_ += col < sym ? f[b] : 0;
-        fr += col == sym ? f[b] : 0;
+        const int fb = (16 * b + r < kNSym) ? (int)freq_of((uint32_t)lg[i][b], S_, K_) : 0;
+        fsum += fb;
+        st_ = 16 * b < lim ? fsum : st_;
+        fr = 16 * b == lim ? fb : fr;
       }
+      // the remainder R goes to entry arg
+      const int R = 65536 - red16_sum(fsum);
       st_ = red16_sum(st_) + (arg[i] < sym ? R : 0);
       fr = red16_sum(fr) + (arg[i] == sym ? R : 0);
       if (r == 0 && nrow < S.rows) gp(S.sf)[nrow] = (uint32_t)st_ | ((uint32_t)fr << 16);
     } else {
+#pragma unroll
+      for (int b = 0; b < 16; b++) {
+        f[b] = (16 * b + r < kNSym) ? (int)freq_of((uint32_t)lg[i][b], S_, K_) : 0;
+        fsum += f[b];
+      }
+      // the remainder R goes to entry arg, added once per node below
+      rem[i] = 65536 - red16_sum(fsum);
       // frequencies of the node into LDS for the row-wise prefix below
 #pragma unroll
       for (int b = 0; b < 16; b++) fs[wave][node_of(g, i)][16 * b + r] = (uint16_t)f[b];

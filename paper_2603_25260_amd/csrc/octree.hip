@@ -2,6 +2,7 @@
 // expansion on gfx950 (Sec. S3.2 of the paper; neighbourhoods for the sparse
 // convolutions of Sec. 3.3).  Integer-only; wave64 ballots and prefix counts.
 #include <cstring>
+#include <utility>
 
 #include "lpcc_internal.h"
 
@@ -603,6 +604,133 @@ hipError_t launch_kmap(const uint64_t* keys, int64_t n, int j, const uint64_t* t
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_kmap, dim3((unsigned)((n + 7) / 8)), dim3(256), 0, s, keys, n, j, table, mask, kmap,
                      kstride);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour table of depth j from the table of depth j-1, without a hash.
+// The neighbour of child c (slot o of parent p) at offset delta lies, per
+// axis, in the depth-(j-1) cell p + floor((o + delta) / 2), in that cell's
+// child slot (o + delta) mod 2.  The cell is p's own neighbour at that offset
+// (the table of depth j-1), and the child exists when that slot's bit is set
+// in the cell's occupancy code; its row is the cell's first-child row plus
+// the number of set bits below the slot, since children are stored in
+// ascending slot order (Sec. S3.2).  Cells outside the cube are absent at
+// depth j-1, so their children are absent too: the table equals the one the
+// hash lookups give, entry for entry.
+//
+// A block takes kTreeParents consecutive parents; their children are the
+// consecutive rows [cstart[p0], cstart[p_end]).  One lane per child reads the
+// 2x2x2 cells its 27 neighbours fall in: cell a = (ax, ay, az) in {0,1}^3
+// sits at parent offset (o - 1 + a) per axis, tap 9(ox+ax) + 3(oy+ay) +
+// (oz+az) of the parent.  The stores are coalesced: lanes hold consecutive
+// rows of one tap.
+// ---------------------------------------------------------------------------
+constexpr int kTreeParents = 256;
+
+// Cell index along one axis for child-tap component T (0, 1, 2 = delta -1,
+// 0, +1) of a child at slot bit o: delta -1 stays in cell 0, +1 in cell 1,
+// and 0 in cell 1 - o; the slot inside the cell is o for T = 1, else 1 - o.
+template <int T>
+__device__ __forceinline__ int tree_cell(int o) { return T == 0 ? 0 : (T == 2 ? 1 : 1 - o); }
+template <int T>
+__device__ __forceinline__ int tree_slot(int o) { return T == 1 ? o : 1 - o; }
+
+template <int TX, int TY, int TZ>
+__device__ __forceinline__ int32_t tree_row(const uint32_t (&cc)[8], const int32_t (&cs)[8], int ox, int oy,
+                                            int oz) {
+  const int a = tree_cell<TX>(ox) * 4 + tree_cell<TY>(oy) * 2 + tree_cell<TZ>(oz);
+  // select the cell by explicit compares (an index into a register array
+  // would go through scratch); cells this tap cannot reach fold away
+  uint32_t code = cc[(TX == 2 ? 4 : 0) + (TY == 2 ? 2 : 0) + (TZ == 2 ? 1 : 0)];
+  int32_t first = cs[(TX == 2 ? 4 : 0) + (TY == 2 ? 2 : 0) + (TZ == 2 ? 1 : 0)];
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    const bool reach = (TX == 1 || ((k >> 2) & 1) == (TX == 2)) && (TY == 1 || ((k >> 1) & 1) == (TY == 2)) &&
+                       (TZ == 1 || (k & 1) == (TZ == 2));
+    if (reach) {
+      code = a == k ? cc[k] : code;
+      first = a == k ? cs[k] : first;
+    }
+  }
+  const int s = tree_slot<TX>(ox) * 4 + tree_slot<TY>(oy) * 2 + tree_slot<TZ>(oz);
+  return ((code >> s) & 1u) ? first + __popc(code & ((1u << s) - 1u)) : -1;
+}
+
+// A row at or past the depth's node count (kstride) only arises when the
+// decoded codes claim more children than the stream's header (a corrupt
+// stream or the wrong model): it is stored as absent, so that no gather
+// reads past the depth's feature rows (the hash lookups can only return
+// inserted rows).
+template <int T>
+__device__ __forceinline__ void tree_tap(const uint32_t (&cc)[8], const int32_t (&cs)[8], int ox, int oy, int oz,
+                                         GAS int32_t* __restrict__ out, int64_t kstride, uint32_t& m) {
+  int32_t r = tree_row<T / 9, (T / 3) % 3, T % 3>(cc, cs, ox, oy, oz);
+  r = (r >= 0 && (int64_t)r < kstride) ? r : -1;
+  out[(int64_t)T * kstride] = r;
+  m |= (r >= 0 ? 1u : 0u) << T;
+}
+
+template <int... T>
+__device__ __forceinline__ void tree_taps(std::integer_sequence<int, T...>, const uint32_t (&cc)[8],
+                                          const int32_t (&cs)[8], int ox, int oy, int oz,
+                                          GAS int32_t* __restrict__ out, int64_t kstride, uint32_t& m) {
+  (tree_tap<T>(cc, cs, ox, oy, oz, out, kstride, m), ...);
+}
+
+__global__ __launch_bounds__(256) void k_kmap_tree(const int32_t* __restrict__ pkmap, int64_t pstride,
+                                                   const uint8_t* __restrict__ pcode,
+                                                   const int32_t* __restrict__ pcstart, int64_t np,
+                                                   int32_t* __restrict__ kmap, int64_t kstride) {
+  __shared__ uint16_t who[8 * kTreeParents];  // (parent in block << 3) | slot, per child row
+  const int64_t p0 = (int64_t)blockIdx.x * kTreeParents;
+  const int64_t pe = min(p0 + (int64_t)kTreeParents, np);
+  const int64_t p = p0 + threadIdx.x;
+  const int32_t c0 = gp(pcstart)[p0];
+  // children past the table (a stream whose codes claim more children than
+  // its header) are not written; the expansion reports that stream
+  const int64_t c1 = min((int64_t)gp(pcstart)[pe], kstride);
+  if (p < pe) {
+    uint32_t code = gp(pcode)[p];
+    int32_t r = gp(pcstart)[p] - c0;
+    while (code) {
+      if (r >= 0 && r < 8 * kTreeParents) who[r] = (uint16_t)((threadIdx.x << 3) | (__ffs(code) - 1));
+      r++;
+      code &= code - 1;
+    }
+  }
+  __syncthreads();
+  const int nk = (int)min(c1 - (int64_t)c0, (int64_t)8 * kTreeParents);
+  for (int k = threadIdx.x; k < nk; k += 256) {
+    const uint32_t w = who[k];
+    if ((int64_t)(w >> 3) >= pe - p0) continue;  // only with codes and first-child rows that disagree
+    const int64_t pp = p0 + (w >> 3);
+    const int ox = (w >> 2) & 1, oy = (w >> 1) & 1, oz = w & 1;
+    const int tb = ox * 9 + oy * 3 + oz;
+    int32_t q[8];
+#pragma unroll
+    for (int a = 0; a < 8; a++) q[a] = gp(pkmap)[(int64_t)(tb + (a >> 2) * 9 + ((a >> 1) & 1) * 3 + (a & 1)) * pstride + pp];
+    uint32_t cc[8];
+    int32_t cs[8];
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+      const int32_t qi = q[a] >= 0 ? q[a] : 0;  // absent cells read row 0 and are masked
+      const uint32_t c = gp(pcode)[qi];
+      cs[a] = gp(pcstart)[qi];
+      cc[a] = q[a] >= 0 ? c : 0u;
+    }
+    uint32_t m = 0;
+    GAS int32_t* out = gp(kmap) + c0 + k;
+    tree_taps(std::make_integer_sequence<int, 27>{}, cc, cs, ox, oy, oz, out, kstride, m);
+    out[27 * kstride] = (int32_t)m;
+  }
+}
+
+hipError_t launch_kmap_tree(const int32_t* pkmap, int64_t np, const uint8_t* pcode, const int32_t* pcstart,
+                            int32_t* kmap, int64_t n, hipStream_t s) {
+  if (n <= 0 || np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kmap_tree, dim3((unsigned)((np + kTreeParents - 1) / kTreeParents)), dim3(256), 0, s, pkmap,
+                     np, pcode, pcstart, np, kmap, n);
   return hipGetLastError();
 }
 

@@ -200,6 +200,16 @@ bool requant_fits24(int32_t m_pos, int32_t m_neg, int32_t a_lo, int32_t a_hi, in
   return pos && neg;
 }
 
+// a m + rnd + z 2^r inside int32 for a in [a_lo, a_hi] (identity layers,
+// m = m_pos = m_neg, 24-bit operands already checked)
+bool requant_fold_fits(const LayerDev& F) {
+  if (F.r < 0 || F.r > 30) return false;
+  const int64_t rndz = F.rnd + (int64_t)F.z_out * (1ll << F.r);
+  const int64_t lo = (int64_t)F.a_lo * F.m_pos + rndz, hi = (int64_t)F.a_hi * F.m_pos + rndz;
+  const int64_t top = 1ll << 31;
+  return rndz >= -top && rndz < top && lo >= -top && lo < top && hi >= -top && hi < top;
+}
+
 RqBounds requant_bounds(int32_t m_pos, int32_t m_neg, int r, int z) {
   RqBounds B;
   B.m_pos = r == 0 ? std::min<int32_t>(m_pos, 256) : m_pos;
@@ -372,6 +382,9 @@ struct lpcc_ctx {
   // base depth B of the streams this context encodes: depths below B are
   // coded from the counts of their own codes, the model runs from depth B
   int base = 0;
+  // neighbour tables: 0 = from the parent depth's table (a hash only at the
+  // first convolved depth), 1 = a coordinate hash at every convolved depth
+  int kmap_mode = 0;
   // workspace cap in bytes (0 = none) and the most held so far
   size_t budget = 0, peak = 0;
   // fixed mode (the entry point that allocates nothing): the arenas are
@@ -730,6 +743,9 @@ struct ModelBufs {
   int8_t* F[kMaxD + 1] = {};         // features that predict depth d (shallow d and k0)
   int32_t* kmap[kMaxD + 1] = {};     // [28][tot[j]] for the depths that convolve: 27 taps, masks
   uint64_t* hkeys[kMaxD + 1] = {};   // hash tables: 16-byte slots {u64 key, i32 row}
+  bool tree[kMaxD + 1] = {};          // neighbour table derived from depth j-1's (no hash table)
+  bool hash_all = false;              // set before carving: hash every convolved depth
+  int64_t tree_min = 0;               // set before carving: smaller depths hash
   uint64_t hmask[kMaxD + 1] = {};
   uint64_t* hash_lo = nullptr;        // first word of the contiguous tables
   size_t hash_words = 0;              // their extent in u64 words
@@ -742,6 +758,8 @@ struct ModelBufs {
   int8_t* ds[kMaxD + 1] = {};
   int8_t* Z[kMaxD + 1][kMaxD + 1] = {};  // [d][j] upsampled features at depth j (j = k0 is H)
 };
+
+constexpr int64_t kTreeMinEncode = 32768;
 
 bool need_kmap(const lpcc_model* m, int j) { return j <= m->k0 - 1 || (j == m->k0 && m->n_deep > 0); }
 
@@ -766,6 +784,9 @@ void carve_model(Arena& A, const lpcc_model* m, const Frames& fr, int last, cons
   B.hash_words = 0;
   for (int j = 0; j <= kmax; j++) {
     if (!hashed(j)) continue;  // only depths that feed a wanted depth
+    // a depth whose parent depth has a neighbour table derives its own from it
+    B.tree[j] = !B.hash_all && j > 0 && hashed(j - 1) && fr.tot[j] >= B.tree_min;
+    if (B.tree[j]) continue;
     uint64_t sz = 1;
     while (sz < (uint64_t)std::max<int64_t>(2 * fr.tot[j], 2)) sz <<= 1;
     B.hmask[j] = sz - 1;
@@ -806,15 +827,27 @@ void plan_hash_clear(Batch& b, ModelBufs& B, hipStream_t st) {
   b.launch("hash", 0, [=](const uint8_t*) { return launch_fill_u64(p, words, ~0ull, st); });
 }
 
+// Neighbour table of depth j from depth j-1's table, codes and first-child
+// rows (the table of depth j-1 is complete)
+void plan_kmap_tree(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, int j, hipStream_t st) {
+  const int64_t n = fr.tot[j], np = fr.tot[j - 1];
+  const int32_t* pk = B.kmap[j - 1];
+  const uint8_t* pc = lv.code[j - 1];
+  const int32_t* ps = lv.cstart[j - 1];
+  int32_t* km = B.kmap[j];
+  b.launch("hash", n, [=](const uint8_t*) { return launch_kmap_tree(pk, np, pc, ps, km, n, st); });
+}
+
 // Hash + neighbour tables of all depths in `js` whose keys are known: one
-// insertion launch and one neighbour launch for all of them (tables cleared)
+// insertion launch and one neighbour launch for the depths that hash (tables
+// cleared), then the derived tables of the others
 void plan_kmaps(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, const std::vector<int>& js,
                 hipStream_t st) {
   std::vector<HashJob> jobs;
   int ib = 0, kb = 0;
   int64_t units = 0;
   for (int j : js) {
-    if (!B.kmap[j] || fr.tot[j] == 0) continue;
+    if (!B.kmap[j] || fr.tot[j] == 0 || B.tree[j]) continue;
     HashJob h;
     memset(&h, 0, sizeof(h));
     h.keys = lv.key[j];
@@ -831,12 +864,19 @@ void plan_kmaps(Batch& b, const Levels& lv, const Frames& fr, ModelBufs& B, cons
     units += h.n;
     jobs.push_back(h);
   }
-  if (jobs.empty()) return;
-  const size_t jo = b.add(jobs);
-  const int nj = (int)jobs.size();
-  b.launch("hash", units, [=](const uint8_t* base) {
-    return launch_hash_multi((const HashJob*)(base + jo), nj, ib, kb, st);
-  });
+  if (!jobs.empty()) {
+    const size_t jo = b.add(jobs);
+    const int nj = (int)jobs.size();
+    b.launch("hash", units, [=](const uint8_t* base) {
+      return launch_hash_multi((const HashJob*)(base + jo), nj, ib, kb, st);
+    });
+  }
+  // then the derived tables, coarse to fine (each reads the one before)
+  std::vector<int> tj;
+  for (int j : js)
+    if (B.kmap[j] && B.tree[j]) tj.push_back(j);
+  std::sort(tj.begin(), tj.end());
+  for (int j : tj) plan_kmap_tree(b, lv, fr, B, j, st);
 }
 
 // Neighbour table of depth j whose hash table is already filled
@@ -1186,12 +1226,13 @@ void plan_predict(Batch& b, const lpcc_model* m, const std::vector<PredSeg>& seg
   if (nt == 0) return;
   PredArg one;
   memset(&one, 0, sizeof(one));
-  // the logit layers' requantisation: a 24-bit multiply-add for identity
-  // layers (2), else the general form (0)
+  // the logit layers' requantisation: a 24-bit multiply-add with the zero
+  // point in the rounding term for identity layers where that stays inside
+  // int32 (2), else the general form (0)
   bool fits = true;
   for (auto& s : segs) {
     const LayerDev& F = hlayer(m, s.fc2);
-    fits = fits && F.rq24 && F.m_pos == F.m_neg;
+    fits = fits && F.rq24 && F.m_pos == F.m_neg && requant_fold_fits(F);
   }
   one.rq24 = fits ? 2 : 0;
   size_t so = 0, to = 0;
@@ -1554,6 +1595,10 @@ void lpcc::encode_workspace_bound(const lpcc_model* m, int nf, const int64_t* n,
   std::vector<bool> wanted(D, true);
   for (int d = 0; d < nb && d < D; d++) wanted[d] = false;
   ModelBufs B;
+  // the bound counts a hash table at every convolved depth: an encode
+  // hashes the depths below kTreeMinEncode nodes, and the bound's node
+  // counts are upper bounds
+  B.hash_all = true;
   EncBufs eb;
   Arena a1;
   carve_encode(a1, m, fr, D - 1, wanted, nb, -1, false, EL, B, eb);
@@ -1618,6 +1663,10 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   const std::vector<size_t>& stage_off = EL.stage_off;
   const bool cdf_dev = probe && is_device_ptr(cdf_out);
   ModelBufs B;
+  B.hash_all = c->kmap_mode == 1;
+  // the encoder hashes every depth it can in two launches; a derived table
+  // costs a launch of its own, which pays from about this many nodes
+  B.tree_min = kTreeMinEncode;
   EncBufs eb;
   Arena meas;
   carve_encode(meas, m, fr, last, wanted, nb, probe ? probe_level : -1, cdf_dev, EL, B, eb);
@@ -2277,6 +2326,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
   }
   Levels lv;
   ModelBufs B;
+  B.hash_all = c->kmap_mode == 1;
   size_t maxch = 0;
   for (int d = 0; d < D; d++) maxch = std::max(maxch, dchunks[d].size());
   std::vector<bool> xdev(nf, false);
@@ -2444,7 +2494,7 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       int32_t* cst = lv.cstart[d];
       uint32_t* e1 = err + 1;
       uint32_t* cs = csum;
-      const bool hashed = d + 1 <= k0 && d + 1 >= nb && B.kmap[d + 1];
+      const bool hashed = d + 1 <= k0 && d + 1 >= nb && B.kmap[d + 1] && !B.tree[d + 1];
       uint64_t* tk = hashed ? B.hkeys[d + 1] : nullptr;
       const uint64_t hm = hashed ? B.hmask[d + 1] : 0;
       b.launch("expand", np, [=](const uint8_t* base) {
@@ -2453,8 +2503,11 @@ int decode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const uint8_t* const* 
       });
     }
     if (t <= k0 && t >= nb && B.kmap[t]) {
-      join(st, sd);  // the expansion filled the hash table of depth t
-      plan_kmap_only(b, lv, fr, B, t, sd);
+      join(st, sd);  // the expansion: hash table or first-child rows of depth d
+      if (B.tree[t])
+        plan_kmap_tree(b, lv, fr, B, t, sd);
+      else
+        plan_kmap_only(b, lv, fr, B, t, sd);
       if (t == k0) kmap_k0 = mark(sd);
     }
     if (t <= k0 && modelled) {
@@ -2825,6 +2878,12 @@ int lpcc_ctx_graph_stats(lpcc_ctx* c, int64_t* instantiated, int64_t* updated) {
 int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb) {
   if (!c || !(rb == 0 || rb == 1 || rb == 2 || rb == 4 || rb == 11 || rb == 12 || rb == 14)) return LPCC_E_INVAL;
   c->tiling = rb;
+  return LPCC_OK;
+}
+
+int lpcc_ctx_set_kmap_mode(lpcc_ctx* c, int mode) {
+  if (!c || (mode != 0 && mode != 1)) return LPCC_E_INVAL;
+  c->kmap_mode = mode;
   return LPCC_OK;
 }
 

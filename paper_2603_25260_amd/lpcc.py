@@ -84,6 +84,7 @@ def lib():
         L.lpcc_requant_bounds.argtypes = [i32, i32, i32, i32, vp]
         L.lpcc_ctx_set_tiling.argtypes = [vp, i32]
         L.lpcc_ctx_set_base_depth.argtypes = [vp, i32]
+        L.lpcc_ctx_set_kmap_mode.argtypes = [vp, i32]
         L.lpcc_ctx_set_graphs.argtypes = [vp, i32]
         L.lpcc_ctx_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.lpcc_ctx_tuning.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
@@ -225,6 +226,11 @@ class Context:
     # -- base geometry: depths below B coded from their own code counts
     def set_base_depth(self, base: int):
         _check(lib().lpcc_ctx_set_base_depth(self.handle, int(base)), self.handle)
+
+    # -- neighbour tables: 0 derives each depth's from its parent depth's (a
+    # hash at the first convolved depth only), 1 hashes every convolved depth
+    def set_kmap_mode(self, mode: int):
+        _check(lib().lpcc_ctx_set_kmap_mode(self.handle, int(mode)), self.handle)
 
     # -- graph mode: launch batches captured into HIP graphs and replayed
     def set_graphs(self, on: bool):
