@@ -192,19 +192,19 @@ FAMILY_BOUND = {"conv": "hbm", "down": "hbm", "skip": "hbm", "emb": "hbm", "up":
 # what the same counters read for a 256 MiB device copy (fetch x2, write x1).
 # They hold for the library sources whose digest is TRAFFIC_SOURCES; any other
 # source tree reports traffic null.
-TRAFFIC_SOURCES = "4ac1d3bcce96c877"
+TRAFFIC_SOURCES = "39099e89d2b50a08"
 FAMILY_TRAFFIC = {
-    "conv": (5803468254, 2248017152),
-    "down": (1584537167, 2081497216),
-    "skip": (1708499899, 853240960),
-    "emb": (3487286, 170779264),
-    "up": (4577782316, 4400884372),
-    "predict": (1692934449, 6584371178),
-    "rc_encode": (65128064, 16356444),
-    "rc_decode": (8107890476, 25174298),
-    "hash": (14530627786, 2447233452),
-    "expand": (138530343, 566879436),
-    "pack": (32347860, 15933280),
+    "conv": (5830858466, 2248017152),
+    "down": (1584240325, 2081497216),
+    "skip": (1708504433, 853240960),
+    "emb": (3488015, 170779264),
+    "up": (4559830124, 4402424111),
+    "predict": (1692950543, 6584371188),
+    "rc_encode": (65128182, 16356416),
+    "rc_decode": (8107403717, 25176793),
+    "hash": (505214528, 806702527),
+    "expand": (136333824, 170685344),
+    "pack": (32347845, 15933280),
 }
 
 
