@@ -1041,9 +1041,11 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
   if (gb < ge) fetch(gb, nx);
   for (int gi = gb; gi < ge; gi++) {
     const Op x = nx;
-    if (gi + 1 < ge) fetch(gi + 1, nx);
     const int o = x.o;
-    if (o != cur) {  // weights and biases of slot o (wave-uniform)
+    // weights and biases of slot o (wave-uniform), requested before the next
+    // group's operands: the memory counter drains in order, so the waits for
+    // these loads then leave the prefetch in flight
+    if (o != cur) {
       cur = o;
 #pragma unroll
       for (int s = 0; s < KS; s++)
@@ -1052,6 +1054,7 @@ __global__ __launch_bounds__(256) void k_up_cx(const GemmSeg* __restrict__ segs,
 #pragma unroll
       for (int nb = 0; nb < NBS; nb++) bb[nb] = Bp[(o * C + 16 * nb + 4 * g) / 4];
     }
+    if (gi + 1 < ge) fetch(gi + 1, nx);
     const bool ev = x.ev;
     const int p = x.p;
     const uint32_t pc = x.pc;
@@ -1206,9 +1209,11 @@ __global__ __launch_bounds__(256) void k_down_cx(const GemmSeg* __restrict__ seg
   if (gb < ge) fetch(gb, nx);
   for (int gi = gb; gi < ge; gi++) {
     const Op x = nx;
-    if (gi + 1 < ge) fetch(gi + 1, nx);
     const int o = x.o;
-    if (o != cur) {  // the slot's weights: rows k = o C + c of the packed layout
+    // the slot's weights (rows k = o C + c of the packed layout), requested
+    // before the next group's operands so that waiting for them leaves the
+    // prefetch in flight (the memory counter drains in order)
+    if (o != cur) {
       cur = o;
 #pragma unroll
       for (int s = 0; s < KS; s++) {
@@ -1222,6 +1227,7 @@ __global__ __launch_bounds__(256) void k_down_cx(const GemmSeg* __restrict__ seg
         }
       }
     }
+    if (gi + 1 < ge) fetch(gi + 1, nx);
     const int t = x.t;
     const bool cv = x.cv;
     v4i acc[NB];
