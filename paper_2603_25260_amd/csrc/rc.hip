@@ -7,6 +7,8 @@
 
 namespace lpcc {
 
+constexpr int kRcEncodeLanes = 2048;
+
 // ---------------------------------------------------------------------------
 // Encoder: one wave per chunk.  The coder state is wave-uniform (scalar
 // registers); the node values start | freq << 16 are loaded 64 at a time
@@ -29,7 +31,8 @@ struct RcEnc {
   uint32_t range;
   uint32_t cache;
   uint32_t pending;
-  __device__ __forceinline__ void shift_low(WaveSink& o) {
+  template <class Sink>
+  __device__ __forceinline__ void shift_low(Sink& o) {
     // low < 2^33: bits 24..32 hold the carry and the top byte; a byte leaves
     // unless they read 0x0FF (one 32-bit scalar compare)
     const uint32_t top = (uint32_t)(low >> 24);
@@ -45,7 +48,8 @@ struct RcEnc {
   }
   // freq >= 1 always holds for the model's tables; a zero is clamped so that
   // the renormalisation loop always ends
-  __device__ __forceinline__ void encode(uint32_t sf, WaveSink& o) {
+  template <class Sink>
+  __device__ __forceinline__ void encode(uint32_t sf, Sink& o) {
     const uint32_t start = sf & 0xFFFFu, freq = (sf >> 16) ? (sf >> 16) : 1u;
     const uint32_t r = range >> 16;
     low += (uint64_t)r * start;
@@ -78,10 +82,58 @@ __global__ __launch_bounds__(64) void k_rc_encode(const Chunk* __restrict__ chun
   if (lane == 0) lens[blockIdx.x] = o.pos;
 }
 
+// Encoder for many chunks: one lane per chunk, the coder state in vector
+// registers.  The wave-per-chunk form above keeps its state in scalar
+// registers, and a compute unit has one scalar unit for all its waves, so
+// with thousands of chunks in flight the scalar unit, not the chunks' serial
+// chains, sets the time; here 64 chunks advance side by side on the vector
+// unit.  Each lane stores its own chunk's bytes.  Same bytes as above.
+struct LaneSink {
+  GAS uint8_t* out;
+  uint32_t pos;
+  __device__ __forceinline__ void put(uint32_t b) {
+    out[pos] = (uint8_t)b;
+    pos++;
+  }
+};
+
+__global__ __launch_bounds__(64) void k_rc_encode_lanes(const Chunk* __restrict__ chunks, int nch,
+                                                        const uint32_t* __restrict__ sf,
+                                                        uint8_t* __restrict__ scratch, uint32_t* __restrict__ lens) {
+  const int c = (int)blockIdx.x * 64 + (int)threadIdx.x;
+  if (c >= nch) return;
+  const Chunk ch = chunks[c];
+  LaneSink o{(GAS uint8_t*)(scratch + ch.scratch), 0u};
+  RcEnc e{0ull, 0xFFFFFFFFu, 0u, 1u};
+  const GAS uint32_t* p = gp(sf) + ch.node0;
+  const int n = ch.count;
+  // symbols in batches of 16, the next batch in flight while one is coded
+  constexpr int kB = 16;
+  uint32_t cur[kB], nxt[kB];
+#pragma unroll
+  for (int j = 0; j < kB; j++) cur[j] = j < n ? p[j] : 0u;
+  for (int base = 0; base < n; base += kB) {
+#pragma unroll
+    for (int j = 0; j < kB; j++) nxt[j] = base + kB + j < n ? p[base + kB + j] : 0u;
+#pragma unroll
+    for (int j = 0; j < kB; j++)
+      if (base + j < n) e.encode(cur[j], o);
+#pragma unroll
+    for (int j = 0; j < kB; j++) cur[j] = nxt[j];
+  }
+  for (int k = 0; k < 5; k++) e.shift_low(o);
+  lens[c] = o.pos;
+}
+
 hipError_t launch_rc_encode(const Chunk* chunks, int nchunks, const uint32_t* sf, uint8_t* scratch, uint32_t* lens,
                             hipStream_t s) {
   if (nchunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rc_encode, dim3(nchunks), dim3(64), 0, s, chunks, nchunks, sf, scratch, lens);
+  // lane per chunk once there are enough chunks to fill many waves
+  if (nchunks >= kRcEncodeLanes)
+    hipLaunchKernelGGL(k_rc_encode_lanes, dim3((nchunks + 63) / 64), dim3(64), 0, s, chunks, nchunks, sf, scratch,
+                       lens);
+  else
+    hipLaunchKernelGGL(k_rc_encode, dim3(nchunks), dim3(64), 0, s, chunks, nchunks, sf, scratch, lens);
   return hipGetLastError();
 }
 
