@@ -192,7 +192,7 @@ FAMILY_BOUND = {"conv": "hbm", "down": "hbm", "skip": "hbm", "emb": "hbm", "up":
 # what the same counters read for a 256 MiB device copy (fetch x2, write x1).
 # They hold for the library sources whose digest is TRAFFIC_SOURCES; any other
 # source tree reports traffic null.
-TRAFFIC_SOURCES = "68b17e162596795c"
+TRAFFIC_SOURCES = "56eb3d69864ad588"
 FAMILY_TRAFFIC = {
     "conv": (5826960970, 2248017152),
     "down": (1584567119, 2081497216),
@@ -208,13 +208,28 @@ FAMILY_TRAFFIC = {
 }
 
 
+def code_lines(text):
+    """The lines of a C++ source without // comments, trailing blanks and
+    empty lines (a comment edit leaves the digest unchanged)."""
+    out = []
+    for line in text.splitlines():
+        i = line.find("//")
+        if i >= 0:
+            line = line[:i]
+        line = line.rstrip()
+        if line:
+            out.append(line)
+    return out
+
+
 def library_sources_digest():
-    """sha256[:16] of the library's sources, concatenated in name order."""
+    """sha256[:16] of the library's sources in name order, by code_lines."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2603_25260_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        with open(os.path.join(d, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(d, name), encoding="utf-8") as f:
+            h.update("\n".join(code_lines(f.read())).encode())
+            h.update(b"\n")
     return h.hexdigest()[:16]
 
 

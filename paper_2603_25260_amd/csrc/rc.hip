@@ -1,8 +1,9 @@
 // Range coder on gfx950: G. N. N. Martin's byte-oriented range coder (1979)
 // with a cache byte and carry propagation; 32-bit range, 16-bit totals.  The
 // stream of every (frame, depth) is cut into chunks of 2^c nodes that are
-// coded independently: encoding runs one wave per chunk (all depths at once),
-// decoding one wave per chunk with a wave-wide symbol search over the CDF.
+// coded independently: encoding runs one wave per chunk, or one lane per
+// chunk when there are many (all depths at once), decoding one wave per chunk
+// with a wave-wide symbol search over the CDF.
 #include "lpcc_internal.h"
 
 namespace lpcc {

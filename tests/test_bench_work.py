@@ -38,3 +38,14 @@ def test_frame_work_closed_form_single_voxel():
     assert w["conv"]["macs"] == k0 * 2 * C * C + nd * 3 * C * C
     assert w["predict"]["macs"] == D * (C * C + 255 * C)
     assert w["up"]["macs"] == (k0 + sum(d - k0 for d in range(k0 + 1, D))) * (C + 8) * C
+
+
+def test_source_digest_ignores_comments_only():
+    """The profiled-traffic table is tied to the library's code: a comment or
+    blank-line edit keeps the digest's input, any code edit changes it."""
+    a = "int f(int x) {  // doubles\n  return 2 * x;\n}\n"
+    b = "// a new note\nint f(int x) {\n\n  return 2 * x;   // still doubles\n}\n"
+    c = "int f(int x) {\n  return 3 * x;\n}\n"
+    assert bench.code_lines(a) == bench.code_lines(b)
+    assert bench.code_lines(a) != bench.code_lines(c)
+    assert len(bench.library_sources_digest()) == 16
