@@ -267,8 +267,8 @@ FAMILIES = ("conv", "down", "skip", "emb", "up", "predict", "rc_encode", "rc_dec
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(frames shard across GPUs with no exchange; see the design notes)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 (frames are independent: "
+                                   "several GPUs would each code their own frames, with no exchange)"}))
         sys.exit(2)
     import torch
 

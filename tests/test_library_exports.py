@@ -26,7 +26,7 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("liblpcc.so is not built (run __graft_entry__.build())")
+        pytest.fail("liblpcc.so is not built (python paper_2603_25260_amd/build.py)")
     return ctypes.CDLL(LIB)
 
 

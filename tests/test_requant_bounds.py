@@ -20,7 +20,7 @@ I32_MIN, I32_MAX = -(1 << 31), (1 << 31) - 1
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        pytest.fail("liblpcc.so is not built (run __graft_entry__.build())")
+        pytest.fail("liblpcc.so is not built (python paper_2603_25260_amd/build.py)")
     L = ctypes.CDLL(LIB)
     L.lpcc_requant_bounds.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
     return L
