@@ -358,11 +358,13 @@ int lpcc_ctx_set_base_depth(lpcc_ctx* c, int base);
  * hash).  Both modes give the same tables, entry for entry, hence the same
  * streams and decodes.
  *   mode 0 (default): a coordinate hash (open addressing, linear probing,
- *     2^k >= 2N slots of {u64 key, i32 row}) only at the first convolved
- *     depth; every later depth derives its table from its parent depth's
- *     table, occupancy codes and first-child rows (the neighbour at offset
- *     delta of the child in slot o of parent p is child slot (o + delta)
- *     mod 2 of the parent-level cell p + floor((o + delta) / 2), per axis).
+ *     2^k >= 2N slots of {u64 key, i32 row}) at the first convolved depth
+ *     (an encode also hashes its depths below 32768 nodes, in the two
+ *     launches it shares across depths); every other depth derives its
+ *     table from its parent depth's table, occupancy codes and first-child
+ *     rows (the neighbour at offset delta of the child in slot o of parent p
+ *     is child slot (o + delta) mod 2 of the parent-level cell
+ *     p + floor((o + delta) / 2), per axis).
  *   mode 1: a coordinate hash and 27 probes per node at every convolved
  *     depth.
  * Applies to the calls made on this context after it returns.  LPCC_E_INVAL
