@@ -69,6 +69,11 @@ def parse():
                     help="skip the schedule, base-depth, chunk-size and graph-mode lines")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration under a profiler)")
+    ap.add_argument("--tuning-out", default="",
+                    help="write the headline context's autotuner table (JSON) after the warm-up steps")
+    ap.add_argument("--tuning-in", default="",
+                    help="start the headline context from an autotuner table written by --tuning-out "
+                         "(separate profiler passes then launch the same kernels)")
     return ap.parse_args()
 
 
@@ -192,19 +197,19 @@ FAMILY_BOUND = {"conv": "hbm", "down": "hbm", "skip": "hbm", "emb": "hbm", "up":
 # what the same counters read for a 256 MiB device copy (fetch x2, write x1).
 # They hold for the library sources whose digest is TRAFFIC_SOURCES; any other
 # source tree reports traffic null.
-TRAFFIC_SOURCES = "56eb3d69864ad588"
+TRAFFIC_SOURCES = "42a9a4b386e5ab26"
 FAMILY_TRAFFIC = {
-    "conv": (5826960970, 2248017152),
-    "down": (1584567119, 2081497216),
-    "skip": (1708502223, 853240960),
-    "emb": (3487946, 170779264),
-    "up": (4651833787, 4393200364),
-    "predict": (1692948160, 6584371296),
-    "rc_encode": (58843840, 19096089),
-    "rc_decode": (8107935345, 25172891),
-    "hash": (505135513, 806672357),
+    "conv": (5787705895, 2248017152),
+    "down": (1583890442, 2081497216),
+    "skip": (1708495714, 853240960),
+    "emb": (3487665, 170779264),
+    "up": (4592781932, 4374711995),
+    "predict": (1692922260, 6723545627),
+    "rc_encode": (58745620, 19069899),
+    "rc_decode": (8108631286, 25131190),
+    "hash": (505229681, 806691531),
     "expand": (136333824, 170685344),
-    "pack": (32347899, 15933287),
+    "pack": (32347958, 15933339),
 }
 
 
@@ -285,6 +290,9 @@ def main():
     ctx = lpcc.Context(0, stream.cuda_stream)
     if args.tiling:
         ctx.set_tiling(args.tiling)
+    if args.tuning_in:
+        with open(args.tuning_in) as fh:
+            ctx.set_tuning(json.load(fh))
     frames = [synth.make_scan(cfg.scan, s) for s in cfg.seeds]
     nf = len(frames)
     dx = [torch.from_numpy(f).to(dev) for f in frames]
@@ -319,6 +327,9 @@ def main():
     for _ in range(max(args.warmup, 1)):
         ln, nout, _, _ = batch_step(wo, wd)
     warm_exact = check(wo, wd, ln, nout)
+    if args.tuning_out:
+        with open(args.tuning_out, "w") as fh:
+            json.dump(ctx.tuning(), fh)
     stream_bytes = sum(ln)
     bufs = [new_outs() for _ in range(args.steps)]
     torch.cuda.synchronize()

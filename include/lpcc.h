@@ -315,8 +315,18 @@ int lpcc_timing_read(lpcc_ctx* c, int64_t* launches, double* total_ms, int64_t* 
  * 2, 4) and 10 + rb for the gather-GEMMs, 101/102 (compacted, 64/128 parents
  * per block) and 110 + rb for the child convolution, 201/202 (compacted,
  * 128/512 parents per block) and 210 + rb for the upsampling.
+ *
+ * lpcc_ctx_set_tuning imports such a table (host, 6 * n ints, the format
+ * lpcc_ctx_tuning writes): each row's class then uses the row's variant
+ * without timing candidates, so runs in separate processes (a profiler's
+ * counter passes, say) launch the same kernels.  Rows with variant 0 are
+ * skipped.  A fixed tiling (lpcc_ctx_set_tiling) still takes precedence.
+ * Returns LPCC_E_INVAL, with nothing applied, for a kind other than 0 or 1,
+ * widths <= 0, log2 rows outside [0, 62] or a variant code the kind does not
+ * have.
  */
 int lpcc_ctx_set_tiling(lpcc_ctx* c, int rb);
+int lpcc_ctx_set_tuning(lpcc_ctx* c, const int32_t* rows, int n);
 
 /*
  * Graph mode (off by default; launch mechanics only, the computation is that

@@ -1643,9 +1643,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const uint32_t hi = (r == 15 && k == 7) ? 0u : off + ex[2 * k + 1];
             o2[k] = (lo & 0xFFFFu) | (hi << 16);
           }
+          // streaming stores: a large depth's rows (512 B per node) are read
+          // once, by the range decoder, and exceed the caches; marked
+          // non-temporal they leave L2 to the next kernels' working set
           GAS v4i* dst = (GAS v4i*)(S.cdf16 + (int64_t)nrow * 256 + 16 * r);
-          dst[0] = v4i{(int)o2[0], (int)o2[1], (int)o2[2], (int)o2[3]};
-          dst[1] = v4i{(int)o2[4], (int)o2[5], (int)o2[6], (int)o2[7]};
+          __builtin_nontemporal_store(v4i{(int)o2[0], (int)o2[1], (int)o2[2], (int)o2[3]}, dst);
+          __builtin_nontemporal_store(v4i{(int)o2[4], (int)o2[5], (int)o2[6], (int)o2[7]}, dst + 1);
         } else {
           uint32_t o4[16];
 #pragma unroll

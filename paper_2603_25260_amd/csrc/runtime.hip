@@ -2909,6 +2909,25 @@ int lpcc_ctx_tuning(lpcc_ctx* c, int32_t* out, int cap, int* n) {
   return k > cap && out ? LPCC_E_CAPACITY : LPCC_OK;
 }
 
+int lpcc_ctx_set_tuning(lpcc_ctx* c, const int32_t* rows, int n) {
+  if (!c || n < 0 || (n > 0 && !rows)) return LPCC_E_INVAL;
+  // every row is checked before any is applied
+  for (int k = 0; k < n; k++) {
+    const int32_t* r = rows + 6 * k;
+    if (r[0] != 0 && r[0] != 1) return LPCC_E_INVAL;
+    if (r[2] <= 0 || r[3] <= 0 || r[4] < 0 || r[4] > 62) return LPCC_E_INVAL;
+    if (r[5] == 0) continue;
+    bool known = false;
+    for (const Variant& v : variants(r[0] == 1, r[1])) known = known || v.code == r[5];
+    if (!known) return LPCC_E_INVAL;
+  }
+  for (int k = 0; k < n; k++) {
+    const int32_t* r = rows + 6 * k;
+    if (r[5] != 0) c->tune[{r[0], r[1], r[2], r[3], r[4]}].best = r[5];
+  }
+  return LPCC_OK;
+}
+
 // Exponent table of the integer softmax as the library builds it (host only).
 int lpcc_softmax_table(int32_t* out) {
   if (!out) return LPCC_E_INVAL;

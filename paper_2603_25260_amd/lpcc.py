@@ -88,6 +88,7 @@ def lib():
         L.lpcc_ctx_set_graphs.argtypes = [vp, i32]
         L.lpcc_ctx_graph_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.lpcc_ctx_tuning.argtypes = [vp, vp, i32, ctypes.POINTER(i32)]
+        L.lpcc_ctx_set_tuning.argtypes = [vp, vp, i32]
         L.lpcc_server_create.argtypes = [i32, vp, i32, i32, i32, sz, ctypes.POINTER(vp)]
         L.lpcc_server_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
         L.lpcc_server_poll.argtypes = [vp, ctypes.POINTER(Done), i32, ctypes.POINTER(i32), i32]
@@ -254,6 +255,14 @@ class Context:
             out.append({"kind": "up" if v[0] else "gemm", "mode": v[1], "cin": v[2], "cout": v[3],
                         "log2_rows": v[4], "rb": v[5]})
         return out
+
+    def set_tuning(self, table):
+        """Import an autotuner table in the format `tuning` returns: each
+        class then uses its recorded variant without timing candidates."""
+        rows = [[1 if t["kind"] == "up" else 0, t["mode"], t["cin"], t["cout"], t["log2_rows"], t["rb"]]
+                for t in table]
+        buf = (ctypes.c_int32 * (6 * max(len(rows), 1)))(*[int(x) for r in rows for x in r])
+        _check(lib().lpcc_ctx_set_tuning(self.handle, buf, len(rows)), self.handle)
 
     # -- timing of one kernel family (HIP events on the context's stream)
     def timing_enable(self, family: str):

@@ -69,6 +69,52 @@ def test_autotuned_tiling_decides_and_matches(L):
     assert all(t["rb"] in valid for t in table), table
 
 
+def test_imported_tuning_table_is_used(L):
+    """A table imported into a fresh context decides its classes without
+    timing: the context reports the imported variants (here each class moved
+    to another valid variant), and the outputs are still the oracle's."""
+    C, D, n_deep = 32, 11, 4
+    blob = synth.make_weights(6, C, D, n_deep)
+    xyz = synth.random_cloud(20000, D, 78)
+    want = O.encode(blob, xyz, 8)
+    m = L.Model(blob, 0)
+    dx = torch.from_numpy(xyz).cuda()
+    ctx = L.Context(0)
+    print("tuning source context", flush=True)
+    assert L.encode_frame(ctx, m, dx, 8) == want
+    L.decode_frame(ctx, m, want)
+    table = ctx.tuning()
+    assert table and all(t["rb"] for t in table), table
+
+    def other(t):
+        if t["kind"] == "up":
+            return 201 if t["rb"] != 201 else 202
+        if t["rb"] > 100:
+            return 101 if t["rb"] != 101 else 102
+        return 1 if t["rb"] != 1 else 2
+
+    moved = [dict(t, rb=other(t)) for t in table]
+    ctx2 = L.Context(0)
+    ctx2.set_tuning(moved)
+    print("imported table", flush=True)
+    assert L.encode_frame(ctx2, m, dx, 8) == want
+    dec = L.decode_frame(ctx2, m, want)
+    assert len(dec) == len(np.unique(xyz, axis=0))
+    key = lambda t: (t["kind"], t["mode"], t["cin"], t["cout"], t["log2_rows"])
+    assert {key(t): t["rb"] for t in ctx2.tuning()} == {key(t): t["rb"] for t in moved}
+
+
+def test_bad_tuning_rows_rejected(L):
+    ctx = L.Context(0)
+    good = {"kind": "gemm", "mode": 0, "cin": 32, "cout": 32, "log2_rows": 10, "rb": 2}
+    for bad in ({"rb": 3}, {"rb": 201}, {"cin": 0}, {"log2_rows": 63}, {"kind": "up", "rb": 2}):
+        with pytest.raises(Exception):
+            ctx.set_tuning([good, dict(good, **bad)])
+    assert ctx.tuning() == []  # nothing applied by a rejected import
+    ctx.set_tuning([good, dict(good, log2_rows=11, rb=0)])
+    assert ctx.tuning() == [good]
+
+
 def test_bad_tiling_rejected(L):
     ctx = L.Context(0)
     with pytest.raises(Exception):
