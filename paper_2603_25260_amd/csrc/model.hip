@@ -1394,8 +1394,11 @@ __device__ __forceinline__ uint32_t recip_k(uint32_t S) {  // floor(65281 * 2^16
 // (q' + 1) S <= E 65281; both sides stay below 2^32 (q' S <= E 65281 <
 // 2^31, plus S < 2^23), and (q' + 1) S is one 24-bit multiply-add.  The
 // masks only tell the instruction selector that 24-bit operands suffice.
+// E K reaches 2^31 once S <= 65281 (a confident head: one dominant logit),
+// and HIP's __umul24 returns int, so the product is made unsigned before the
+// shift (an arithmetic shift would sign-extend it).
 __device__ __forceinline__ uint32_t freq_of(uint32_t E, uint32_t S, uint32_t K) {
-  const uint32_t q = __umul24(E & 0xFFFFu, K & 0x1FFFFu) >> 16;
+  const uint32_t q = (uint32_t)__umul24(E & 0xFFFFu, K & 0x1FFFFu) >> 16;
   const uint32_t up = __umul24(q, S & 0xFFFFFFu) + S;
   return q + 1u + (up <= __umul24(E & 0xFFFFu, 65281u) ? 1u : 0u);
 }

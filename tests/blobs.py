@@ -27,3 +27,22 @@ def build_blob(C, D, n_deep, fill, xfp=True):
 def zeros(taps, cin, cout, r=20):
     """A layer computing 0 (zero weights and bias, unit gain)."""
     return {"W": np.zeros((taps, cin, cout)), "bias": np.zeros(cout), "m_pos": 1 << r, "m_neg": 1 << r, "r": r}
+
+
+def with_fc2_bias(blob, sym, bias):
+    """The same (unshared) blob with output ``sym`` of every predictor head
+    (FC2) given bias ``bias``: a confident head whose logit ``sym`` sits at
+    the top of the int8 range far above the others."""
+    b = bytearray(blob)
+    _, ver, _, _, _, nl, _ = struct.unpack_from("<6IQ", b, 0)
+    assert not ver & synth.SHARED
+    off = struct.calcsize("<6IQ")
+    rec = struct.calcsize("<6I2iI2i")
+    for _ in range(nl):
+        kind, _, _, taps, cin, cout = struct.unpack_from("<6I", b, off)
+        off += rec
+        if kind == synth.FC2:
+            struct.pack_into("<i", b, off + 4 * sym, bias)
+        off += 4 * cout + taps * cin * cout
+        off += -off % 4
+    return bytes(b)
