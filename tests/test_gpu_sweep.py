@@ -70,3 +70,41 @@ def test_sweep_case(L, case):
     assert L.encode_frame(ctx, m, dx, c["cl"]) == want
     u = np.unique(xyz, axis=0)
     assert np.array_equal(L.decode_frame(ctx, m, want), u[np.argsort(O.morton(u, c["D"]))])
+
+
+def _batch_cases():
+    rng = np.random.default_rng(2027)
+    out = []
+    for k in range(20):
+        C = int(rng.choice([16, 32, 64]))
+        D = int(rng.integers(5, 13))
+        nd = int(rng.integers(0, min(5, D - 1) + 1))
+        sizes = [int(rng.choice([0, 1, int(rng.integers(2, 5000))], p=[0.1, 0.1, 0.8]))
+                 for _ in range(int(rng.integers(1, 7)))]
+        out.append(dict(k=k, C=C, D=D, nd=nd, sizes=sizes, zp=bool(rng.random() < 0.4),
+                        cl=int(rng.integers(4, 15)), mode=int(rng.integers(0, 2)), seed=int(rng.integers(1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("case", _batch_cases(), ids=lambda c: f"batch{c['k']}")
+def test_sweep_batch(L, case):
+    """Batched encode and decode of frames of uneven sizes (empty and
+    one-point frames included): every stream is the oracle's per-frame
+    stream, every decode the frame's sorted unique points."""
+    c = case
+    print(c, flush=True)
+    blob = synth.make_weights(c["seed"] % 1000, c["C"], c["D"], c["nd"], zero_points=c["zp"])
+    frames = [synth.random_cloud(n, c["D"], c["seed"] + i) if n else np.zeros((0, 3), np.int32)
+              for i, n in enumerate(c["sizes"])]
+    want = [O.encode(blob, f, c["cl"]) for f in frames]
+    m = L.Model(blob, 0)
+    ctx = L.Context(0)
+    ctx.set_kmap_mode(c["mode"])
+    got, st = L.encode_batch(ctx, m, frames, c["cl"])
+    assert st == [0] * len(frames)
+    assert got == want
+    decs, st2 = L.decode_batch(ctx, m, got)
+    assert st2 == [0] * len(frames)
+    for f, x in zip(frames, decs):
+        u = np.unique(f, axis=0)
+        assert np.array_equal(np.asarray(x).reshape(-1, 3), u[np.argsort(O.morton(u, c["D"]))])
