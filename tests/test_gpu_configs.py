@@ -102,6 +102,19 @@ def test_128beam_batch_of_8_matches_oracle(L):
     _batch_round_trip(L, m, frames, cfg.scan.D, [str(s) for s in cfg.seeds], want)
 
 
+def test_128beam_batch_of_24_matches_oracle(L):
+    """The eight 128-beam frames three times over in one batched call (5.7 M
+    points): the finest depths' CDF rows then take about 2.9 GB, so the
+    device offsets of rows, tables and features go past 2^31 bytes; every
+    stream still equals the oracle's digest of its frame."""
+    cfg = synth.CONFIGS["cfg4"]
+    want = _need("cfg4", len(cfg.seeds))
+    m = L.Model(synth.make_weights(cfg.weight_seed, cfg.C, cfg.scan.D, cfg.n_deep), 0)
+    frames = [synth.make_scan(cfg.scan, s) for s in cfg.seeds] * 3
+    print("24-frame 128-beam batch", sum(len(f) for f in frames), "points", flush=True)
+    _batch_round_trip(L, m, frames, cfg.scan.D, [str(s) for s in cfg.seeds] * 3, want)
+
+
 def test_served_fleet_matches_oracle(L):
     """Every sensor's frame is encoded and its oracle-checked stream decoded
     through the server at once (48 jobs, 8 models, 14-18 levels, C = 32/64)."""
