@@ -519,8 +519,11 @@ int run_batch(lpcc_ctx* c, Batch& b, size_t* desc_off) {
   const size_t n = align_up(b.bytes.size(), 256);
   size_t need = *desc_off + n;
   if (need > c->cap[2]) {
-    // everything enqueued so far has to finish before the arena may move
+    // everything enqueued so far, on both streams, has to finish before the
+    // arena may move (an earlier batch of the call may have left work on the
+    // second stream that still reads its descriptors)
     HIPC(hipStreamSynchronize(c->stream));
+    if (c->side) HIPC(hipStreamSynchronize(c->side));
     *desc_off = 0;
     need = n;
     int st = reserve(c, 2, std::max<size_t>(need, 1 << 20));
@@ -1714,6 +1717,12 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
       return launch_base_sf(bl, (const int32_t*)(base + to), sf0, st);
     });
   }
+  // The GPU waits for nothing but these launches: submit them, so that it
+  // builds the tables while the model stages are planned and launched.
+  if (!c->graphs) {
+    s = run_batch(c, b, &desc_off);
+    if (s) return s;
+  }
   // Two streams: the re-densification of the deep depths needs only the
   // codes and runs beside the shallow chain; the predictor of the shallow
   // depths runs beside the deep ResBlock and upsampling.
@@ -1745,6 +1754,17 @@ int encode_impl(lpcc_ctx* c, const lpcc_model* m, int nf, const int32_t* const* 
   wait(sd, mark(st));  // the side stream starts after the fills
   plan_deep(b, m, lv, fr, B, dset, sd, 1);
   hipEvent_t g_done = mark(sd);
+  // the re-densification is long GPU work: submit it before planning the
+  // rest (the next batch's first side-stream launch waits for an event the
+  // main stream records after that batch's descriptors are copied)
+  if (!c->graphs) {
+    if (!ok_ev) {
+      c->err = "event creation failed";
+      return LPCC_E_DEVICE;
+    }
+    s = run_batch(c, b, &desc_off);
+    if (s) return s;
+  }
   for (int d = nb + 1; d <= std::min(last, k0); d++) plan_shallow(b, m, lv, fr, B, d, st);
   hipEvent_t f_done = mark(st);
   wait(st, g_done);
